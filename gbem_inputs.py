@@ -1,0 +1,197 @@
+"""Seeded synthetic layouts shared by the GPU path's tests/bench and the CPU oracle.
+
+This module only describes geometry: lists of axis-aligned boxes with a conductor
+id each, plus the meshing rule to apply.  It holds none of the method's
+arithmetic (no meshing, no integrals, no solve); both the library and the oracle
+mesh these boxes with their own code.
+
+A box is ``(lo, hi, cond)`` with ``lo``/``hi`` 3-tuples in micrometres.
+``cond`` is the conductor index 0..M-1, or -1 for a grounded boundary that is
+part of the boundary integral equation but not reported (the paper's Dirichlet
+outer boundary, section 2.1 / 3.1).
+
+Mesh rules (numbers are in the box's length unit):
+  ("uniform", h)                  every box edge of length L is split into
+                                  n = max(1, ceil(L/h - 1e-9)) equal cells
+  ("graded", h_min, growth, h_max) edge-graded split, cells grow geometrically
+                                  from both ends (see the design doc for the rule)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+EPS0 = 8.8541878128e-12      # vacuum permittivity, F/m (CODATA 2018)
+MICRON = 1e-6                 # metres per coordinate unit
+
+
+@dataclass
+class Layout:
+    name: str
+    boxes: list               # [(lo(3), hi(3), cond)]
+    n_conductors: int
+    rule: tuple
+    eps_r: float = 3.9
+    length_unit_m: float = MICRON
+    meta: dict = field(default_factory=dict)
+
+    def arrays(self):
+        lo = np.array([b[0] for b in self.boxes], dtype=np.float64).reshape(-1, 3)
+        hi = np.array([b[1] for b in self.boxes], dtype=np.float64).reshape(-1, 3)
+        cond = np.array([b[2] for b in self.boxes], dtype=np.int32)
+        return lo, hi, cond
+
+
+def two_plates(gap: float = 0.2, h: float = 0.1, eps_r: float = 3.9) -> Layout:
+    """Two 1 x 1 x 0.1 um boxes stacked face to face ``gap`` apart (480 panels at h=0.1)."""
+    t = 0.1
+    boxes = [((0.0, 0.0, 0.0), (1.0, 1.0, t), 0),
+             ((0.0, 0.0, t + gap), (1.0, 1.0, 2 * t + gap), 1)]
+    return Layout("two_plates", boxes, 2, ("uniform", h), eps_r)
+
+
+def crossing_bus(eps_r: float = 3.9, rule=("graded", 0.01, 1.2, 0.03)) -> Layout:
+    """Two metal layers x 5 wires (0.1 x 0.1 x 2 um, pitch 0.2 um, layer gap 0.1 um),
+    layer 1 along x, layer 2 along y; 10 conductors, about 21k panels with the
+    default edge-graded rule."""
+    boxes = []
+    for k in range(5):
+        boxes.append(((0.0, 0.5 + 0.2 * k, 0.0), (2.0, 0.6 + 0.2 * k, 0.1), k))
+    for k in range(5):
+        boxes.append(((0.5 + 0.2 * k, 0.0, 0.2), (0.6 + 0.2 * k, 2.0, 0.3), 5 + k))
+    return Layout("crossing_bus", boxes, 10, rule, eps_r)
+
+
+def three_layer_bus(n_per_layer: int = 16, length: float = 10.0, h: float = 0.0646,
+                    eps_r: float = 3.9) -> Layout:
+    """3 layers x 16 wires, 0.1 x 0.1 x 10 um, pitch 0.2 um, layers 0.1 um apart,
+    directions x, y, x, each layer centred on (5, 5); 59,904 panels at h=0.0646."""
+    boxes = []
+    c = 0
+    half = 0.5 * length
+    y0 = half - 0.2 * n_per_layer / 2 + 0.05
+    for layer in range(3):
+        z0 = 0.2 * layer
+        for i in range(n_per_layer):
+            a = y0 + 0.2 * i
+            if layer % 2 == 0:   # along x
+                boxes.append(((0.0, a, z0), (length, a + 0.1, z0 + 0.1), c))
+            else:                # along y
+                boxes.append(((a, 0.0, z0), (a + 0.1, length, z0 + 0.1), c))
+            c += 1
+    return Layout("three_layer_bus", boxes, c, ("uniform", h), eps_r)
+
+
+def crossing_bars_in_box(rule=("graded", 0.25, 1.5, 4.0), eps_r: float = 1.0) -> Layout:
+    """The paper's single-dielectric experiment (section 5): bars 4x1x1 um at
+    (-2,-0.5,1)-(2,0.5,2) and (-0.5,-2,3)-(0.5,2,4) inside a grounded box
+    (-20,-20,0)-(20,20,10).  The permittivity is not given there; 1 is used."""
+    boxes = [((-2.0, -0.5, 1.0), (2.0, 0.5, 2.0), 0),
+             ((-0.5, -2.0, 3.0), (0.5, 2.0, 4.0), 1),
+             ((-20.0, -20.0, 0.0), (20.0, 20.0, 10.0), -1)]
+    return Layout("crossing_bars_in_box", boxes, 2, rule, eps_r)
+
+
+def unit_cube(h: float = 0.25, eps_r: float = 1.0) -> Layout:
+    return Layout("unit_cube", [((0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 0)], 1, ("uniform", h), eps_r)
+
+
+def parallel_plates(w: float, d: float, t: float, h: float, eps_r: float = 1.0) -> Layout:
+    """Two w x w plates of thickness t with face-to-face gap d."""
+    boxes = [((0.0, 0.0, 0.0), (w, w, t), 0), ((0.0, 0.0, t + d), (w, w, 2 * t + d), 1)]
+    return Layout("parallel_plates", boxes, 2, ("uniform", h), eps_r)
+
+
+def _count_uniform(boxes, h):
+    n = 0
+    for lo, hi, _ in boxes:
+        c = [max(1, math.ceil((hi[k] - lo[k]) / h - 1e-9)) for k in range(3)]
+        n += 2 * (c[0] * c[1] + c[1] * c[2] + c[0] * c[2])
+    return n
+
+
+def random_manhattan(rng: np.random.Generator, n_target: float | None = None,
+                     n_min: int = 500, n_max: int = 20000, eps_r: float = 3.9) -> Layout:
+    """One random multi-layer Manhattan layout (serving stream job).
+
+    Layers L ~ U{1,2,3}, directions x, y, x, layer k at z in [0.2k, 0.2k+0.1];
+    wires W ~ U{2..16} dealt round-robin to layers; width ~ U[0.05,0.2],
+    thickness 0.1, length ~ U[1,10], start offset ~ U[0,1], in-layer spacing
+    ~ U[0.05,0.2].  Uniform panel size chosen so that the panel count is within
+    10 % of a log-uniform target in [n_min, n_max]."""
+    n_layers = int(rng.integers(1, 4))
+    n_wires = int(rng.integers(2, 17))
+    per_layer = [[] for _ in range(n_layers)]
+    for w in range(n_wires):
+        per_layer[w % n_layers].append(w)
+    boxes = []
+    for layer in range(n_layers):
+        z0 = 0.2 * layer
+        pos = 0.0
+        for idx, w in enumerate(per_layer[layer]):
+            width = float(rng.uniform(0.05, 0.2))
+            length = float(rng.uniform(1.0, 10.0))
+            start = float(rng.uniform(0.0, 1.0))
+            if idx > 0:
+                pos += float(rng.uniform(0.05, 0.2))
+            if layer % 2 == 0:
+                boxes.append(((start, pos, z0), (start + length, pos + width, z0 + 0.1), w))
+            else:
+                boxes.append(((pos, start, z0), (pos + width, start + length, z0 + 0.1), w))
+            pos += width
+    if n_target is None:
+        n_target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+    area = 0.0
+    for lo, hi, _ in boxes:
+        d = [hi[k] - lo[k] for k in range(3)]
+        area += 2 * (d[0] * d[1] + d[1] * d[2] + d[0] * d[2])
+    h = math.sqrt(area / n_target)
+    lo_h, hi_h = h * 1e-3, max(h, 20.0)
+    for _ in range(200):
+        n = _count_uniform(boxes, h)
+        if n_min <= n <= n_max and abs(n - n_target) <= 0.1 * n_target:
+            break
+        if n > n_target:
+            lo_h = h
+        else:
+            hi_h = h
+        h = 0.5 * (lo_h + hi_h)
+    return Layout("manhattan", boxes, n_wires, ("uniform", h), eps_r,
+                  meta={"n_target": n_target})
+
+
+def serving_stream(n_jobs: int = 256, seed: int = 20220322, rate_hz: float = 50.0,
+                   n_min: int = 500, n_max: int = 20000):
+    """Seeded job stream: list of (arrival_time_s, Layout).  Job k draws its layout
+    from SeedSequence(seed).spawn(n_jobs)[k]; arrivals are Poisson at rate_hz."""
+    ss = np.random.SeedSequence(seed)
+    children = ss.spawn(n_jobs + 1)
+    gaps = np.random.default_rng(children[-1]).exponential(1.0 / rate_hz, size=n_jobs)
+    t = np.cumsum(gaps) - gaps[0]
+    jobs = []
+    for k in range(n_jobs):
+        rng = np.random.default_rng(children[k])
+        jobs.append((float(t[k]), random_manhattan(rng, n_min=n_min, n_max=n_max)))
+    return jobs
+
+
+def random_small_layout(seed: int, n_boxes: int = 3, h: float = 0.25) -> Layout:
+    """A few random disjoint boxes, for property tests at small N."""
+    rng = np.random.default_rng(seed)
+    boxes = []
+    tries = 0
+    while len(boxes) < n_boxes and tries < 1000:
+        tries += 1
+        lo = rng.uniform(0.0, 3.0, size=3)
+        size = rng.uniform(0.3, 1.2, size=3)
+        hi = lo + size
+        ok = True
+        for blo, bhi, _ in boxes:
+            if all(lo[k] <= bhi[k] + 0.1 and blo[k] <= hi[k] + 0.1 for k in range(3)):
+                ok = False
+                break
+        if ok:
+            boxes.append((tuple(float(x) for x in lo), tuple(float(x) for x in hi), len(boxes)))
+    return Layout(f"random{seed}", boxes, len(boxes), ("uniform", h), 1.0)
