@@ -1,0 +1,189 @@
+/*
+ * gbem.h -- C ABI of the MI355X (gfx950) Galerkin boundary element
+ * capacitance extractor.
+ *
+ * Method: arXiv 2203.11733 ("GBEM"), single-dielectric case, section 3.
+ * The boundary of the conductors (and of an optional grounded enclosure) is
+ * split into axis-aligned rectangles I_j; with piecewise constant charge the
+ * Galerkin system is A X = B with
+ *     A_ij = 1/(4 pi |I_i||I_j|) Int_{I_i} Int_{I_j} 1/|x-y|     (section 3.1, eq. "matrix")
+ *     B_ik = 1 if I_i lies on conductor k, else 0               (eq. "lineareq1", one
+ *                                                                right-hand side per main net)
+ * A is symmetric positive definite (section 3.2, Theorem 1) and is factored by
+ * Cholesky; the Maxwell capacitance matrix is
+ *     C_kl = eps_r * eps0 * l * sum_{i on conductor k} X_il      (eq. "electriccharge";
+ *                                                                C_1n = Q_n, section 3.2)
+ * with eps0 = 8.8541878128e-12 F/m and l the length of one coordinate unit in
+ * metres.  Self and near pairs are integrated in closed form (section 3.4),
+ * far pairs by a p x p tensor Gauss-Legendre rule per panel.
+ *
+ * Conventions for every entry point:
+ *  - Return codes only: nothing aborts or throws across the ABI.  On failure
+ *    gbem_last_error() returns a message for the calling thread.
+ *  - Host input arrays are read during the call (or copied before a
+ *    non-blocking call returns); the caller keeps ownership.
+ *  - Outputs are written only when GBEM_OK is returned.
+ *  - "device" pointers are HIP device allocations on the context's device;
+ *    "stream" arguments are hipStream_t passed as void* (NULL = the
+ *    context's own stream).
+ *  - A context is bound to one device.  Calls on one context are serialised
+ *    internally, except gbem_submit/gbem_poll/gbem_wait which are thread-safe
+ *    and overlap with other jobs.
+ */
+#ifndef GBEM_H
+#define GBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gbem_ctx gbem_ctx;   /* opaque: device context, workspaces, serving loop */
+typedef struct gbem_job gbem_job;   /* opaque: one submitted extraction */
+
+typedef enum {
+    GBEM_OK = 0,
+    GBEM_EINVAL = 1,    /* invalid argument or mesh */
+    GBEM_ENOMEM = 2,    /* device memory or the HBM budget cannot hold the job */
+    GBEM_EDEVICE = 3,   /* a HIP call failed */
+    GBEM_ENOTPD = 4,    /* Cholesky met a non-positive pivot */
+    GBEM_ENOCONV = 5,   /* iterative refinement did not reach the tolerance */
+    GBEM_EBUSY = 6,     /* job still running (gbem_poll) */
+    GBEM_ETIMEOUT = 7   /* gbem_wait timed out */
+} gbem_status;
+
+typedef enum {
+    GBEM_F64 = 0,
+    GBEM_F32 = 1,
+    GBEM_F16 = 2,       /* factor stored FP32, trailing updates on FP16 MFMA, FP32 accumulate */
+    GBEM_BF16 = 3       /* factor stored FP32, trailing updates on BF16 MFMA, FP32 accumulate */
+} gbem_dtype;
+
+/* A mesh: n_panels axis-aligned rectangles.  Panel i is the box lo[3i..3i+2] ..
+ * hi[3i..3i+2] with exactly one axis where lo == hi (its normal axis) and
+ * lo < hi on the other two.  conductor[i] is in [-1, n_conductors); -1 marks
+ * a grounded panel (e.g. the paper's Dirichlet outer boundary, section 3.1)
+ * that takes part in the system but has no right-hand side and is not reported. */
+typedef struct {
+    int32_t n_panels;
+    int32_t n_conductors;
+    const double *lo;           /* [3 * n_panels] */
+    const double *hi;           /* [3 * n_panels] */
+    const int32_t *conductor;   /* [n_panels] */
+    double eps_r;               /* relative permittivity of the uniform dielectric, > 0 */
+    double length_unit_m;       /* metres per coordinate unit (1e-6 for micrometres), > 0 */
+} gbem_mesh;
+
+typedef struct {
+    int32_t far_order;          /* p: Gauss points per panel direction for far pairs, 1..8 (default 3) */
+    double near_eta;            /* near iff dist^2 < eta^2 * max(diam_i^2, diam_j^2) (default 2) */
+    int32_t far_dtype;          /* gbem_dtype of the far-pair arithmetic: GBEM_F64 or GBEM_F32 */
+    int32_t factor_dtype;       /* gbem_dtype of the factorisation (GBEM_F64: no refinement) */
+    double refine_tol;          /* refinement stops when max_k |b_k - A x_k|_2 / |b_k|_2 <= tol */
+    int32_t max_refine;         /* refinement iteration cap (default 30) */
+} gbem_opts;
+
+typedef struct {
+    double t_assemble_ms;       /* panel table + near list + far + near kernels */
+    double t_factor_ms;         /* scaling/conversion + Cholesky */
+    double t_solve_ms;          /* triangular solves + refinement + charge sums */
+    double t_total_ms;
+    double residual;            /* max_k |b_k - A x_k| / |b_k| (FP64 A), computed in the mixed modes */
+    double asym;                /* max |C - C^T| / max |C| */
+    int32_t refine_iters;
+    int32_t factor_used;        /* gbem_dtype actually used (after any fallback) */
+    int64_t n_near;             /* near pairs j <= i, diagonal included */
+    int64_t n_panels;
+} gbem_report;
+
+/* Version string of the library. */
+const char *gbem_version(void);
+/* Static text for a status code. */
+const char *gbem_status_str(gbem_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char *gbem_last_error(void);
+/* Fill *o with the defaults: p = 3, eta = 2, far FP64, factor FP64, tol 1e-6, 30 iterations. */
+void gbem_default_opts(gbem_opts *o);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory the serving loop admits jobs into (0 = 90 % of the free memory). */
+gbem_status gbem_create(int device, size_t hbm_budget_bytes, gbem_ctx **out);
+/* Wait for outstanding jobs, free every resource of the context. */
+gbem_status gbem_destroy(gbem_ctx *ctx);
+
+/* Whole extraction, synchronous: host mesh in, host C_out (n_conductors^2
+ * doubles, row-major, Farads) out.  rep may be NULL. */
+gbem_status gbem_extract(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                         double *C_out, gbem_report *rep);
+
+/* Same with a device-resident mesh (mesh->lo/hi/conductor are device pointers)
+ * and a device-resident C_out; work is queued on `stream` and the call returns
+ * when C_out is final on that stream. */
+gbem_status gbem_extract_device(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                double *C_out_device, void *stream, gbem_report *rep);
+
+/* Serving loop (continuous batching): submit copies the mesh and returns at
+ * once; jobs are admitted as their HBM footprint fits the budget and run
+ * concurrently on their own streams. */
+gbem_status gbem_submit(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, gbem_job **out);
+/* GBEM_OK when finished, GBEM_EBUSY while queued or running, else the job's error. */
+gbem_status gbem_poll(gbem_job *job);
+/* Block until the job finishes or timeout_s passes (< 0: no limit).  On
+ * GBEM_OK writes C_out (host, n_conductors^2, row-major) and *rep (may be NULL). */
+gbem_status gbem_wait(gbem_job *job, double timeout_s, double *C_out, gbem_report *rep);
+/* Release a finished job (waits for it if it is still running). */
+void gbem_job_free(gbem_job *job);
+/* Serving statistics: jobs finished, peak admitted bytes. */
+gbem_status gbem_server_stats(gbem_ctx *ctx, int64_t *jobs_done, size_t *peak_bytes);
+
+/* Mesher.  Boxes -> rectangles with a deterministic order (boxes as given;
+ * faces -x,+x,-y,+y,-z,+z; lower in-plane axis outer).  Edge rules:
+ *   kind 0 (uniform): n = max(1, ceil(L/h - 1e-9)) cells, edges lo + ((hi-lo)*k)/n
+ *   kind 1 (graded):  cells h_min, h_min*growth, ... from both ends while the
+ *                     cell is <= h_max and the run stays <= L/2; the middle is
+ *                     split uniformly into max(1, ceil(rem/h_max - 1e-9)) cells.
+ * Rejects boxes with non-positive extent and box surfaces that intersect. */
+typedef struct {
+    int32_t kind;               /* 0 uniform, 1 edge-graded */
+    double h;                   /* uniform cell size */
+    double h_min, growth, h_max;
+} gbem_mesh_rule;
+typedef struct {
+    int32_t n_panels;
+    double *lo, *hi;            /* library-allocated [3 * n_panels] */
+    int32_t *conductor;         /* library-allocated [n_panels] */
+} gbem_mesh_buf;
+gbem_status gbem_mesh_boxes(const double *box_lo, const double *box_hi, const int32_t *box_cond,
+                            int32_t n_boxes, const gbem_mesh_rule *rule, gbem_mesh_buf *out);
+/* Free the arrays of a gbem_mesh_buf filled by gbem_mesh_boxes. */
+void gbem_mesh_buf_free(gbem_mesh_buf *buf);
+
+/* ---- stage entry points (same kernels as gbem_extract; for parity tests) ---- */
+
+/* Near-pair list of the mesh (host arrays in/out): row_ptr[n+1], col[nnz] with
+ * j <= i ascending per row.  Call with col == NULL to get *nnz only. */
+gbem_status gbem_near_list(gbem_ctx *ctx, const gbem_mesh *mesh, double near_eta,
+                           int64_t *row_ptr, int32_t *col, int64_t col_capacity, int64_t *nnz);
+/* Assemble A and copy it to host A_out (n x n, row-major; A is symmetric). */
+gbem_status gbem_assemble(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, double *A_out);
+/* Assemble A with the same launches as gbem_extract and return m sampled
+ * entries out[k] = A[ii[k], jj[k]] (host arrays). */
+gbem_status gbem_assemble_sample(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                 int64_t m, const int32_t *ii, const int32_t *jj, double *out);
+/* In-place Cholesky A = L L^T of a device matrix (column-major, lower
+ * triangle referenced, leading dimension lda >= n).  dtype GBEM_F64 takes
+ * double*, GBEM_F32/F16/BF16 take float* (F16/BF16 = FP32 storage with 16-bit
+ * MFMA trailing updates).  On GBEM_ENOTPD *info = 1 + index of the first bad pivot. */
+gbem_status gbem_cholesky_device(gbem_ctx *ctx, int32_t n, int32_t dtype, void *A, int64_t lda,
+                                 int32_t *info, void *stream);
+/* Solve L L^T X = B in place on device (B: n x nrhs, column-major, ldb),
+ * L from gbem_cholesky_device with the same dtype. */
+gbem_status gbem_cholesky_solve_device(gbem_ctx *ctx, int32_t n, int32_t dtype, const void *L,
+                                       int64_t lda, int32_t nrhs, void *B, int64_t ldb, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBEM_H */

@@ -77,22 +77,52 @@ void oracle_gauss_legendre(int n, double *x, double *w)
 /* Adaptive one-dimensional quadrature: 16-point Gauss on [a,b] compared with */
 /* 16-point Gauss on both halves; bisect until they agree.                   */
 /* ------------------------------------------------------------------------ */
-typedef double (*fun1d)(double t, const double *par);
+/* The near-pair reductions run in x87 extended precision (long double, 64-bit
+ * significand): the corner sums cancel up to (D/h)^4 of their magnitude for
+ * panels of very different sizes, and the extra 11 bits keep the rounded FP64
+ * result accurate. */
+typedef long double real;
+typedef real (*fun1d)(real t, const real *par);
 
-static double g16x[16], g16w[16];
+static real g16x[16], g16w[16];
 static int g16_ready = 0;
+
+static void legendre_eval_l(int n, real x, real *pn, real *dpn)
+{
+    real p0 = 1.0L, p1 = x;
+    for (int k = 1; k < n; ++k) {
+        real p2 = ((2.0L * k + 1.0L) * x * p1 - k * p0) / (k + 1.0L);
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    *dpn = n * (x * p1 - p0) / (x * x - 1.0L);
+}
 
 static void ensure_g16(void)
 {
     if (!g16_ready) {
-        oracle_gauss_legendre(16, g16x, g16w);
+        const int n = 16;
+        for (int i = 0; i < n; ++i) {
+            real z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+            real pn, dpn;
+            for (int it = 0; it < 100; ++it) {
+                legendre_eval_l(n, z, &pn, &dpn);
+                real dz = pn / dpn;
+                z -= dz;
+                if (fabsl(dz) < 1e-21L) break;
+            }
+            legendre_eval_l(n, z, &pn, &dpn);
+            g16x[n - 1 - i] = z;
+            g16w[n - 1 - i] = 2.0L / ((1.0L - z * z) * dpn * dpn);
+        }
         g16_ready = 1;
     }
 }
 
-static double gauss16(fun1d f, const double *par, double a, double b)
+static real gauss16(fun1d f, const real *par, real a, real b)
 {
-    double m = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
+    real m = 0.5L * (a + b), h = 0.5L * (b - a), s = 0.0L;
     for (int k = 0; k < 16; ++k) s += g16w[k] * f(m + h * g16x[k], par);
     return s * h;
 }
@@ -101,50 +131,50 @@ static double gauss16(fun1d f, const double *par, double a, double b)
  * of a piece shrinks with its length while the tolerance does not, so the
  * refinement ends even where the integrand's own rounding noise is above the
  * tolerance of the whole interval; *budget bounds the work in any case. */
-static double adapt_rec(fun1d f, const double *par, double a, double b, double whole,
-                        double tol, int depth, long *budget)
+static real adapt_rec(fun1d f, const real *par, real a, real b, real whole, real tol, int depth,
+                      long *budget)
 {
-    double m = 0.5 * (a + b);
-    double left = gauss16(f, par, a, m), right = gauss16(f, par, m, b);
-    double both = left + right;
+    real m = 0.5L * (a + b);
+    real left = gauss16(f, par, a, m), right = gauss16(f, par, m, b);
+    real both = left + right;
     *budget -= 32;
-    if (depth >= 40 || *budget <= 0 || fabs(both - whole) <= tol) return both;
+    if (depth >= 40 || *budget <= 0 || fabsl(both - whole) <= tol) return both;
     return adapt_rec(f, par, a, m, left, tol, depth + 1, budget) +
            adapt_rec(f, par, m, b, right, tol, depth + 1, budget);
 }
 
 /* 16-point Gauss estimate of the integral of |f| over [a,b] */
-static double gauss16_abs(fun1d f, const double *par, double a, double b)
+static real gauss16_abs(fun1d f, const real *par, real a, real b)
 {
-    double m = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
-    for (int k = 0; k < 16; ++k) s += g16w[k] * fabs(f(m + h * g16x[k], par));
-    return s * fabs(h);
+    real m = 0.5L * (a + b), h = 0.5L * (b - a), s = 0.0L;
+    for (int k = 0; k < 16; ++k) s += g16w[k] * fabsl(f(m + h * g16x[k], par));
+    return s * fabsl(h);
 }
 
-/* Integral of f over [a,b] to about 1e-15 of the integral of |f| (estimated
+/* Integral of f over [a,b] to about 1e-18 of the integral of |f| (estimated
  * from the first 16-point sum). */
-static double integrate(fun1d f, const double *par, double a, double b)
+static real integrate(fun1d f, const real *par, real a, real b)
 {
-    if (a == b) return 0.0;
+    if (a == b) return 0.0L;
     ensure_g16();
-    double mag = gauss16_abs(f, par, a, b);
-    if (mag == 0.0) return 0.0;
+    real mag = gauss16_abs(f, par, a, b);
+    if (mag == 0.0L) return 0.0L;
     long budget = 400000;
-    return adapt_rec(f, par, a, b, gauss16(f, par, a, b), 2e-16 * mag, 0, &budget);
+    return adapt_rec(f, par, a, b, gauss16(f, par, a, b), 1e-18L * mag, 0, &budget);
 }
 
 /* ln(z + sqrt(z^2 + r2)) without cancellation when z < 0; r2 = the sum of the
  * other squared coordinates.  Returns 0 when the argument is exactly 0, for use
  * only where the prefactor vanishes there (limit x ln x -> 0). */
-static double log_z_plus_r(double z, double r2)
+static real log_z_plus_r(real z, real r2)
 {
-    double R = sqrt(z * z + r2);
-    if (z >= 0.0) {
-        double s = z + R;
-        return s > 0.0 ? log(s) : 0.0;
+    real R = sqrtl(z * z + r2);
+    if (z >= 0.0L) {
+        real s = z + R;
+        return s > 0.0L ? logl(s) : 0.0L;
     }
-    if (r2 <= 0.0) return 0.0;
-    return log(r2) - log(R - z);
+    if (r2 <= 0.0L) return 0.0L;
+    return logl(r2) - logl(R - z);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -153,42 +183,42 @@ static double log_z_plus_r(double z, double r2)
 /* is a ln(a + sqrt(a^2 + u^2)) - sqrt(a^2 + u^2); G1 and G2 are its second  */
 /* antiderivatives in u (u = difference along the second in-plane axis).     */
 /* ------------------------------------------------------------------------ */
-static double G1(double a, double u)
+static real G1(real a, real u)
 {
-    double r2a = a * a, r2u = u * u;
-    double R = sqrt(r2a + r2u);
-    double t = 0.0;
-    if (a != 0.0 && u != 0.0) t += 0.5 * a * r2u * log_z_plus_r(a, r2u);
-    t -= 0.75 * a * r2u;
-    t -= 0.5 * r2a * R;
-    if (a != 0.0 && u != 0.0) t += r2a * u * log_z_plus_r(u, r2a);
+    real r2a = a * a, r2u = u * u;
+    real R = sqrtl(r2a + r2u);
+    real t = 0.0L;
+    if (a != 0.0L && u != 0.0L) t += 0.5L * a * r2u * log_z_plus_r(a, r2u);
+    t -= 0.75L * a * r2u;
+    t -= 0.5L * r2a * R;
+    if (a != 0.0L && u != 0.0L) t += r2a * u * log_z_plus_r(u, r2a);
     return t;
 }
 
-static double G2(double a, double u)
+static real G2(real a, real u)
 {
-    double r2a = a * a, r2u = u * u;
-    double R = sqrt(r2a + r2u);
-    double t = (r2u + r2a) * R / 6.0;
-    if (a != 0.0 && u != 0.0) t += 0.5 * r2a * u * log_z_plus_r(u, r2a);
-    t -= 0.5 * r2a * R;
+    real r2a = a * a, r2u = u * u;
+    real R = sqrtl(r2a + r2u);
+    real t = (r2u + r2a) * R / 6.0L;
+    if (a != 0.0L && u != 0.0L) t += 0.5L * r2a * u * log_z_plus_r(u, r2a);
+    t -= 0.5L * r2a * R;
     return t;
 }
 
 /* Sign of a corner of the difference operator D along one axis shared by both
  * panels: the double integral of g(x - y) over [xd,xu] x [yd,yu] equals
  * sum over corners of -s(x) s(y) H(x_c - y_c), H'' = g, s(upper)=+1, s(lower)=-1. */
-static double coplanar_integral(const double x1[2], const double x2[2],
-                                const double y1[2], const double y2[2])
+static real coplanar_integral(const double x1[2], const double x2[2],
+                              const double y1[2], const double y2[2])
 {
-    double g = 0.0;
+    real g = 0.0L;
     for (int al = 0; al < 2; ++al)
         for (int be = 0; be < 2; ++be)
             for (int ga = 0; ga < 2; ++ga)
                 for (int de = 0; de < 2; ++de) {
-                    double sg = ((al + be + ga + de) & 1) ? -1.0 : 1.0;
-                    double a = x1[al] - y1[be];
-                    double u = x2[ga] - y2[de];
+                    real sg = ((al + be + ga + de) & 1) ? -1.0L : 1.0L;
+                    real a = (real)x1[al] - (real)y1[be];
+                    real u = (real)x2[ga] - (real)y2[de];
                     g += sg * (G1(a, u) - G2(a, u));
                 }
     return g;
@@ -200,40 +230,40 @@ static double coplanar_integral(const double x1[2], const double x2[2],
 /* double integral over the second axis to one dimension with the trapezoid  */
 /* weight of eq. int3.                                                        */
 /* ------------------------------------------------------------------------ */
-static double par_integrand(double t, const double *par)
+static real par_integrand(real t, const real *par)
 {
     /* par: s, b2, tau0, dx, dy */
-    double s = par[0], b2 = par[1], tau = t + par[2], dx = par[3], dy = par[4];
-    double w = t;
-    double dmin = dx < dy ? dx : dy;
+    real s = par[0], b2 = par[1], tau = t + par[2], dx = par[3], dy = par[4];
+    real w = t;
+    real dmin = dx < dy ? dx : dy;
     if (dmin < w) w = dmin;
     if (dx + dy - t < w) w = dx + dy - t;
-    if (w <= 0.0) return 0.0;
-    double r2 = tau * tau + b2;
-    double R = sqrt(s * s + r2);
-    double h = -R;
-    if (s != 0.0) h += s * log_z_plus_r(s, r2);
+    if (w <= 0.0L) return 0.0L;
+    real r2 = tau * tau + b2;
+    real R = sqrtl(s * s + r2);
+    real h = -R;
+    if (s != 0.0L) h += s * log_z_plus_r(s, r2);
     return w * h;
 }
 
-static double parallel_offset_integral(const double x1[2], const double x2[2],
-                                       const double y1[2], const double y2[2], double b)
+static real parallel_offset_integral(const double x1[2], const double x2[2],
+                                     const double y1[2], const double y2[2], double b)
 {
-    double dx = x2[1] - x2[0], dy = y2[1] - y2[0];
-    double dmin = dx < dy ? dx : dy, dmax = dx < dy ? dy : dx;
-    double g = 0.0;
+    real dx = (real)x2[1] - x2[0], dy = (real)y2[1] - y2[0];
+    real dmin = dx < dy ? dx : dy, dmax = dx < dy ? dy : dx;
+    real g = 0.0L;
     for (int al = 0; al < 2; ++al)
         for (int be = 0; be < 2; ++be) {
-            double sg = (al == be) ? -1.0 : 1.0;   /* -s(x)s(y) */
-            double par[5];
-            par[0] = x1[al] - y1[be];
-            par[1] = b * b;
-            par[2] = x2[0] - y2[1];
+            real sg = (al == be) ? -1.0L : 1.0L;   /* -s(x)s(y) */
+            real par[5];
+            par[0] = (real)x1[al] - (real)y1[be];
+            par[1] = (real)b * (real)b;
+            par[2] = (real)x2[0] - (real)y2[1];
             par[3] = dx;
             par[4] = dy;
-            double v = integrate(par_integrand, par, 0.0, dmin) +
-                       integrate(par_integrand, par, dmin, dmax) +
-                       integrate(par_integrand, par, dmax, dx + dy);
+            real v = integrate(par_integrand, par, 0.0L, dmin) +
+                     integrate(par_integrand, par, dmin, dmax) +
+                     integrate(par_integrand, par, dmax, dx + dy);
             g += sg * v;
         }
     return g;
@@ -249,42 +279,42 @@ static double parallel_offset_integral(const double x1[2], const double x2[2],
 /*          - 1/2 ( [a x y]_{x,y} - [Int a^2 ln(y+R) dx]_y )                  */
 /* and the wanted double integral of H = a ln(a+R) - R is I_L - I_R.          */
 /* ------------------------------------------------------------------------ */
-static double f_g3(double x, const double *par)
+static real f_g3(real x, const real *par)
 {
     /* par: a, y ; G3(x,y) = y/2 R + (x^2 + a^2)/2 ln(y + R) */
-    double a = par[0], y = par[1];
-    double r2 = x * x + a * a;
-    double R = sqrt(r2 + y * y);
-    double t = 0.5 * y * R;
-    if (r2 != 0.0) t += 0.5 * r2 * log_z_plus_r(y, r2);
+    real a = par[0], y = par[1];
+    real r2 = x * x + a * a;
+    real R = sqrtl(r2 + y * y);
+    real t = 0.5L * y * R;
+    if (r2 != 0.0L) t += 0.5L * r2 * log_z_plus_r(y, r2);
     return t;
 }
 
-static double f_yaln(double x, const double *par)
+static real f_yaln(real x, const real *par)
 {
     /* par: a, y ; y a ln(a + R) */
-    double a = par[0], y = par[1];
-    if (a == 0.0 || y == 0.0) return 0.0;
+    real a = par[0], y = par[1];
+    if (a == 0.0L || y == 0.0L) return 0.0L;
     return y * a * log_z_plus_r(a, x * x + y * y);
 }
 
-static double f_a2lny(double x, const double *par)
+static real f_a2lny(real x, const real *par)
 {
     /* par: a, y ; a^2 ln(y + R) */
-    double a = par[0], y = par[1];
-    if (a == 0.0) return 0.0;
+    real a = par[0], y = par[1];
+    if (a == 0.0L) return 0.0L;
     return a * a * log_z_plus_r(y, x * x + a * a);
 }
 
-static double orth_double(double a, double xd, double xu, double yd, double yu)
+static real orth_double(real a, real xd, real xu, real yd, real yu)
 {
-    double par[2];
-    double IR = 0.0, IL = 0.0;
+    real par[2];
+    real IR = 0.0L, IL = 0.0L;
     /* I_R */
     par[0] = a; par[1] = yu; IR += integrate(f_g3, par, xd, xu);
     par[1] = yd;             IR -= integrate(f_g3, par, xd, xu);
-    if (a != 0.0) {
-        double t1 = 0.0, t2 = 0.0, t3, t4 = 0.0;
+    if (a != 0.0L) {
+        real t1 = 0.0L, t2 = 0.0L, t3, t4 = 0.0L;
         par[0] = a; par[1] = yu; t1 += integrate(f_yaln, par, xd, xu);
         par[1] = yd;             t1 -= integrate(f_yaln, par, xd, xu);
         /* x a ln(a+R) integrated over y at x = xu, xd (same function with roles swapped) */
@@ -293,7 +323,7 @@ static double orth_double(double a, double xd, double xu, double yd, double yu)
         t3 = a * (xu * yu - xu * yd - xd * yu + xd * yd);
         par[1] = yu;             t4 += integrate(f_a2lny, par, xd, xu);
         par[1] = yd;             t4 -= integrate(f_a2lny, par, xd, xu);
-        IL = 0.5 * t1 + 0.5 * t2 - 0.5 * (t3 - t4);
+        IL = 0.5L * t1 + 0.5L * t2 - 0.5L * (t3 - t4);
     }
     return IL - IR;
 }
@@ -301,17 +331,17 @@ static double orth_double(double a, double xd, double xu, double yd, double yu)
 /* panel i spans the shared axis (xs) and the normal axis of j (xq) at X (its
  * own plane); panel j spans the shared axis (ys) and the normal axis of i (yp)
  * at Y. */
-static double orthogonal_integral(const double xs[2], const double xq[2], double X,
-                                  const double ys[2], const double yp[2], double Y)
+static real orthogonal_integral(const double xs[2], const double xq[2], double X,
+                                const double ys[2], const double yp[2], double Y)
 {
-    double g = 0.0;
+    real g = 0.0L;
     for (int al = 0; al < 2; ++al)
         for (int be = 0; be < 2; ++be) {
-            double sg = (al == be) ? -1.0 : 1.0;
-            double a = xs[al] - ys[be];
+            real sg = (al == be) ? -1.0L : 1.0L;
+            real a = (real)xs[al] - (real)ys[be];
             /* x <-> offset of the point of panel i along j's normal: xq - Y
                y <-> offset of the point of panel j along i's normal: yp - X */
-            g += sg * orth_double(a, xq[0] - Y, xq[1] - Y, yp[0] - X, yp[1] - X);
+            g += sg * orth_double(a, (real)xq[0] - Y, (real)xq[1] - Y, (real)yp[0] - X, (real)yp[1] - X);
         }
     return g;
 }
@@ -319,7 +349,7 @@ static double orthogonal_integral(const double xs[2], const double xq[2], double
 /* ------------------------------------------------------------------------ */
 /* Panels                                                                    */
 /* ------------------------------------------------------------------------ */
-static int normal_axis(const double *lo, const double *hi)
+int normal_axis(const double *lo, const double *hi)
 {
     for (int k = 0; k < 3; ++k)
         if (lo[k] == hi[k]) return k;
@@ -337,13 +367,13 @@ double oracle_pair_integral_exact(const double *lo_i, const double *hi_i,
         double x1[2] = {lo_i[t1], hi_i[t1]}, x2[2] = {lo_i[t2], hi_i[t2]};
         double y1[2] = {lo_j[t1], hi_j[t1]}, y2[2] = {lo_j[t2], hi_j[t2]};
         double b = lo_i[ni] - lo_j[ni];
-        if (b == 0.0) return coplanar_integral(x1, x2, y1, y2);
-        return parallel_offset_integral(x1, x2, y1, y2, b);
+        if (b == 0.0) return (double)coplanar_integral(x1, x2, y1, y2);
+        return (double)parallel_offset_integral(x1, x2, y1, y2, b);
     }
     int s = 3 - ni - nj;
     double xs[2] = {lo_i[s], hi_i[s]}, xq[2] = {lo_i[nj], hi_i[nj]};
     double ys[2] = {lo_j[s], hi_j[s]}, yp[2] = {lo_j[ni], hi_j[ni]};
-    return orthogonal_integral(xs, xq, lo_i[ni], ys, yp, lo_j[nj]);
+    return (double)orthogonal_integral(xs, xq, lo_i[ni], ys, yp, lo_j[nj]);
 }
 
 double oracle_panel_area(const double *lo, const double *hi)

@@ -1,0 +1,308 @@
+"""ctypes binding of libgbem (include/gbem.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch appears only to hand device buffers and streams to the
+``*_device`` entry points.  Loading fails loudly when the library is missing;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgbem.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENOCONV, EBUSY, ETIMEOUT = range(8)
+F64, F32, F16, BF16 = range(4)
+DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+
+EXPORTS = [
+    "gbem_version", "gbem_status_str", "gbem_last_error", "gbem_default_opts", "gbem_create",
+    "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit", "gbem_poll", "gbem_wait",
+    "gbem_job_free", "gbem_server_stats", "gbem_mesh_boxes", "gbem_mesh_buf_free", "gbem_near_list",
+    "gbem_assemble", "gbem_assemble_sample", "gbem_cholesky_device", "gbem_cholesky_solve_device",
+]
+
+
+class GbemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gbem status {status}: {msg}")
+        self.status = status
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("n_panels", ctypes.c_int32), ("n_conductors", ctypes.c_int32),
+                ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("conductor", ctypes.c_void_p),
+                ("eps_r", ctypes.c_double), ("length_unit_m", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("far_order", ctypes.c_int32), ("near_eta", ctypes.c_double),
+                ("far_dtype", ctypes.c_int32), ("factor_dtype", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("t_assemble_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("residual", ctypes.c_double), ("asym", ctypes.c_double),
+                ("refine_iters", ctypes.c_int32), ("factor_used", ctypes.c_int32),
+                ("n_near", ctypes.c_int64), ("n_panels", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MeshRule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("h", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("growth", ctypes.c_double), ("h_max", ctypes.c_double)]
+
+
+class MeshBuf(ctypes.Structure):
+    _fields_ = [("n_panels", ctypes.c_int32), ("lo", ctypes.POINTER(ctypes.c_double)),
+                ("hi", ctypes.POINTER(ctypes.c_double)), ("conductor", ctypes.POINTER(ctypes.c_int32))]
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+
+
+def load():
+    """Load libgbem.so (built by ``__graft_entry__.build()``); raises if missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.gbem_version.restype = ctypes.c_char_p
+    lib.gbem_status_str.restype = ctypes.c_char_p
+    lib.gbem_status_str.argtypes = [ctypes.c_int]
+    lib.gbem_last_error.restype = ctypes.c_char_p
+    lib.gbem_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.gbem_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)]
+    lib.gbem_destroy.argtypes = [_vp]
+    lib.gbem_extract.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp, ctypes.POINTER(Report)]
+    lib.gbem_extract_device.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp, _vp,
+                                        ctypes.POINTER(Report)]
+    lib.gbem_submit.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
+    lib.gbem_poll.argtypes = [_vp]
+    lib.gbem_wait.argtypes = [_vp, ctypes.c_double, _vp, ctypes.POINTER(Report)]
+    lib.gbem_job_free.argtypes = [_vp]
+    lib.gbem_job_free.restype = None
+    lib.gbem_server_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]
+    lib.gbem_mesh_boxes.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(MeshRule),
+                                    ctypes.POINTER(MeshBuf)]
+    lib.gbem_mesh_buf_free.argtypes = [ctypes.POINTER(MeshBuf)]
+    lib.gbem_mesh_buf_free.restype = None
+    lib.gbem_near_list.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.c_double, _vp, _vp, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64)]
+    lib.gbem_assemble.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp]
+    lib.gbem_assemble_sample.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), ctypes.c_int64,
+                                         _vp, _vp, _vp]
+    lib.gbem_cholesky_device.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int32), _vp]
+    lib.gbem_cholesky_solve_device.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
+                                               ctypes.c_int32, _vp, ctypes.c_int64, _vp]
+    for name in ("gbem_create", "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit",
+                 "gbem_poll", "gbem_wait", "gbem_server_stats", "gbem_mesh_boxes", "gbem_near_list",
+                 "gbem_assemble", "gbem_assemble_sample", "gbem_cholesky_device",
+                 "gbem_cholesky_solve_device"):
+        getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(st: int):
+    if st != OK:
+        lib = load()
+        raise GbemError(st, lib.gbem_last_error().decode())
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def make_opts(far_order=3, near_eta=2.0, far_dtype="f64", factor_dtype="f64", refine_tol=1e-6,
+              max_refine=30) -> Opts:
+    return Opts(far_order, near_eta, DTYPES[far_dtype] if isinstance(far_dtype, str) else far_dtype,
+                DTYPES[factor_dtype] if isinstance(factor_dtype, str) else factor_dtype, refine_tol, max_refine)
+
+
+def mesh_boxes(box_lo, box_hi, box_cond, rule):
+    """Library mesher: returns (lo, hi, cond) numpy arrays."""
+    lib = load()
+    blo = np.ascontiguousarray(box_lo, dtype=np.float64).reshape(-1, 3)
+    bhi = np.ascontiguousarray(box_hi, dtype=np.float64).reshape(-1, 3)
+    bc = np.ascontiguousarray(box_cond, dtype=np.int32).reshape(-1)
+    if rule[0] == "uniform":
+        r = MeshRule(0, rule[1], 0.0, 0.0, 0.0)
+    else:
+        r = MeshRule(1, 0.0, rule[1], rule[2], rule[3])
+    buf = MeshBuf()
+    _check(lib.gbem_mesh_boxes(_ptr(blo), _ptr(bhi), _ptr(bc), blo.shape[0], ctypes.byref(r), ctypes.byref(buf)))
+    try:
+        n = buf.n_panels
+        lo = np.ctypeslib.as_array(buf.lo, shape=(n * 3,)).reshape(n, 3).copy()
+        hi = np.ctypeslib.as_array(buf.hi, shape=(n * 3,)).reshape(n, 3).copy()
+        cond = np.ctypeslib.as_array(buf.conductor, shape=(n,)).copy()
+    finally:
+        lib.gbem_mesh_buf_free(ctypes.byref(buf))
+    return lo, hi, cond
+
+
+def mesh_layout(layout):
+    blo, bhi, bcond = layout.arrays()
+    return mesh_boxes(blo, bhi, bcond, layout.rule)
+
+
+class Context:
+    """A device context: synchronous extraction, serving loop and stage calls."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.lib = load()
+        h = _vp()
+        _check(self.lib.gbem_create(device, hbm_budget_bytes, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.gbem_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _mesh(lo, hi, cond, n_cond, eps_r, lu):
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        cond = np.ascontiguousarray(cond, dtype=np.int32)
+        m = Mesh(cond.shape[0], n_cond, lo.ctypes.data, hi.ctypes.data, cond.ctypes.data, eps_r, lu)
+        return m, (lo, hi, cond)
+
+    def extract(self, lo, hi, cond, n_conductors, eps_r, length_unit_m, opts: Opts | None = None):
+        m, keep = self._mesh(lo, hi, cond, n_conductors, eps_r, length_unit_m)
+        C = np.zeros((n_conductors, n_conductors))
+        rep = Report()
+        o = opts or make_opts()
+        _check(self.lib.gbem_extract(self.h, ctypes.byref(m), ctypes.byref(o), _ptr(C), ctypes.byref(rep)))
+        return C, rep.as_dict()
+
+    def extract_layout(self, layout, opts: Opts | None = None):
+        lo, hi, cond = mesh_layout(layout)
+        return self.extract(lo, hi, cond, layout.n_conductors, layout.eps_r, layout.length_unit_m, opts)
+
+    def extract_device(self, d_lo, d_hi, d_cond, n_conductors, eps_r, length_unit_m, d_C,
+                       opts: Opts | None = None, stream=None):
+        """Device-resident mesh and output (torch tensors on the context's device)."""
+        m = Mesh(d_cond.shape[0], n_conductors, d_lo.data_ptr(), d_hi.data_ptr(), d_cond.data_ptr(), eps_r,
+                 length_unit_m)
+        rep = Report()
+        o = opts or make_opts()
+        st = stream.cuda_stream if stream is not None else None
+        _check(self.lib.gbem_extract_device(self.h, ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(d_C.data_ptr()),
+                                            ctypes.c_void_p(st), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def near_list(self, lo, hi, near_eta=2.0):
+        n = np.asarray(lo).shape[0]
+        m, keep = self._mesh(lo, hi, np.zeros(n, dtype=np.int32), 1, 1.0, 1.0)
+        rp = np.zeros(n + 1, dtype=np.int64)
+        nnz = ctypes.c_int64(0)
+        _check(self.lib.gbem_near_list(self.h, ctypes.byref(m), near_eta, _ptr(rp), None, 0, ctypes.byref(nnz)))
+        col = np.zeros(max(nnz.value, 1), dtype=np.int32)
+        _check(self.lib.gbem_near_list(self.h, ctypes.byref(m), near_eta, _ptr(rp), _ptr(col), col.shape[0],
+                                       ctypes.byref(nnz)))
+        return rp, col[:nnz.value]
+
+    def assemble(self, lo, hi, opts: Opts | None = None):
+        n = np.asarray(lo).shape[0]
+        m, keep = self._mesh(lo, hi, np.zeros(n, dtype=np.int32), 1, 1.0, 1.0)
+        A = np.zeros((n, n))
+        o = opts or make_opts()
+        _check(self.lib.gbem_assemble(self.h, ctypes.byref(m), ctypes.byref(o), _ptr(A)))
+        return A
+
+    def assemble_sample(self, lo, hi, ii, jj, opts: Opts | None = None, cond=None, n_conductors=1):
+        n = np.asarray(lo).shape[0]
+        if cond is None:
+            cond = np.zeros(n, dtype=np.int32)
+        m, keep = self._mesh(lo, hi, cond, n_conductors, 1.0, 1.0)
+        ii = np.ascontiguousarray(ii, dtype=np.int32)
+        jj = np.ascontiguousarray(jj, dtype=np.int32)
+        out = np.zeros(ii.shape[0])
+        o = opts or make_opts()
+        _check(self.lib.gbem_assemble_sample(self.h, ctypes.byref(m), ctypes.byref(o), ii.shape[0], _ptr(ii),
+                                             _ptr(jj), _ptr(out)))
+        return out
+
+    def cholesky_device(self, A, dtype="f64", stream=None):
+        """In-place Cholesky of a square torch tensor (column-major view: pass A.T of a row-major tensor)."""
+        n = A.shape[0]
+        info = ctypes.c_int32(0)
+        st = stream.cuda_stream if stream is not None else None
+        lda = A.stride(1) if A.stride(0) == 1 else A.stride(0)
+        _check(self.lib.gbem_cholesky_device(self.h, n, DTYPES[dtype], ctypes.c_void_p(A.data_ptr()), lda,
+                                             ctypes.byref(info), ctypes.c_void_p(st)))
+        return info.value
+
+    def cholesky_solve_device(self, L, B, dtype="f64", stream=None):
+        n = L.shape[0]
+        st = stream.cuda_stream if stream is not None else None
+        lda = L.stride(1) if L.stride(0) == 1 else L.stride(0)
+        ldb = B.stride(1)
+        _check(self.lib.gbem_cholesky_solve_device(self.h, n, DTYPES[dtype], ctypes.c_void_p(L.data_ptr()), lda,
+                                                   B.shape[1], ctypes.c_void_p(B.data_ptr()), ldb,
+                                                   ctypes.c_void_p(st)))
+
+    # ---- serving
+    def submit(self, lo, hi, cond, n_conductors, eps_r, length_unit_m, opts: Opts | None = None):
+        m, keep = self._mesh(lo, hi, cond, n_conductors, eps_r, length_unit_m)
+        o = opts or make_opts()
+        j = _vp()
+        _check(self.lib.gbem_submit(self.h, ctypes.byref(m), ctypes.byref(o), ctypes.byref(j)))
+        return Job(self.lib, j, n_conductors)
+
+    def server_stats(self):
+        d = ctypes.c_int64(0)
+        p = ctypes.c_size_t(0)
+        _check(self.lib.gbem_server_stats(self.h, ctypes.byref(d), ctypes.byref(p)))
+        return {"jobs_done": d.value, "peak_bytes": p.value}
+
+
+class Job:
+    def __init__(self, lib, h, m):
+        self.lib, self.h, self.m = lib, h, m
+
+    def poll(self) -> int:
+        return self.lib.gbem_poll(self.h)
+
+    def wait(self, timeout_s: float = -1.0):
+        C = np.zeros((self.m, self.m))
+        rep = Report()
+        _check(self.lib.gbem_wait(self.h, timeout_s, _ptr(C), ctypes.byref(rep)))
+        return C, rep.as_dict()
+
+    def free(self):
+        if self.h:
+            self.lib.gbem_job_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

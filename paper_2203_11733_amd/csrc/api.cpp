@@ -1,0 +1,1003 @@
+// C ABI of libgbem: contexts, the extraction pipeline, the serving loop and
+// the stage entry points.  Every numerical step runs in the HIP kernels of
+// this library; the host code only sequences launches, sizes workspaces and
+// moves the (small) inputs and outputs.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "gbem_internal.h"
+
+namespace gbem {
+
+static thread_local std::string t_err;
+void set_error(const std::string &msg) { t_err = msg; }
+
+// Gauss-Legendre rule: Newton iteration on P_p (Bonnet recurrence, long
+// double) from Tricomi's asymptotic node estimates.
+void gauss_legendre(int p, double *xo, double *wo)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 1; i <= p; ++i) {
+        long double th = pi * (4.0L * i - 1.0L) / (4.0L * p + 2.0L);
+        long double x = (1.0L - 1.0L / (8.0L * p * p) + 1.0L / (8.0L * p * p * p)) * cosl(th);
+        long double dp = 1.0L;
+        for (int it = 0; it < 50; ++it) {
+            long double p0 = 1.0L, p1 = x;
+            for (int k = 2; k <= p; ++k) {
+                long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (p == 1) p0 = 1.0L;
+            dp = p * (p0 - x * p1) / (1.0L - x * x);
+            long double dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) < 1e-19L) break;
+        }
+        // nodes ascending: i = 1 is the largest root
+        const int idx = p - i;
+        xo[idx] = (double)x;
+        wo[idx] = (double)(1.0L / ((1.0L - x * x) * dp * dp));   // = w/2 (halved weight)
+    }
+}
+
+void gauss_legendre_rule(int p, GaussRule *r)
+{
+    memset(r, 0, sizeof(*r));
+    gauss_legendre(p, r->x, r->w);
+    for (int a = 0; a < p; ++a) {
+        r->xf[a] = (float)r->x[a];
+        for (int b = 0; b < p; ++b) {
+            r->ww[a * p + b] = r->w[a] * r->w[b];
+            r->wwf[a * p + b] = (float)r->ww[a * p + b];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// device buffers
+// ------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        release();
+        size_t want = (bytes + 4095) & ~(size_t)4095;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        cap = want;
+        return hipSuccess;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+struct Workspace {
+    DevBuf lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, D, s, partial, C,
+        flags, norms;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool events_ok = false;
+
+    size_t bytes() const
+    {
+        const DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv,
+                               &Pw, &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms};
+        size_t t = 0;
+        for (auto *b : all) t += b->cap;
+        return t;
+    }
+    void release_all()
+    {
+        DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv,
+                         &Pw, &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms};
+        for (auto *b : all) b->release();
+    }
+    hipError_t init_events()
+    {
+        if (events_ok) return hipSuccess;
+        for (auto &e : ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+        }
+        events_ok = true;
+        return hipSuccess;
+    }
+    ~Workspace()
+    {
+        release_all();
+        if (events_ok)
+            for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+// Device bytes one extraction needs (near list estimated at 512 entries/row).
+static size_t footprint(int64_t n, int m, int factor_dtype)
+{
+    const int64_t npad = round_up(n, kPad);
+    size_t b = (size_t)npad * npad * 8;                                   // A
+    if (factor_dtype != GBEM_F64) b += (size_t)npad * npad * 4;           // FP32 factor
+    const size_t es = factor_dtype == GBEM_F64 ? 8 : 4;
+    b += 2 * (size_t)npad * kNB * es + (size_t)npad * kNB * 2;           // W, panel, 16-bit panel
+    b += 4 * (size_t)npad * m * 8 + (size_t)npad * 8;                    // B X R D, s
+    b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 8;            // mesh, panels, near list
+    return b;
+}
+
+static gbem_status dev_fail(hipError_t e, const char *where)
+{
+    set_error(std::string(where) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? GBEM_ENOMEM : GBEM_EDEVICE;
+}
+
+#define HIPCHK(call, where)                                   \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return dev_fail(e_, where);     \
+    } while (0)
+
+static bool opts_ok(const gbem_opts &o, std::string &why)
+{
+    if (o.far_order < 1 || o.far_order > kMaxOrder || o.far_order == 7) {
+        why = "far_order must be 1..6 or 8";
+        return false;
+    }
+    if (!(o.near_eta >= 0.0) || !isfinite(o.near_eta)) {
+        why = "near_eta must be a finite number >= 0";
+        return false;
+    }
+    if (o.far_dtype != GBEM_F64 && o.far_dtype != GBEM_F32) {
+        why = "far_dtype must be GBEM_F64 or GBEM_F32";
+        return false;
+    }
+    if (o.factor_dtype < GBEM_F64 || o.factor_dtype > GBEM_BF16) {
+        why = "unknown factor_dtype";
+        return false;
+    }
+    if (o.factor_dtype != GBEM_F64 && (!(o.refine_tol > 0.0) || o.max_refine < 0)) {
+        why = "refinement needs refine_tol > 0 and max_refine >= 0";
+        return false;
+    }
+    return true;
+}
+
+static bool mesh_header_ok(const gbem_mesh *m, std::string &why)
+{
+    if (!m || m->n_panels <= 0 || !m->lo || !m->hi || !m->conductor) {
+        why = "mesh needs n_panels > 0 and lo/hi/conductor arrays";
+        return false;
+    }
+    if (m->n_conductors < 1 || m->n_conductors > kMaxRhs) {
+        why = "n_conductors must be in 1..64";
+        return false;
+    }
+    if (!(m->eps_r > 0.0) || !(m->length_unit_m > 0.0) || !isfinite(m->eps_r) || !isfinite(m->length_unit_m)) {
+        why = "eps_r and length_unit_m must be positive and finite";
+        return false;
+    }
+    return true;
+}
+
+struct Timing {
+    float assemble = 0, factor = 0, solve = 0, total = 0;
+};
+
+enum class Stop { kAssembled, kFull };
+
+// The extraction pipeline on one stream and workspace.  Mesh arrays and C
+// are device pointers.
+static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, const double *dlo,
+                                const double *dhi, const int32_t *dcond, double eps_r, double lu,
+                                const gbem_opts &o, double *dC, gbem_report *rep, Stop stop)
+{
+    const int64_t npad = round_up(n, kPad);
+    HIPCHK(ws.init_events(), "hipEventCreate");
+    HIPCHK(ws.pan.ensure(sizeof(Panel) * n), "alloc panels");
+    HIPCHK(ws.cnt.ensure(sizeof(int64_t) * n), "alloc near counts");
+    HIPCHK(ws.rowptr.ensure(sizeof(int64_t) * (n + 1)), "alloc row_ptr");
+    HIPCHK(ws.flags.ensure(64), "alloc flags");
+    HIPCHK(ws.A.ensure((size_t)npad * npad * 8), "alloc A");
+    HIPCHK(ws.B.ensure((size_t)npad * m * 8), "alloc B");
+    HIPCHK(ws.norms.ensure(sizeof(double) * 2 * kMaxRhs), "alloc norms");
+    int32_t *flags = ws.flags.as<int32_t>();   // [0] bad panel, [1] factor info
+    double *A = ws.A.as<double>();
+    const int64_t lda = npad;
+
+    HIPCHK(hipEventRecord(ws.ev[0], st), "hipEventRecord");
+    HIPCHK(hipMemsetAsync(flags, 0, 64, st), "hipMemsetAsync");
+    HIPCHK(launch_build_panels(dlo, dhi, dcond, n, m, ws.pan.as<Panel>(), flags, st), "build_panels");
+    const double eta2 = o.near_eta * o.near_eta;
+    HIPCHK(launch_near_count(dlo, dhi, n, eta2, ws.cnt.as<int64_t>(), st), "near_count");
+    HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), st), "scan");
+    double *B = ws.B.as<double>();
+    HIPCHK(launch_rhs(dcond, n, (int)npad, m, B, npad, st), "rhs");
+    double *bnorm = ws.norms.as<double>() + kMaxRhs;
+    HIPCHK(launch_col_norms(B, npad, (int)npad, m, bnorm, st), "col_norms");
+
+    // one host sync: near-list size, validation flag, panels per conductor
+    int64_t nnz = 0;
+    int32_t bad = 0;
+    double bn[kMaxRhs];
+    HIPCHK(hipMemcpyAsync(&nnz, ws.rowptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st), "D2H nnz");
+    HIPCHK(hipMemcpyAsync(&bad, flags, 4, hipMemcpyDeviceToHost, st), "D2H flag");
+    HIPCHK(hipMemcpyAsync(bn, bnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
+    HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (bad) {
+        set_error("panel " + std::to_string(bad - 1) +
+                  " is not an axis-aligned rectangle with exactly one zero extent, or its conductor id is out of range");
+        return GBEM_EINVAL;
+    }
+    for (int k = 0; k < m; ++k)
+        if (bn[k] == 0.0) {
+            set_error("conductor " + std::to_string(k) + " has no panels");
+            return GBEM_EINVAL;
+        }
+
+    HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near rows");
+    HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
+    HIPCHK(launch_near_fill(dlo, dhi, n, eta2, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
+                            ws.ncol.as<int32_t>(), st), "near_fill");
+    GaussRule rule;
+    gauss_legendre_rule(o.far_order, &rule);
+    HIPCHK(launch_far(ws.pan.as<Panel>(), n, (int)npad, o.far_order, rule, o.far_dtype, A, lda, st), "far");
+    HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
+                            A, lda, st), "near_eval");
+    HIPCHK(hipEventRecord(ws.ev[1], st), "hipEventRecord");
+    if (rep) {
+        rep->n_near = nnz;
+        rep->n_panels = n;
+    }
+    if (stop == Stop::kAssembled) return GBEM_OK;
+
+    HIPCHK(ws.X.ensure((size_t)npad * m * 8), "alloc X");
+    double *X = ws.X.as<double>();
+    int dtype = o.factor_dtype;
+    int iters = 0;
+    double resid = 0.0;
+    for (;;) {   // fallback loop: a failed low-precision factor retries one level up
+        const size_t es = dtype == GBEM_F64 ? 8 : 4;
+        HIPCHK(ws.Winv.ensure(chol_winv_bytes(dtype, npad)), "alloc W");
+        HIPCHK(ws.Pw.ensure(chol_panel_bytes(dtype, npad)), "alloc panel");
+        HIPCHK(ws.P16.ensure(std::max<size_t>(chol_panel16_bytes(dtype, npad), 64)), "alloc panel16");
+        HIPCHK(hipMemsetAsync(flags + 1, 0, 4, st), "hipMemsetAsync");
+        void *Fm = A;
+        if (dtype != GBEM_F64) {
+            HIPCHK(ws.F.ensure((size_t)npad * npad * es), "alloc F");
+            HIPCHK(ws.s.ensure((size_t)npad * 8), "alloc s");
+            HIPCHK(launch_jacobi_scale(A, lda, (int)npad, ws.s.as<double>(), st), "jacobi");
+            HIPCHK(launch_scale_convert(A, lda, ws.s.as<double>(), (int)npad, ws.F.as<float>(), npad, st),
+                   "scale_convert");
+            Fm = ws.F.p;
+        }
+        HIPCHK(chol_factor(dtype, npad, Fm, lda, ws.Winv.p, ws.Pw.p, ws.P16.p, flags + 1, st), "cholesky");
+        int32_t info = 0;
+        HIPCHK(hipMemcpyAsync(&info, flags + 1, 4, hipMemcpyDeviceToHost, st), "D2H info");
+        HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (info != 0) {
+            if (dtype == GBEM_F64) {
+                set_error("Cholesky: non-positive pivot at row " + std::to_string(info - 1));
+                return GBEM_ENOTPD;
+            }
+            dtype = (dtype == GBEM_F32) ? GBEM_F64 : GBEM_F32;   // BF16/F16 -> F32 -> F64
+            continue;
+        }
+        HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
+        HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
+        if (dtype == GBEM_F64) {
+            HIPCHK(chol_solve(dtype, npad, A, lda, ws.Winv.p, m, X, npad, st), "solve");
+            break;
+        }
+        // mixed precision: X = S F^{-1} S B, then FP64 refinement with A
+        const double *sv = ws.s.as<double>();
+        HIPCHK(launch_scale_rows(X, npad, sv, (int)npad, m, st), "scale");
+        HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, X, npad, st), "solve");
+        HIPCHK(launch_scale_rows(X, npad, sv, (int)npad, m, st), "scale");
+        HIPCHK(ws.R.ensure((size_t)npad * m * 8), "alloc R");
+        double *R = ws.R.as<double>();
+        double *rnorm = ws.norms.as<double>();
+        bool converged = false;
+        for (iters = 0;; ++iters) {
+            HIPCHK(launch_residual(A, lda, (int)npad, X, npad, B, npad, m, R, npad, st), "residual");
+            HIPCHK(launch_col_norms(R, npad, (int)npad, m, rnorm, st), "col_norms");
+            double rn[kMaxRhs];
+            HIPCHK(hipMemcpyAsync(rn, rnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
+            HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+            resid = 0.0;
+            for (int k = 0; k < m; ++k) resid = std::max(resid, sqrt(rn[k] / bn[k]));
+            if (!(resid == resid)) break;   // NaN: give up
+            if (resid <= o.refine_tol) {
+                converged = true;
+                break;
+            }
+            if (iters >= o.max_refine) break;
+            HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
+            HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, R, npad, st), "solve");
+            HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
+            HIPCHK(launch_axpy_cols(X, npad, R, npad, (int)npad, m, st), "update");
+        }
+        if (!converged) {
+            if (rep) {
+                rep->residual = resid;
+                rep->refine_iters = iters;
+            }
+            set_error("iterative refinement stopped at residual " + std::to_string(resid) + " after " +
+                      std::to_string(iters) + " iterations");
+            return GBEM_ENOCONV;
+        }
+        break;
+    }
+    const int nchunks = (n + 1023) / 1024;
+    HIPCHK(ws.partial.ensure((size_t)nchunks * m * m * 8), "alloc partials");
+    HIPCHK(launch_charge_partials(X, npad, dcond, n, m, ws.partial.as<double>(), nchunks, st), "charges");
+    const double eps0 = 8.8541878128e-12;
+    HIPCHK(launch_charge_finish(ws.partial.as<double>(), nchunks, m, eps_r * eps0 * lu, dC, st), "charges");
+    HIPCHK(hipEventRecord(ws.ev[3], st), "hipEventRecord");
+    HIPCHK(hipEventSynchronize(ws.ev[3]), "hipEventSynchronize");
+    if (rep) {
+        float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+        (void)hipEventElapsedTime(&t01, ws.ev[0], ws.ev[1]);
+        (void)hipEventElapsedTime(&t12, ws.ev[1], ws.ev[2]);
+        (void)hipEventElapsedTime(&t23, ws.ev[2], ws.ev[3]);
+        (void)hipEventElapsedTime(&t03, ws.ev[0], ws.ev[3]);
+        rep->t_assemble_ms = t01;
+        rep->t_factor_ms = t12;
+        rep->t_solve_ms = t23;
+        rep->t_total_ms = t03;
+        rep->residual = resid;
+        rep->refine_iters = iters;
+        rep->factor_used = dtype;
+    }
+    return GBEM_OK;
+}
+
+static double asym_of(const double *C, int m)
+{
+    double mx = 0.0, d = 0.0;
+    for (int i = 0; i < m * m; ++i) mx = std::max(mx, fabs(C[i]));
+    for (int k = 0; k < m; ++k)
+        for (int l = 0; l < m; ++l) d = std::max(d, fabs(C[k * m + l] - C[l * m + k]));
+    return mx > 0 ? d / mx : 0.0;
+}
+
+}  // namespace gbem
+
+using namespace gbem;
+
+// ------------------------------------------------------------------------
+// serving loop
+// ------------------------------------------------------------------------
+struct gbem_job {
+    gbem_ctx *ctx = nullptr;
+    std::vector<double> lo, hi, C;
+    std::vector<int32_t> cond;
+    int n = 0, m = 0;
+    double eps_r = 1, lu = 1;
+    gbem_opts opts{};
+    size_t need = 0;
+    int state = 0;   // 0 queued, 1 running, 2 done
+    gbem_status status = GBEM_OK;
+    gbem_report rep{};
+    std::string err;
+    std::mutex mu;
+    std::condition_variable cv;
+};
+
+struct Worker {
+    std::thread th;
+    hipStream_t stream = nullptr;
+    Workspace ws;
+    gbem_job *job = nullptr;
+    bool busy = false;
+    size_t held = 0;   // device bytes this worker may hold while busy (set at dispatch)
+};
+
+struct gbem_ctx {
+    int device = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;
+    Workspace ws;
+    std::mutex call_mu;   // serialises the synchronous entry points
+
+    // serving state
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_work;
+    std::deque<gbem_job *> queue;
+    std::vector<Worker *> workers;
+    std::thread sched;
+    bool started = false, stopping = false;
+    size_t reserved = 0, peak = 0;
+    int64_t done = 0;
+};
+
+static constexpr int kWorkers = 4;
+
+static void worker_main(gbem_ctx *ctx, Worker *w)
+{
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        gbem_job *j;
+        {
+            std::unique_lock<std::mutex> lk(ctx->mu);
+            ctx->cv_work.wait(lk, [&] { return ctx->stopping || w->job != nullptr; });
+            if (!w->job && ctx->stopping) return;
+            j = w->job;
+        }
+        gbem_status st = GBEM_OK;
+        gbem_report rep{};
+        std::vector<double> C(j->m * j->m);
+        {
+            double *dC = nullptr;
+            hipError_t e = hipSuccess;
+            e = w->ws.lo.ensure(sizeof(double) * 3 * j->n);
+            if (e == hipSuccess) e = w->ws.hi.ensure(sizeof(double) * 3 * j->n);
+            if (e == hipSuccess) e = w->ws.cond.ensure(sizeof(int32_t) * j->n);
+            if (e == hipSuccess) e = w->ws.C.ensure(sizeof(double) * j->m * j->m);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(w->ws.lo.p, j->lo.data(), sizeof(double) * 3 * j->n, hipMemcpyHostToDevice, w->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(w->ws.hi.p, j->hi.data(), sizeof(double) * 3 * j->n, hipMemcpyHostToDevice, w->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(w->ws.cond.p, j->cond.data(), sizeof(int32_t) * j->n, hipMemcpyHostToDevice,
+                                   w->stream);
+            if (e != hipSuccess) {
+                st = dev_fail(e, "serving: upload");
+            } else {
+                dC = w->ws.C.as<double>();
+                st = run_pipeline(w->ws, w->stream, j->n, j->m, w->ws.lo.as<double>(), w->ws.hi.as<double>(),
+                                  w->ws.cond.as<int32_t>(), j->eps_r, j->lu, j->opts, dC, &rep, Stop::kFull);
+                if (st == GBEM_OK) {
+                    e = hipMemcpyAsync(C.data(), dC, sizeof(double) * j->m * j->m, hipMemcpyDeviceToHost, w->stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(w->stream);
+                    if (e != hipSuccess) st = dev_fail(e, "serving: download");
+                }
+            }
+        }
+        if (st == GBEM_OK) rep.asym = asym_of(C.data(), j->m);
+        {
+            std::lock_guard<std::mutex> lk(j->mu);
+            j->status = st;
+            j->rep = rep;
+            j->C.swap(C);
+            if (st != GBEM_OK) j->err = gbem_last_error();
+            j->state = 2;
+        }
+        j->cv.notify_all();
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            w->job = nullptr;
+            w->busy = false;
+            ctx->reserved -= j->need;
+            ctx->done += 1;
+        }
+        ctx->cv_sched.notify_all();
+    }
+}
+
+// Admission: the device memory held by all worker workspaces never exceeds
+// the budget.  A queued job goes to an idle worker when the worker's
+// workspace, grown to the job's footprint, still fits; idle workspaces are
+// released to make room.  Jobs that fit may pass a larger job at the head of
+// the queue for up to one second.
+static void sched_main(gbem_ctx *ctx)
+{
+    (void)hipSetDevice(ctx->device);
+    auto head_since = std::chrono::steady_clock::now();
+    gbem_job *head_seen = nullptr;
+    std::unique_lock<std::mutex> lk(ctx->mu);
+    for (;;) {
+        if (ctx->stopping && ctx->queue.empty()) break;
+        bool dispatched = false;
+        if (!ctx->queue.empty()) {
+            if (ctx->queue.front() != head_seen) {
+                head_seen = ctx->queue.front();
+                head_since = std::chrono::steady_clock::now();
+            }
+            const bool head_starving = std::chrono::steady_clock::now() - head_since > std::chrono::seconds(1);
+            for (size_t qi = 0; qi < ctx->queue.size() && !dispatched; ++qi) {
+                if (qi > 0 && head_starving) break;
+                gbem_job *j = ctx->queue[qi];
+                Worker *w = nullptr;
+                for (Worker *c : ctx->workers)
+                    if (!c->busy) {
+                        w = c;
+                        break;
+                    }
+                if (!w) break;
+                // idle workspaces are only touched by this thread; busy ones
+                // are bounded by what was recorded when they were dispatched
+                auto held_by_others = [&](bool count_idle) {
+                    size_t t = 0;
+                    for (Worker *c : ctx->workers)
+                        if (c != w) t += c->busy ? c->held : (count_idle ? c->ws.bytes() : 0);
+                    return t;
+                };
+                size_t held_others = held_by_others(true);
+                size_t mine = std::max(w->ws.bytes(), j->need);
+                if (held_others + mine > ctx->budget) {
+                    for (Worker *c : ctx->workers)
+                        if (!c->busy && c->ws.bytes() > 0) c->ws.release_all();
+                    held_others = held_by_others(false);
+                    mine = j->need;
+                }
+                if (held_others + mine <= ctx->budget) {
+                    ctx->queue.erase(ctx->queue.begin() + qi);
+                    {
+                        std::lock_guard<std::mutex> jl(j->mu);
+                        j->state = 1;
+                    }
+                    w->busy = true;
+                    w->job = j;
+                    w->held = mine;
+                    ctx->reserved += j->need;
+                    ctx->peak = std::max(ctx->peak, held_others + mine);
+                    dispatched = true;
+                }
+            }
+        }
+        if (dispatched) {
+            ctx->cv_work.notify_all();
+            continue;
+        }
+        ctx->cv_sched.wait_for(lk, std::chrono::milliseconds(50));
+    }
+}
+
+static void start_server(gbem_ctx *ctx)
+{
+    if (ctx->started) return;
+    for (int i = 0; i < kWorkers; ++i) {
+        Worker *w = new Worker();
+        (void)hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+        ctx->workers.push_back(w);
+    }
+    for (Worker *w : ctx->workers) w->th = std::thread(worker_main, ctx, w);
+    ctx->sched = std::thread(sched_main, ctx);
+    ctx->started = true;
+}
+
+// ------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------
+extern "C" const char *gbem_version(void) { return "gbem-mi355x 0.1 (gfx950)"; }
+
+extern "C" const char *gbem_status_str(gbem_status s)
+{
+    switch (s) {
+    case GBEM_OK: return "ok";
+    case GBEM_EINVAL: return "invalid argument";
+    case GBEM_ENOMEM: return "out of device memory or HBM budget";
+    case GBEM_EDEVICE: return "HIP device error";
+    case GBEM_ENOTPD: return "matrix not positive definite";
+    case GBEM_ENOCONV: return "iterative refinement did not converge";
+    case GBEM_EBUSY: return "busy";
+    case GBEM_ETIMEOUT: return "timed out";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *gbem_last_error(void) { return t_err.c_str(); }
+
+extern "C" void gbem_default_opts(gbem_opts *o)
+{
+    if (!o) return;
+    o->far_order = 3;
+    o->near_eta = 2.0;
+    o->far_dtype = GBEM_F64;
+    o->factor_dtype = GBEM_F64;
+    o->refine_tol = 1e-6;
+    o->max_refine = 30;
+}
+
+extern "C" gbem_status gbem_create(int device, size_t budget, gbem_ctx **out)
+{
+    if (!out) {
+        set_error("gbem_create: out is NULL");
+        return GBEM_EINVAL;
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || device < 0 || device >= count) {
+        set_error("gbem_create: no such HIP device");
+        return GBEM_EDEVICE;
+    }
+    HIPCHK(hipSetDevice(device), "hipSetDevice");
+    gbem_ctx *c = new gbem_ctx();
+    c->device = device;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        (void)hipMemGetInfo(&fr, &tot);
+        budget = (size_t)(0.9 * (double)fr);
+    }
+    c->budget = budget;
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return dev_fail(e, "hipStreamCreate");
+    }
+    *out = c;
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_destroy(gbem_ctx *ctx)
+{
+    if (!ctx) return GBEM_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->started) {
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->stopping = true;
+        }
+        ctx->cv_sched.notify_all();
+        ctx->sched.join();
+        ctx->cv_work.notify_all();
+        for (Worker *w : ctx->workers) {
+            w->th.join();
+            (void)hipStreamDestroy(w->stream);
+            delete w;
+        }
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return GBEM_OK;
+}
+
+static gbem_status upload_mesh(gbem_ctx *ctx, const gbem_mesh *mesh)
+{
+    Workspace &ws = ctx->ws;
+    const int n = mesh->n_panels;
+    HIPCHK(ws.lo.ensure(sizeof(double) * 3 * n), "alloc mesh");
+    HIPCHK(ws.hi.ensure(sizeof(double) * 3 * n), "alloc mesh");
+    HIPCHK(ws.cond.ensure(sizeof(int32_t) * n), "alloc mesh");
+    HIPCHK(hipMemcpyAsync(ws.lo.p, mesh->lo, sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream), "H2D");
+    HIPCHK(hipMemcpyAsync(ws.hi.p, mesh->hi, sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream), "H2D");
+    HIPCHK(hipMemcpyAsync(ws.cond.p, mesh->conductor, sizeof(int32_t) * n, hipMemcpyHostToDevice, ctx->stream),
+           "H2D");
+    return GBEM_OK;
+}
+
+static gbem_status check_args(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, gbem_opts &o)
+{
+    std::string why;
+    if (!ctx) {
+        set_error("context is NULL");
+        return GBEM_EINVAL;
+    }
+    if (!mesh_header_ok(mesh, why)) {
+        set_error(why);
+        return GBEM_EINVAL;
+    }
+    if (opts) o = *opts; else gbem_default_opts(&o);
+    if (!opts_ok(o, why)) {
+        set_error(why);
+        return GBEM_EINVAL;
+    }
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_extract(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                    double *C_out, gbem_report *rep)
+{
+    gbem_opts o;
+    gbem_status s = check_args(ctx, mesh, opts, o);
+    if (s != GBEM_OK) return s;
+    if (!C_out) {
+        set_error("C_out is NULL");
+        return GBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    if ((s = upload_mesh(ctx, mesh)) != GBEM_OK) return s;
+    const int m = mesh->n_conductors;
+    HIPCHK(ctx->ws.C.ensure(sizeof(double) * m * m), "alloc C");
+    gbem_report r{};
+    s = run_pipeline(ctx->ws, ctx->stream, mesh->n_panels, m, ctx->ws.lo.as<double>(), ctx->ws.hi.as<double>(),
+                     ctx->ws.cond.as<int32_t>(), mesh->eps_r, mesh->length_unit_m, o, ctx->ws.C.as<double>(),
+                     &r, Stop::kFull);
+    if (s != GBEM_OK) {
+        if (rep) *rep = r;
+        return s;
+    }
+    std::vector<double> C(m * m);
+    HIPCHK(hipMemcpyAsync(C.data(), ctx->ws.C.p, sizeof(double) * m * m, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    memcpy(C_out, C.data(), sizeof(double) * m * m);
+    r.asym = asym_of(C.data(), m);
+    if (rep) *rep = r;
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_extract_device(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                           double *C_out_device, void *stream, gbem_report *rep)
+{
+    gbem_opts o;
+    gbem_status s = check_args(ctx, mesh, opts, o);
+    if (s != GBEM_OK) return s;
+    if (!C_out_device) {
+        set_error("C_out_device is NULL");
+        return GBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
+    gbem_report r{};
+    s = run_pipeline(ctx->ws, st, mesh->n_panels, mesh->n_conductors, mesh->lo, mesh->hi, mesh->conductor,
+                     mesh->eps_r, mesh->length_unit_m, o, C_out_device, &r, Stop::kFull);
+    if (s == GBEM_OK && rep) {
+        const int m = mesh->n_conductors;
+        std::vector<double> C(m * m);
+        HIPCHK(hipMemcpyAsync(C.data(), C_out_device, sizeof(double) * m * m, hipMemcpyDeviceToHost, st), "D2H");
+        HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+        r.asym = asym_of(C.data(), m);
+    }
+    if (rep) *rep = r;
+    return s;
+}
+
+extern "C" gbem_status gbem_submit(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, gbem_job **out)
+{
+    gbem_opts o;
+    gbem_status s = check_args(ctx, mesh, opts, o);
+    if (s != GBEM_OK) return s;
+    if (!out) {
+        set_error("out is NULL");
+        return GBEM_EINVAL;
+    }
+    gbem_job *j = new gbem_job();
+    j->ctx = ctx;
+    j->n = mesh->n_panels;
+    j->m = mesh->n_conductors;
+    j->lo.assign(mesh->lo, mesh->lo + 3 * (size_t)j->n);
+    j->hi.assign(mesh->hi, mesh->hi + 3 * (size_t)j->n);
+    j->cond.assign(mesh->conductor, mesh->conductor + j->n);
+    j->eps_r = mesh->eps_r;
+    j->lu = mesh->length_unit_m;
+    j->opts = o;
+    j->need = footprint(j->n, j->m, o.factor_dtype);
+    if (j->need > ctx->budget) {
+        delete j;
+        set_error("job footprint exceeds the HBM budget of the context");
+        return GBEM_ENOMEM;
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        start_server(ctx);
+        ctx->queue.push_back(j);
+    }
+    ctx->cv_sched.notify_all();
+    *out = j;
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_poll(gbem_job *j)
+{
+    if (!j) return GBEM_EINVAL;
+    std::lock_guard<std::mutex> lk(j->mu);
+    if (j->state != 2) return GBEM_EBUSY;
+    return j->status;
+}
+
+extern "C" gbem_status gbem_wait(gbem_job *j, double timeout_s, double *C_out, gbem_report *rep)
+{
+    if (!j) return GBEM_EINVAL;
+    std::unique_lock<std::mutex> lk(j->mu);
+    if (timeout_s < 0) {
+        j->cv.wait(lk, [&] { return j->state == 2; });
+    } else if (!j->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return j->state == 2; })) {
+        set_error("gbem_wait: timed out");
+        return GBEM_ETIMEOUT;
+    }
+    if (j->status != GBEM_OK) {
+        set_error(j->err);
+        if (rep) *rep = j->rep;
+        return j->status;
+    }
+    if (C_out) memcpy(C_out, j->C.data(), sizeof(double) * j->m * j->m);
+    if (rep) *rep = j->rep;
+    return GBEM_OK;
+}
+
+extern "C" void gbem_job_free(gbem_job *j)
+{
+    if (!j) return;
+    {
+        std::unique_lock<std::mutex> lk(j->mu);
+        j->cv.wait(lk, [&] { return j->state == 2; });
+    }
+    delete j;
+}
+
+extern "C" gbem_status gbem_server_stats(gbem_ctx *ctx, int64_t *jobs_done, size_t *peak_bytes)
+{
+    if (!ctx) return GBEM_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (jobs_done) *jobs_done = ctx->done;
+    if (peak_bytes) *peak_bytes = ctx->peak;
+    return GBEM_OK;
+}
+
+// ---- stage entry points ----------------------------------------------------
+extern "C" gbem_status gbem_near_list(gbem_ctx *ctx, const gbem_mesh *mesh, double near_eta, int64_t *row_ptr,
+                                      int32_t *col, int64_t col_capacity, int64_t *nnz)
+{
+    gbem_opts o;
+    gbem_default_opts(&o);
+    o.near_eta = near_eta;
+    gbem_status s = check_args(ctx, mesh, &o, o);
+    if (s != GBEM_OK) return s;
+    if (!row_ptr || !nnz) {
+        set_error("row_ptr and nnz are required");
+        return GBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    if ((s = upload_mesh(ctx, mesh)) != GBEM_OK) return s;
+    Workspace &ws = ctx->ws;
+    const int n = mesh->n_panels;
+    HIPCHK(ws.cnt.ensure(sizeof(int64_t) * n), "alloc");
+    HIPCHK(ws.rowptr.ensure(sizeof(int64_t) * (n + 1)), "alloc");
+    const double eta2 = near_eta * near_eta;
+    HIPCHK(launch_near_count(ws.lo.as<double>(), ws.hi.as<double>(), n, eta2, ws.cnt.as<int64_t>(), ctx->stream), "near_count");
+    HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), ctx->stream), "scan");
+    HIPCHK(hipMemcpyAsync(row_ptr, ws.rowptr.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    *nnz = row_ptr[n];
+    if (!col) return GBEM_OK;
+    if (col_capacity < *nnz) {
+        set_error("col_capacity is smaller than the number of near pairs");
+        return GBEM_EINVAL;
+    }
+    HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(*nnz, 1)), "alloc");
+    HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(*nnz, 1)), "alloc");
+    HIPCHK(launch_near_fill(ws.lo.as<double>(), ws.hi.as<double>(), n, eta2, ws.rowptr.as<int64_t>(),
+                            ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), ctx->stream), "near_fill");
+    HIPCHK(hipMemcpyAsync(col, ws.ncol.p, sizeof(int32_t) * *nnz, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    return GBEM_OK;
+}
+
+static gbem_status assemble_common(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, gbem_report *r)
+{
+    gbem_opts o;
+    gbem_status s = check_args(ctx, mesh, opts, o);
+    if (s != GBEM_OK) return s;
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    if ((s = upload_mesh(ctx, mesh)) != GBEM_OK) return s;
+    return run_pipeline(ctx->ws, ctx->stream, mesh->n_panels, mesh->n_conductors, ctx->ws.lo.as<double>(),
+                        ctx->ws.hi.as<double>(), ctx->ws.cond.as<int32_t>(), mesh->eps_r, mesh->length_unit_m, o,
+                        nullptr, r, Stop::kAssembled);
+}
+
+extern "C" gbem_status gbem_assemble(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, double *A_out)
+{
+    if (!A_out) {
+        set_error("A_out is NULL");
+        return GBEM_EINVAL;
+    }
+    if (!ctx) return GBEM_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    gbem_report r{};
+    gbem_status s = assemble_common(ctx, mesh, opts, &r);
+    if (s != GBEM_OK) return s;
+    const int n = mesh->n_panels;
+    const int64_t npad = round_up(n, kPad);
+    // A is symmetric: its column-major n x n block read row by row is the row-major matrix
+    HIPCHK(hipMemcpy2DAsync(A_out, sizeof(double) * n, ctx->ws.A.p, sizeof(double) * npad, sizeof(double) * n, n,
+                            hipMemcpyDeviceToHost, ctx->stream), "D2H A");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_assemble_sample(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, int64_t m,
+                                            const int32_t *ii, const int32_t *jj, double *out)
+{
+    if (!ctx || m < 0 || (m > 0 && (!ii || !jj || !out))) {
+        set_error("gbem_assemble_sample: bad arguments");
+        return GBEM_EINVAL;
+    }
+    const int n = mesh ? mesh->n_panels : 0;
+    for (int64_t k = 0; k < m; ++k)
+        if (ii[k] < 0 || ii[k] >= n || jj[k] < 0 || jj[k] >= n) {
+            set_error("gbem_assemble_sample: index out of range");
+            return GBEM_EINVAL;
+        }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    gbem_report r{};
+    gbem_status s = assemble_common(ctx, mesh, opts, &r);
+    if (s != GBEM_OK || m == 0) return s;
+    Workspace &ws = ctx->ws;
+    DevBuf di, dj, dout;
+    HIPCHK(di.ensure(sizeof(int32_t) * m), "alloc");
+    HIPCHK(dj.ensure(sizeof(int32_t) * m), "alloc");
+    HIPCHK(dout.ensure(sizeof(double) * m), "alloc");
+    HIPCHK(hipMemcpyAsync(di.p, ii, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream), "H2D");
+    HIPCHK(hipMemcpyAsync(dj.p, jj, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream), "H2D");
+    HIPCHK(launch_gather(ws.A.as<double>(), round_up(n, kPad), di.as<int32_t>(), dj.as<int32_t>(), m,
+                         dout.as<double>(), ctx->stream), "gather");
+    HIPCHK(hipMemcpyAsync(out, dout.p, sizeof(double) * m, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    di.release();
+    dj.release();
+    dout.release();
+    return GBEM_OK;
+}
+
+static gbem_status chol_common(gbem_ctx *ctx, int32_t n, int32_t dtype, void *A, int64_t lda, int32_t *info,
+                               void *stream, int32_t nrhs, void *Bm, int64_t ldb, bool solve)
+{
+    if (!ctx || n <= 0 || !A || lda < n || dtype < GBEM_F64 || dtype > GBEM_BF16 ||
+        (solve && (!Bm || nrhs <= 0 || nrhs > kMaxRhs || ldb < n))) {
+        set_error("cholesky: bad arguments");
+        return GBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
+    Workspace &ws = ctx->ws;
+    const int64_t npad = round_up(n, kPad);
+    const size_t es = dtype == GBEM_F64 ? 8 : 4;
+    DevBuf &Ap = dtype == GBEM_F64 ? ws.A : ws.F;
+    HIPCHK(Ap.ensure((size_t)npad * npad * es), "alloc");
+    HIPCHK(ws.Winv.ensure(chol_winv_bytes(dtype, npad)), "alloc");
+    HIPCHK(ws.Pw.ensure(chol_panel_bytes(dtype, npad)), "alloc");
+    HIPCHK(ws.P16.ensure(std::max<size_t>(chol_panel16_bytes(dtype, npad), 64)), "alloc");
+    HIPCHK(ws.flags.ensure(64), "alloc");
+    HIPCHK(hipMemcpy2DAsync(Ap.p, es * npad, A, es * lda, es * n, n, hipMemcpyDeviceToDevice, st), "copy in");
+    HIPCHK(launch_identity_pad(Ap.p, npad, n, (int)npad, dtype == GBEM_F64, st), "pad");
+    if (!solve) {
+        HIPCHK(hipMemsetAsync(ws.flags.p, 0, 64, st), "memset");
+        HIPCHK(chol_factor(dtype, npad, Ap.p, npad, ws.Winv.p, ws.Pw.p, ws.P16.p, ws.flags.as<int32_t>() + 1, st),
+               "cholesky");
+        int32_t inf = 0;
+        HIPCHK(hipMemcpyAsync(&inf, ws.flags.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost, st), "D2H");
+        HIPCHK(hipStreamSynchronize(st), "sync");
+        if (info) *info = inf;
+        if (inf > n) inf = 0;   // a pivot in the identity padding cannot fail
+        if (inf != 0) {
+            set_error("Cholesky: non-positive pivot at row " + std::to_string(inf - 1));
+            return GBEM_ENOTPD;
+        }
+        HIPCHK(hipMemcpy2DAsync(A, es * lda, Ap.p, es * npad, es * n, n, hipMemcpyDeviceToDevice, st), "copy out");
+        HIPCHK(hipStreamSynchronize(st), "sync");
+        return GBEM_OK;
+    }
+    HIPCHK(chol_diag_inverses(dtype, npad, Ap.p, npad, ws.Winv.p, st), "diag inverses");
+    HIPCHK(ws.X.ensure((size_t)npad * nrhs * 8), "alloc");
+    HIPCHK(hipMemsetAsync(ws.X.p, 0, (size_t)npad * nrhs * 8, st), "memset");
+    HIPCHK(hipMemcpy2DAsync(ws.X.p, 8 * npad, Bm, 8 * ldb, 8 * n, nrhs, hipMemcpyDeviceToDevice, st), "copy B");
+    HIPCHK(chol_solve(dtype, npad, Ap.p, npad, ws.Winv.p, nrhs, ws.X.as<double>(), npad, st), "solve");
+    HIPCHK(hipMemcpy2DAsync(Bm, 8 * ldb, ws.X.p, 8 * npad, 8 * n, nrhs, hipMemcpyDeviceToDevice, st), "copy out");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_cholesky_device(gbem_ctx *ctx, int32_t n, int32_t dtype, void *A, int64_t lda,
+                                            int32_t *info, void *stream)
+{
+    return chol_common(ctx, n, dtype, A, lda, info, stream, 0, nullptr, 0, false);
+}
+
+extern "C" gbem_status gbem_cholesky_solve_device(gbem_ctx *ctx, int32_t n, int32_t dtype, const void *L,
+                                                  int64_t lda, int32_t nrhs, void *B, int64_t ldb, void *stream)
+{
+    return chol_common(ctx, n, dtype, const_cast<void *>(L), lda, nullptr, stream, nrhs, B, ldb, true);
+}

@@ -1,0 +1,117 @@
+// Internal declarations shared by the HIP translation units of libgbem.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "gbem.h"
+
+namespace gbem {
+
+// Tile edge of the far-field assembly kernel and the padding unit of every
+// device matrix: the order of A is padded to a multiple of kPad with an
+// identity block, so the factorisation and solves need no edge cases.
+constexpr int kFarTile = 64;
+constexpr int kNB = 128;          // Cholesky block (diagonal block lives in LDS)
+constexpr int kPad = 128;         // padding of the matrix order
+constexpr int kMaxOrder = 8;      // largest Gauss order of the far rule
+constexpr int kMaxRhs = 64;       // right-hand sides handled per solve pass
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Panel record in HBM: one 64-byte line per panel.
+//   c[3]  centre, h1/h2 half-extents along the two in-plane axes (ascending
+//   axis order), nrm normal axis, area, diam2 = |hi-lo|^2.
+struct __attribute__((aligned(64))) Panel {
+    double c[3];
+    double h1, h2;
+    double area;
+    double diam2;
+    int32_t nrm;
+    int32_t cond;
+};
+static_assert(sizeof(Panel) == 64, "panel record must be one 64-byte line");
+
+// Gauss-Legendre rule on [-1,1] passed by value to the far kernel.
+// ww[a * p + b] = w_a w_b with w the Gauss weights halved (each direction
+// sums to 1); xf/wwf are the same values rounded to FP32.
+struct GaussRule {
+    double x[kMaxOrder];
+    double w[kMaxOrder];
+    double ww[kMaxOrder * kMaxOrder];
+    float xf[kMaxOrder];
+    float wwf[kMaxOrder * kMaxOrder];
+};
+
+// Gauss rule of the semi-analytic near-pair route (halved weights).
+constexpr int kNearOrder = 10;
+struct NearRule {
+    double x[kNearOrder];
+    double w[kNearOrder];
+};
+
+// ---- host helpers --------------------------------------------------------
+void set_error(const std::string &msg);
+// p-point Gauss-Legendre nodes (ascending) and halved weights on [-1, 1]
+void gauss_legendre(int p, double *x, double *w_half);
+void gauss_legendre_rule(int p, GaussRule *r);
+
+// ---- kernel launchers (each returns hipSuccess or the launch error) ------
+// panels.hip
+hipError_t launch_build_panels(const double *lo, const double *hi, const int32_t *cond, int n,
+                               int n_cond, Panel *pan, int32_t *bad, hipStream_t s);
+hipError_t launch_rhs(const int32_t *cond, int n, int npad, int m, double *B, int64_t ldb,
+                      hipStream_t s);
+hipError_t launch_charge_partials(const double *X, int64_t ldx, const int32_t *cond, int n, int m,
+                                  double *partial, int nchunks, hipStream_t s);
+hipError_t launch_charge_finish(const double *partial, int nchunks, int m, double scale,
+                                double *C, hipStream_t s);
+hipError_t launch_gather(const double *A, int64_t lda, const int32_t *ii, const int32_t *jj, int64_t m,
+                         double *out, hipStream_t s);
+hipError_t launch_identity_pad(void *A, int64_t lda, int n, int npad, bool f64, hipStream_t s);
+
+// near.hip (compiled with -ffp-contract=off: the near/far test is bit-exact)
+hipError_t launch_near_count(const double *lo, const double *hi, int n, double eta2,
+                             int64_t *cnt, hipStream_t s);
+hipError_t launch_exclusive_scan(const int64_t *cnt, int n, int64_t *row_ptr, hipStream_t s);
+hipError_t launch_near_fill(const double *lo, const double *hi, int n, double eta2,
+                            const int64_t *row_ptr, int32_t *row, int32_t *col, hipStream_t s);
+
+// near_eval.hip: closed-form Galerkin integrals of the near pairs
+hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
+                            const int32_t *row, const int32_t *col, int64_t nnz, double *A,
+                            int64_t lda, hipStream_t s);
+
+// far.hip
+hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule &rule,
+                      int far_dtype, double *A, int64_t lda, hipStream_t s);
+
+// chol.hip
+hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *panel,
+                       void *panel16, int32_t *info, hipStream_t s);
+hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv,
+                      int m, double *B, int64_t ldb, hipStream_t s);
+size_t chol_winv_bytes(int dtype, int64_t npad);
+size_t chol_panel_bytes(int dtype, int64_t npad);
+size_t chol_panel16_bytes(int dtype, int64_t npad);
+// W_k = inverse of the 128 x 128 diagonal blocks of an existing factor L
+hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t lda, void *Winv,
+                              hipStream_t s);
+
+// refine.hip: mixed-precision helpers
+hipError_t launch_jacobi_scale(const double *A, int64_t lda, int npad, double *s, hipStream_t st);
+hipError_t launch_scale_convert(const double *A, int64_t lda, const double *s, int npad,
+                                float *F, int64_t ldf, hipStream_t st);
+hipError_t launch_residual(const double *A, int64_t lda, int npad, const double *X, int64_t ldx,
+                           const double *B, int64_t ldb, int m, double *R, int64_t ldr,
+                           hipStream_t st);
+hipError_t launch_col_norms(const double *R, int64_t ldr, int npad, int m, double *norms,
+                            hipStream_t st);
+hipError_t launch_scale_rows(double *X, int64_t ldx, const double *s, int npad, int m,
+                             hipStream_t st);
+hipError_t launch_axpy_cols(double *X, int64_t ldx, const double *D, int64_t ldd, int npad, int m,
+                            hipStream_t st);
+
+}  // namespace gbem

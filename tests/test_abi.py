@@ -1,0 +1,83 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/gbem.h declares, and its mesher is bit-exact with
+the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gbem_inputs as gi
+import oracle
+from paper_2203_11733_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gbem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gbem_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(binding.EXPORTS) == names
+
+
+def test_status_strings_and_version():
+    lib = binding.load()
+    assert b"gfx950" in lib.gbem_version()
+    for s in range(8):
+        assert lib.gbem_status_str(s)
+    o = binding.Opts()
+    lib.gbem_default_opts(ctypes.byref(o))
+    assert (o.far_order, o.near_eta, o.far_dtype, o.factor_dtype) == (3, 2.0, 0, 0)
+
+
+@pytest.mark.parametrize("layout", [gi.two_plates(), gi.crossing_bus(), gi.three_layer_bus(),
+                                    gi.crossing_bars_in_box(), gi.random_small_layout(3)],
+                         ids=["two_plates", "crossing_bus", "three_layer_bus", "bars_in_box", "random3"])
+def test_mesher_bit_exact_vs_oracle(layout):
+    a = binding.mesh_layout(layout)
+    b = oracle.mesh_layout(layout)
+    for x, y in zip(a, b):
+        assert x.dtype == y.dtype and x.shape == y.shape
+        assert x.tobytes() == y.tobytes()
+
+
+def test_mesher_serving_layouts_bit_exact():
+    for t, lay in gi.serving_stream(n_jobs=6):
+        a = binding.mesh_layout(lay)
+        b = oracle.mesh_layout(lay)
+        assert all(x.tobytes() == y.tobytes() for x, y in zip(a, b))
+        assert 450 <= a[0].shape[0] <= 22000
+
+
+def test_mesher_rejects_bad_boxes():
+    with pytest.raises(binding.GbemError) as e:
+        binding.mesh_boxes([[0, 0, 0], [0.5, 0, 0]], [[1, 1, 1], [2, 1, 1]], [0, 1], ("uniform", 0.5))
+    assert e.value.status == binding.EINVAL
+    with pytest.raises(binding.GbemError):
+        binding.mesh_boxes([[0, 0, 0]], [[1, 0, 1]], [0], ("uniform", 0.5))   # flat box
+    with pytest.raises(binding.GbemError):
+        binding.mesh_boxes([[0, 0, 0]], [[1, 1, 1]], [0], ("uniform", -1.0))
+    # touching boxes are rejected, a box strictly inside another is accepted
+    with pytest.raises(binding.GbemError):
+        binding.mesh_boxes([[0, 0, 0], [1, 0, 0]], [[1, 1, 1], [2, 1, 1]], [0, 1], ("uniform", 0.5))
+    lo, hi, c = binding.mesh_boxes([[0, 0, 0], [-5, -5, -5]], [[1, 1, 1], [5, 5, 5]], [0, -1], ("uniform", 0.5))
+    assert lo.shape[0] == 24 + 6 * 400
+
+
+def test_context_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(binding.GbemError) as e:
+        binding.Context(0)
+    assert e.value.status == binding.EDEVICE

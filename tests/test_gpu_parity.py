@@ -1,0 +1,266 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: near-list indices bit-exact; FP64 matrix entries 5e-12 relative (the
+closed-form corner sums lose about kappa = D^4/(|I_i||I_j|) ulps, kappa up
+to ~3e3 on the graded meshes tested, times 16 terms);
+FP64 capacitances 1e-10 relative; mixed precision (FP32 far field, FP32/FP16/
+BF16 factor + FP64 refinement) 1e-3 relative.  Full-size layouts are checked
+on sampled entries the oracle evaluates one by one and on properties that
+hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gbem_inputs as gi
+import oracle
+from paper_2203_11733_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def mesh(layout):
+    return binding.mesh_layout(layout)
+
+
+ENTRY_TOL = 5e-12
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+# ---------------------------------------------------------------- Cholesky
+@pytest.mark.parametrize("n", [300, 384, 1000])
+def test_cholesky_f64_vs_lapack(ctx, n):
+    import torch
+    say(f"cholesky f64 n={n}")
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((n, n))
+    A = M @ M.T / n + np.eye(n)
+    T = torch.tensor(A, device="cuda")
+    assert ctx.cholesky_device(T, "f64") == 0
+    L = np.tril(T.cpu().numpy().T)
+    Lr = np.linalg.cholesky(A)
+    assert rel_err(L, Lr) < 1e-12
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 5e-5), ("f16", 3e-3), ("bf16", 2e-2)])
+def test_cholesky_low_precision(ctx, dtype, tol):
+    import torch
+    n = 640
+    say(f"cholesky {dtype} n={n}")
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((n, n))
+    A = M @ M.T / n + np.eye(n)
+    T = torch.tensor(A, dtype=torch.float32, device="cuda")
+    assert ctx.cholesky_device(T, dtype) == 0
+    L = np.tril(T.cpu().numpy().T.astype(np.float64))
+    assert np.linalg.norm(L @ L.T - A) / np.linalg.norm(A) < tol
+
+
+def test_cholesky_solve_vs_numpy(ctx):
+    import torch
+    n, r = 500, 7
+    say("cholesky solve")
+    rng = np.random.default_rng(11)
+    M = rng.standard_normal((n, n))
+    A = M @ M.T / n + np.eye(n)
+    L = torch.tensor(np.linalg.cholesky(A).T.copy(), device="cuda")   # column-major L
+    Bt = torch.tensor(rng.standard_normal((r, n)), device="cuda")      # column-major n x r
+    B0 = Bt.cpu().numpy().T.copy()
+    ctx.cholesky_solve_device(L.T, Bt.T, "f64")
+    X = Bt.cpu().numpy().T
+    assert rel_err(X, np.linalg.solve(A, B0)) < 1e-11
+
+
+def test_cholesky_reports_indefinite(ctx):
+    import torch
+    n = 200
+    A = np.eye(n)
+    A[150, 150] = -1.0
+    T = torch.tensor(A, device="cuda")
+    with pytest.raises(binding.GbemError) as e:
+        ctx.cholesky_device(T, "f64")
+    assert e.value.status == binding.ENOTPD
+
+
+# ---------------------------------------------------------------- near list
+@pytest.mark.parametrize("layout,eta", [(gi.two_plates(), 2.0), (gi.crossing_bars_in_box(), 2.0),
+                                        (gi.random_small_layout(3), 1.0), (gi.two_plates(), 4.0)],
+                         ids=["two_plates", "bars_in_box", "random3_eta1", "two_plates_eta4"])
+def test_near_list_bit_exact(ctx, layout, eta):
+    lo, hi, cond = mesh(layout)
+    say(f"near list {layout.name} N={lo.shape[0]} eta={eta}")
+    rp, col = ctx.near_list(lo, hi, eta)
+    rpo, colo = oracle.near_csr(lo, hi, eta)
+    assert np.array_equal(rp, rpo)
+    assert np.array_equal(col, colo)
+
+
+# ---------------------------------------------------------------- matrix
+@pytest.mark.parametrize("layout", [gi.two_plates(), gi.crossing_bars_in_box(), gi.random_small_layout(5)],
+                         ids=["two_plates", "bars_in_box", "random5"])
+def test_matrix_f64_vs_oracle(ctx, layout):
+    lo, hi, cond = mesh(layout)
+    say(f"assemble f64 {layout.name} N={lo.shape[0]}")
+    A = ctx.assemble(lo, hi, binding.make_opts(3, 2.0, "f64"))
+    Ao = oracle.assemble(lo, hi, 3, 2.0)
+    assert np.array_equal(A, A.T)
+    err = np.abs(A - Ao) / np.abs(Ao)
+    say(f"  max entry rel err {err.max():.3e}")
+    assert err.max() < ENTRY_TOL
+
+
+def test_matrix_f32_far_vs_oracle(ctx):
+    lay = gi.two_plates()
+    lo, hi, cond = mesh(lay)
+    A = ctx.assemble(lo, hi, binding.make_opts(3, 2.0, "f32"))
+    Ao = oracle.assemble(lo, hi, 3, 2.0)
+    rp, col = oracle.near_csr(lo, hi, 2.0)
+    near = np.zeros_like(A, dtype=bool)
+    for i in range(lo.shape[0]):
+        near[i, col[rp[i]:rp[i + 1]]] = True
+    near |= near.T
+    err = np.abs(A - Ao) / np.abs(Ao)
+    say(f"  far f32: near max {err[near].max():.3e} far max {err[~near].max():.3e}")
+    assert err[near].max() < ENTRY_TOL      # near entries stay FP64
+    assert err[~near].max() < 2e-6
+
+
+@pytest.mark.parametrize("p,eta", [(1, 2.0), (2, 1.0), (4, 4.0)])
+def test_matrix_orders_and_thresholds(ctx, p, eta):
+    lay = gi.random_small_layout(8)
+    lo, hi, cond = mesh(lay)
+    A = ctx.assemble(lo, hi, binding.make_opts(p, eta, "f64"))
+    Ao = oracle.assemble(lo, hi, p, eta)
+    assert (np.abs(A - Ao) / np.abs(Ao)).max() < ENTRY_TOL
+
+
+# ---------------------------------------------------------------- capacitance
+def test_capacitance_f64_vs_oracle_two_plates(ctx):
+    lay = gi.two_plates()
+    lo, hi, cond = mesh(lay)
+    say("extract f64 two_plates")
+    C, rep = ctx.extract(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m, binding.make_opts())
+    Co = oracle.extract_panels(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m, 3, 2.0)
+    say(f"  C={C.tolist()} rel {rel_err(C, Co):.3e} report {rep}")
+    assert rel_err(C, Co) < 1e-10
+    assert rep["asym"] < 1e-12
+
+
+def test_capacitance_f64_vs_oracle_bars_in_box(ctx):
+    lay = gi.crossing_bars_in_box()
+    lo, hi, cond = mesh(lay)
+    C, rep = ctx.extract(lo, hi, cond, 2, 1.0, 1e-6, binding.make_opts())
+    Co = oracle.extract_panels(lo, hi, cond, 2, 1.0, 1e-6, 3, 2.0)
+    say(f"  bars in box C(aF)={(C * 1e18).tolist()} rel {rel_err(C, Co):.3e}")
+    assert rel_err(C, Co) < 1e-10
+
+
+@pytest.mark.parametrize("factor", ["f32", "f16", "bf16"])
+def test_capacitance_mixed_vs_oracle(ctx, factor):
+    lay = gi.two_plates()
+    lo, hi, cond = mesh(lay)
+    o = binding.make_opts(3, 2.0, "f32", factor, 1e-8, 40)
+    C, rep = ctx.extract(lo, hi, cond, 2, lay.eps_r, lay.length_unit_m, o)
+    Co = oracle.extract_panels(lo, hi, cond, 2, lay.eps_r, lay.length_unit_m, 3, 2.0)
+    say(f"  mixed {factor}: rel {rel_err(C, Co):.3e} iters {rep['refine_iters']} resid {rep['residual']:.2e} "
+        f"factor_used {rep['factor_used']}")
+    assert rel_err(C, Co) < 1e-3
+    assert rep["residual"] <= 1e-8
+
+
+def test_invalid_inputs(ctx):
+    lay = gi.two_plates(h=0.5)
+    lo, hi, cond = mesh(lay)
+    bad = hi.copy()
+    bad[3] = lo[3]          # panel with two zero extents
+    with pytest.raises(binding.GbemError) as e:
+        ctx.extract(lo, bad, cond, 2, 1.0, 1e-6)
+    assert e.value.status == binding.EINVAL
+    with pytest.raises(binding.GbemError):
+        ctx.extract(lo, hi, cond, 3, 1.0, 1e-6)          # conductor 2 has no panels
+    c2 = cond.copy()
+    c2[0] = 7
+    with pytest.raises(binding.GbemError):
+        ctx.extract(lo, hi, c2, 2, 1.0, 1e-6)             # conductor id out of range
+    with pytest.raises(binding.GbemError):
+        ctx.extract(lo[:0], hi[:0], cond[:0], 1, 1.0, 1e-6)   # empty mesh
+
+
+def test_single_panel_plate(ctx):
+    """One square panel: A = a_11, X = 1/a_11, C = eps l / a_11."""
+    lo = np.array([[0.0, 0.0, 0.0]])
+    hi = np.array([[1.0, 1.0, 0.0]])
+    C, rep = ctx.extract(lo, hi, np.array([0], np.int32), 1, 1.0, 1.0)
+    a11 = oracle.entry(lo[0], hi[0], lo[0], hi[0])
+    assert C[0, 0] == pytest.approx(oracle.EPS0 / a11, rel=1e-13)
+
+
+# ---------------------------------------------------------------- full sizes
+def _sample_pairs(lo, hi, eta, rng, n_rand=3000):
+    n = lo.shape[0]
+    ii = list(rng.integers(0, n, n_rand))
+    jj = list(rng.integers(0, n, n_rand))
+    # every pair of a few rows that lies within 2 diameters (near pairs and
+    # the far pairs just outside the threshold)
+    d2 = ((hi - lo) ** 2).sum(1)
+    for i in rng.integers(0, n, 20):
+        gap = np.maximum(0.0, np.maximum(lo - hi[i], lo[i] - hi))
+        sep2 = (gap ** 2).sum(1)
+        close = np.nonzero(sep2 < 4.0 * eta * eta * np.maximum(d2, d2[i]))[0]
+        ii.extend([int(i)] * len(close))
+        jj.extend(close.tolist())
+    return np.array(ii, np.int32), np.array(jj, np.int32)
+
+
+@pytest.mark.parametrize("layout", [gi.crossing_bus(), gi.three_layer_bus()], ids=["crossing_bus", "three_layer_bus"])
+def test_full_size_matrix_samples(ctx, layout):
+    lo, hi, cond = mesh(layout)
+    say(f"full-size samples {layout.name} N={lo.shape[0]}")
+    rng = np.random.default_rng(3)
+    ii, jj = _sample_pairs(lo, hi, 2.0, rng)
+    for far in ("f64", "f32"):
+        got = ctx.assemble_sample(lo, hi, ii, jj, binding.make_opts(3, 2.0, far))
+        ref = oracle.entries(lo, hi, ii, jj, 3, 2.0)
+        err = np.abs(got - ref) / np.abs(ref)
+        say(f"  far {far}: max rel err {err.max():.3e}")
+        assert err.max() < (ENTRY_TOL if far == "f64" else 2e-6)
+    sym = ctx.assemble_sample(lo, hi, jj, ii, binding.make_opts(3, 2.0, "f64"))
+    got = ctx.assemble_sample(lo, hi, ii, jj, binding.make_opts(3, 2.0, "f64"))
+    assert np.array_equal(sym, got)
+
+
+def test_full_size_crossing_bus_capacitance(ctx):
+    lay = gi.crossing_bus()
+    lo, hi, cond = mesh(lay)
+    say(f"full-size extract crossing_bus N={lo.shape[0]}")
+    C64, r64 = ctx.extract(lo, hi, cond, 10, lay.eps_r, lay.length_unit_m, binding.make_opts())
+    say(f"  f64 report {r64}")
+    Cm, rm = ctx.extract(lo, hi, cond, 10, lay.eps_r, lay.length_unit_m,
+                         binding.make_opts(3, 2.0, "f32", "bf16", 1e-6, 40))
+    say(f"  mixed report {rm}")
+    # Maxwell invariants
+    for C in (C64, Cm):
+        assert np.abs(C - C.T).max() <= 1e-6 * np.abs(C).max()
+        assert np.all(np.diag(C) > 0)
+        off = C[~np.eye(10, dtype=bool)]
+        assert np.all(off < 0)
+        assert np.all(C.sum(1) > 0)
+    err = rel_err(Cm, C64)
+    say(f"  mixed vs f64 rel err {err:.3e}")
+    assert err < 1e-3
