@@ -1,0 +1,168 @@
+"""Benchmark: whole capacitance extractions of the crossing-bus layout on one GPU.
+
+One step = one full extraction (panel table, near list, far and near
+assembly, Cholesky, solves, refinement, charge sums) of a device-resident
+mesh: 2 layers x 5 crossing wires, edge-graded panels, 21,420 panels,
+10 conductors.  Default mode: FP32 far field + BF16 trailing updates + FP64
+refinement to 1e-6; its capacitance error against the FP64 path is reported.
+
+Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K,
+--warmup W, --mode mixed|f64, --layout crossing_bus|three_layer_bus|two_plates,
+--no-cpu-baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MODES = {
+    "mixed": dict(far_dtype="f32", factor_dtype="bf16", refine_tol=1e-6, max_refine=30),
+    "mixed_f16": dict(far_dtype="f32", factor_dtype="f16", refine_tol=1e-6, max_refine=30),
+    "mixed_f32": dict(far_dtype="f32", factor_dtype="f32", refine_tol=1e-6, max_refine=30),
+    "f64": dict(far_dtype="f64", factor_dtype="f64"),
+}
+DTYPE_LABEL = {"mixed": "f32+bf16+f64", "mixed_f16": "f32+f16+f64", "mixed_f32": "f32+f64", "f64": "f64"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def layout_of(name):
+    import gbem_inputs as gi
+    return {"crossing_bus": gi.crossing_bus, "three_layer_bus": gi.three_layer_bus,
+            "two_plates": gi.two_plates}[name]()
+
+
+def cpu_baseline(lo, hi, cond, layout, p, eta):
+    """Time the CPU oracle on a bounded sample and scale to whole extractions.
+
+    Sample: all matrix entries of 1 % of the rows (chosen at random) through the
+    oracle's assembly (near pairs by the section 3.4 reductions, far pairs by
+    Gauss), plus a LAPACK Cholesky solve of an (N/2)-order matrix; the whole
+    extraction time is estimated as pairs / (pairs/s of the sample) + 8 x the
+    half-order Cholesky time."""
+    import numpy as np
+
+    import oracle
+    n = lo.shape[0]
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(n, max(1, n // 100), replace=False))
+    ii = np.concatenate([np.full(r + 1, r, np.int32) for r in rows])
+    jj = np.concatenate([np.arange(r + 1, dtype=np.int32) for r in rows])
+    t0 = time.perf_counter()
+    oracle.entries(lo, hi, ii, jj, p, eta)
+    t_asm = time.perf_counter() - t0
+    pairs_per_s = ii.shape[0] / t_asm
+    h = n // 2
+    sub_lo, sub_hi = lo[:h], hi[:h]
+    # a well-conditioned SPD matrix of the same order as half the problem
+    A = oracle.assemble(sub_lo[: min(h, 2000)], sub_hi[: min(h, 2000)], p, eta)
+    M = np.eye(h) * A[0, 0]
+    M[: A.shape[0], : A.shape[0]] = A
+    B = np.ones((h, layout.n_conductors))
+    t0 = time.perf_counter()
+    oracle.solve(M, B)
+    t_chol_half = time.perf_counter() - t0
+    total_pairs = n * (n + 1) / 2
+    t_est = total_pairs / pairs_per_s + 8.0 * t_chol_half
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": total_pairs / t_est, "unit": "panel-pair integrals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"oracle assembly of {len(rows)} random rows ({ii.shape[0]} entries, {t_asm:.1f} s) + "
+                      f"LAPACK Cholesky solve of order {h} ({t_chol_half:.1f} s) scaled by 8 to order {n}; "
+                      f"estimated {t_est:.1f} s per extraction",
+            "extractions_per_s": 1.0 / t_est}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="mixed", choices=sorted(MODES))
+    ap.add_argument("--layout", default="crossing_bus")
+    ap.add_argument("--p", type=int, default=3)
+    ap.add_argument("--eta", type=float, default=2.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2203_11733_amd import binding
+
+    lay = layout_of(args.layout)
+    lo, hi, cond = binding.mesh_layout(lay)
+    n, m = lo.shape[0], lay.n_conductors
+    log(f"bench: layout={lay.name} N={n} M={m} mode={args.mode} steps={args.steps} warmup={args.warmup}")
+    dev = torch.device("cuda:0")
+    d_lo = torch.tensor(lo, device=dev)
+    d_hi = torch.tensor(hi, device=dev)
+    d_cond = torch.tensor(cond, device=dev)
+    d_C = torch.zeros((m, m), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    ctx = binding.Context(0)
+    opts = binding.make_opts(args.p, args.eta, **MODES[args.mode])
+
+    # reference: the FP64 path (parity-tested against the CPU oracle)
+    rep64 = ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C,
+                               binding.make_opts(args.p, args.eta), stream)
+    C64 = d_C.cpu().numpy().copy()
+    log(f"bench: f64 reference done in {rep64['t_total_ms']:.1f} ms")
+
+    for _ in range(args.warmup):
+        ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C, opts, stream)
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+    lat, reps = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s0 = time.perf_counter()
+        reps.append(ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C, opts, stream))
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    C = d_C.cpu().numpy()
+    err = float(np.abs(C - C64).max() / np.abs(C64).max())
+    pairs = n * (n + 1) / 2
+    lat_ms = np.array(lat) * 1e3
+    r_last = reps[-1]
+    stage = {k: float(np.mean([r[k] for r in reps])) for k in ("t_assemble_ms", "t_factor_ms", "t_solve_ms",
+                                                              "t_total_ms")}
+    out = {
+        "metric": "panel-pair integrals/s (whole extraction)",
+        "value": pairs * args.steps / elapsed,
+        "unit": "panel-pair integrals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE_LABEL[args.mode], "data": "synthetic",
+        "config": {"workload": f"{lay.name}: N={n} panels, M={m} conductors, p={args.p}, eta={args.eta}",
+                   "mode": args.mode},
+        "extractions_per_s": args.steps / elapsed,
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "C_rel_err_vs_f64": err,
+        "refine_iters": r_last["refine_iters"], "residual": r_last["residual"],
+        "stage_ms": stage,
+        "f64_reference_ms": rep64["t_total_ms"],
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(lo, hi, cond, lay, args.p, args.eta)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -26,6 +26,7 @@ SOURCES = {
     "far.hip": [],
     "chol.hip": [],
     "refine.hip": [],
+    "solve.hip": [],
 }
 
 

@@ -94,22 +94,43 @@ struct DevBuf {
 
 struct Workspace {
     DevBuf lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, D, s, partial, C,
-        flags, norms;
+        flags, norms, sflags, rpart;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool events_ok = false;
+    SolveSync sync;
+
+    // flags of the persistent solves: zeroed once when (re)allocated; the
+    // epoch restarts with them
+    hipError_t ensure_sync(int64_t npad, hipStream_t st)
+    {
+        const size_t need = (size_t)2 * (npad / kNB) * 4 + 256;
+        if (sflags.cap < need) {
+            hipError_t e = sflags.ensure(need);
+            if (e != hipSuccess) return e;
+            e = hipMemsetAsync(sflags.p, 0, sflags.cap, st);
+            if (e != hipSuccess) return e;
+            sync.epoch = 0;
+            sync.base_f = sync.base_b = 0;
+        }
+        int32_t *f = sflags.as<int32_t>();
+        sync.err = f;                      // word 0: error flag
+        sync.flags_f = f + 64;
+        sync.flags_b = f + 64 + (sflags.cap / 4 - 64) / 2;
+        return hipSuccess;
+    }
 
     size_t bytes() const
     {
-        const DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv,
-                               &Pw, &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms};
+        const DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
+                               &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart};
         size_t t = 0;
         for (auto *b : all) t += b->cap;
         return t;
     }
     void release_all()
     {
-        DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv,
-                         &Pw, &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms};
+        DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
+                         &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart};
         for (auto *b : all) b->release();
     }
     hipError_t init_events()
@@ -269,6 +290,8 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     if (stop == Stop::kAssembled) return GBEM_OK;
 
     HIPCHK(ws.X.ensure((size_t)npad * m * 8), "alloc X");
+    HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
+    HIPCHK(hipMemsetAsync(ws.sync.err, 0, 4, st), "hipMemsetAsync");
     double *X = ws.X.as<double>();
     int dtype = o.factor_dtype;
     int iters = 0;
@@ -303,24 +326,32 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
         HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
         if (dtype == GBEM_F64) {
-            HIPCHK(chol_solve(dtype, npad, A, lda, ws.Winv.p, m, X, npad, st), "solve");
+            HIPCHK(chol_solve(dtype, npad, A, lda, ws.Winv.p, m, X, npad, ws.sync, st), "solve");
             break;
         }
         // mixed precision: X = S F^{-1} S B, then FP64 refinement with A
         const double *sv = ws.s.as<double>();
         HIPCHK(launch_scale_rows(X, npad, sv, (int)npad, m, st), "scale");
-        HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, X, npad, st), "solve");
+        HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, X, npad, ws.sync, st), "solve");
         HIPCHK(launch_scale_rows(X, npad, sv, (int)npad, m, st), "scale");
         HIPCHK(ws.R.ensure((size_t)npad * m * 8), "alloc R");
+        HIPCHK(ws.rpart.ensure((size_t)residual_splits((int)npad) * m * npad * 8), "alloc residual partials");
         double *R = ws.R.as<double>();
         double *rnorm = ws.norms.as<double>();
         bool converged = false;
         for (iters = 0;; ++iters) {
-            HIPCHK(launch_residual(A, lda, (int)npad, X, npad, B, npad, m, R, npad, st), "residual");
+            HIPCHK(launch_residual(A, lda, (int)npad, X, npad, B, npad, m, R, npad, ws.rpart.as<double>(), st),
+                   "residual");
             HIPCHK(launch_col_norms(R, npad, (int)npad, m, rnorm, st), "col_norms");
             double rn[kMaxRhs];
+            int32_t serr = 0;
             HIPCHK(hipMemcpyAsync(rn, rnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
+            HIPCHK(hipMemcpyAsync(&serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
             HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+            if (serr) {
+                set_error("triangular solve: a block wait exceeded its poll limit");
+                return GBEM_EDEVICE;
+            }
             resid = 0.0;
             for (int k = 0; k < m; ++k) resid = std::max(resid, sqrt(rn[k] / bn[k]));
             if (!(resid == resid)) break;   // NaN: give up
@@ -330,7 +361,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             }
             if (iters >= o.max_refine) break;
             HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
-            HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, R, npad, st), "solve");
+            HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, R, npad, ws.sync, st), "solve");
             HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
             HIPCHK(launch_axpy_cols(X, npad, R, npad, (int)npad, m, st), "update");
         }
@@ -351,7 +382,14 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     const double eps0 = 8.8541878128e-12;
     HIPCHK(launch_charge_finish(ws.partial.as<double>(), nchunks, m, eps_r * eps0 * lu, dC, st), "charges");
     HIPCHK(hipEventRecord(ws.ev[3], st), "hipEventRecord");
+    int32_t serr = 0;
+    HIPCHK(hipMemcpyAsync(&serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
     HIPCHK(hipEventSynchronize(ws.ev[3]), "hipEventSynchronize");
+    HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (serr) {
+        set_error("triangular solve: a block wait exceeded its poll limit");
+        return GBEM_EDEVICE;
+    }
     if (rep) {
         float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
         (void)hipEventElapsedTime(&t01, ws.ev[0], ws.ev[1]);
@@ -984,7 +1022,16 @@ static gbem_status chol_common(gbem_ctx *ctx, int32_t n, int32_t dtype, void *A,
     HIPCHK(ws.X.ensure((size_t)npad * nrhs * 8), "alloc");
     HIPCHK(hipMemsetAsync(ws.X.p, 0, (size_t)npad * nrhs * 8, st), "memset");
     HIPCHK(hipMemcpy2DAsync(ws.X.p, 8 * npad, Bm, 8 * ldb, 8 * n, nrhs, hipMemcpyDeviceToDevice, st), "copy B");
-    HIPCHK(chol_solve(dtype, npad, Ap.p, npad, ws.Winv.p, nrhs, ws.X.as<double>(), npad, st), "solve");
+    HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
+    HIPCHK(hipMemsetAsync(ws.sync.err, 0, 4, st), "memset");
+    HIPCHK(chol_solve(dtype, npad, Ap.p, npad, ws.Winv.p, nrhs, ws.X.as<double>(), npad, ws.sync, st), "solve");
+    int32_t serr = 0;
+    HIPCHK(hipMemcpyAsync(&serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    if (serr) {
+        set_error("triangular solve: a block wait exceeded its poll limit");
+        return GBEM_EDEVICE;
+    }
     HIPCHK(hipMemcpy2DAsync(Bm, 8 * ldb, ws.X.p, 8 * npad, 8 * n, nrhs, hipMemcpyDeviceToDevice, st), "copy out");
     HIPCHK(hipStreamSynchronize(st), "sync");
     return GBEM_OK;

@@ -22,74 +22,212 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------------
-// Step 1: Cholesky of the 128 x 128 diagonal block in LDS, then its inverse.
+// Step 1: Cholesky of the 128 x 128 diagonal block in LDS and its inverse.
+// The block is processed as 4 x 4 sub-blocks of 32.  For each sub-block
+// column s: one wave factors the 32 x 32 diagonal sub-block and inverts it in
+// registers (lane r owns row r, values broadcast with v_readlane, no
+// barriers); all waves then solve the sub-block rows below against it and
+// apply the rank-32 update to the rest.  The inverse of the whole block is
+// assembled in place from the sub-block inverses W_ss:
+//   W_rs = -W_rr sum_{t=s}^{r-1} L_rt W_ts   (columns s left to right).
+// Sub-block inverses wait in the unused upper triangle (transposed) and in a
+// 128-entry diagonal array until the end.
 // ------------------------------------------------------------------------
-constexpr int kLdsLd = kNB + 1;   // column stride of the LDS block
+constexpr int kLdsLd = kNB + 1;   // column stride of the LDS block: a[c * kLdsLd + r]
+constexpr int kSB = 32;
 
-// FACTOR = false: the block already holds L_kk; only W_k is computed.
+// One wave; lanes 0..31 own rows of the 32 x 32 sub-block at a (column
+// stride kLdsLd).  FACTOR: Cholesky in place; then W = L^{-1} is written to
+// the strictly upper part (a[r * ld + c] = W[r][c] for c < r) and dW.
+// Value of v in lane `src` for the whole wave (v_readlane: no LDS round trip).
+__device__ __forceinline__ float lane_bcast(float v, int src)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double lane_bcast(double v, int src)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <typename T, bool FACTOR>
-__global__ __launch_bounds__(1024) void diag_kernel(T *__restrict__ A, int64_t lda,
-                                                    T *__restrict__ W, int32_t *__restrict__ info,
-                                                    int k0)
+__device__ void chol_inv32(T *a, T *dW, int32_t *info, int grow)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 31;
+    T v[kSB], w[kSB];
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kSB; ++c) v[c] = (c <= r) ? a[c * kLdsLd + r] : T(0);
+    if (FACTOR) {
+#pragma clang loop unroll(full)
+        for (int j = 0; j < kSB; ++j) {
+            T piv = lane_bcast(v[j], j);
+            if (!(piv > T(0))) {
+                if (lane == 0 && *info == 0) *info = grow + j + 1;
+                piv = T(1);
+            }
+            const T d = sqrt(piv);
+            if (r == j) v[j] = d;
+            else if (r > j) v[j] = v[j] / d;
+            const T lj = v[j];
+#pragma clang loop unroll(full)
+            for (int c = 0; c < kSB; ++c) {
+                if (c <= j) continue;
+                const T lc = lane_bcast(lj, c);
+                if (r >= c) v[c] -= lj * lc;
+            }
+        }
+        if (lane < kSB) {
+#pragma clang loop unroll(full)
+            for (int c = 0; c < kSB; ++c)
+                if (c <= r) a[c * kLdsLd + r] = v[c];
+        }
+    }
+    // W = L^{-1}: rows of the identity eliminated top to bottom
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kSB; ++c) w[c] = (c == r) ? T(1) : T(0);
+#pragma clang loop unroll(full)
+    for (int j = 0; j < kSB; ++j) {
+        const T ljj = lane_bcast(v[j], j);
+#pragma clang loop unroll(full)
+        for (int c = 0; c < kSB; ++c) {
+            if (c > j) continue;
+            if (r == j) w[c] = w[c] / ljj;
+            const T wjc = lane_bcast(w[c], j);
+            if (r > j) w[c] -= v[j] * wjc;
+        }
+    }
+    T wd = T(0);   // w[r] without a dynamic index (keeps w in registers)
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kSB; ++c)
+        if (c == r) wd = w[c];
+    if (lane < kSB) {
+#pragma clang loop unroll(full)
+        for (int c = 0; c < kSB; ++c)
+            if (c < r) a[r * kLdsLd + c] = w[c];
+        dW[r] = wd;
+    }
+}
+
+// W_ss[c][t] for the sub-block inverse stored by chol_inv32 (t <= c)
+template <typename T>
+__device__ __forceinline__ T wsub(const T *a, const T *dW, int s0, int c, int t)
+{
+    return t == c ? dW[s0 + c] : a[(s0 + c) * kLdsLd + (s0 + t)];
+}
+
+template <typename T, bool FACTOR>
+__global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t lda, T *__restrict__ W,
+                                                   int32_t *__restrict__ info, int k0)
 {
     extern __shared__ unsigned char smem_raw[];
-    T *a = reinterpret_cast<T *>(smem_raw);           // a[c * kLdsLd + r]
-    T *x = a + kNB * kLdsLd;                           // 128-entry temporary
-    const int tid = threadIdx.x;
+    T *a = reinterpret_cast<T *>(smem_raw);   // a[c * kLdsLd + r]
+    T *dW = a + kNB * kLdsLd;                 // 128 diagonal entries of the sub-block inverses
+    T *tmp = dW + kNB;                        // 32 x 33 scratch
+    const int tid = threadIdx.x, wave = tid >> 6;
 
-    for (int idx = tid; idx < kNB * kNB; idx += 1024) {
-        int r = idx % kNB, c = idx / kNB;
-        a[c * kLdsLd + r] = (c <= r) ? A[r + c * lda] : T(0);
+    for (int idx = tid; idx < kNB * kNB; idx += 256) {
+        const int r = idx % kNB, c = idx / kNB;
+        a[c * kLdsLd + r] = (c <= r) ? A[r + (int64_t)c * lda] : T(0);
     }
     __syncthreads();
 
-    // unblocked right-looking Cholesky
-    for (int j = 0; FACTOR && j < kNB; ++j) {
-        if (tid == 0) {
-            T d = a[j * kLdsLd + j];
-            if (!(d > T(0))) {
-                if (*info == 0) *info = k0 + j + 1;
-                d = T(1);
+    for (int s = 0; s < kNB / kSB; ++s) {
+        const int s0 = s * kSB;
+        if (wave == 0) chol_inv32<T, FACTOR>(a + s0 * kLdsLd + s0, dW + s0, info, k0 + s0);
+        __syncthreads();
+        if (!FACTOR) continue;
+        const int r0 = s0 + kSB, nr = kNB - r0;
+        if (nr == 0) break;
+        // rows below: X[r][c] = sum_{t<=c} A[r][s0+t] W_ss[c][t]
+        constexpr int kMaxOut = (kNB - kSB) * kSB / 256;   // 12
+        T x[kMaxOut];
+#pragma unroll
+        for (int q = 0; q < kMaxOut; ++q) {
+            const int idx = tid + 256 * q;
+            x[q] = T(0);
+            if (idx < nr * kSB) {
+                const int r = r0 + idx % nr, c = idx / nr;
+                T acc = T(0);
+                for (int t = 0; t <= c; ++t) acc += a[(s0 + t) * kLdsLd + r] * wsub(a, dW, s0, c, t);
+                x[q] = acc;
             }
-            a[j * kLdsLd + j] = sqrt(d);
         }
         __syncthreads();
-        const T inv = T(1) / a[j * kLdsLd + j];
-        for (int r = j + 1 + tid; r < kNB; r += 1024) a[j * kLdsLd + r] *= inv;
+#pragma unroll
+        for (int q = 0; q < kMaxOut; ++q) {
+            const int idx = tid + 256 * q;
+            if (idx < nr * kSB) {
+                const int r = r0 + idx % nr, c = idx / nr;
+                a[(s0 + c) * kLdsLd + r] = x[q];
+            }
+        }
         __syncthreads();
-        const int cnt = kNB - 1 - j;
-        for (int e = tid; e < cnt * cnt; e += 1024) {
-            int r = j + 1 + e % cnt, c = j + 1 + e / cnt;
-            if (c <= r) a[c * kLdsLd + r] -= a[j * kLdsLd + r] * a[j * kLdsLd + c];
+        // trailing update of the lower part, 2 x 2 outputs per work item
+        const int nb2 = nr / 2;
+        for (int idx = tid; idx < nb2 * nb2; idx += 256) {
+            const int bi = idx % nb2, bj = idx / nb2;
+            if (bj > bi) continue;
+            const int r = r0 + 2 * bi, c = r0 + 2 * bj;
+            T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
+            for (int t = 0; t < kSB; ++t) {
+                const T* col = a + (s0 + t) * kLdsLd;
+                const T xr0 = col[r], xr1 = col[r + 1], xc0 = col[c], xc1 = col[c + 1];
+                c00 += xr0 * xc0;
+                c01 += xr0 * xc1;
+                c10 += xr1 * xc0;
+                c11 += xr1 * xc1;
+            }
+            a[c * kLdsLd + r] -= c00;
+            a[c * kLdsLd + r + 1] -= c10;
+            if (c + 1 <= r) a[(c + 1) * kLdsLd + r] -= c01;
+            a[(c + 1) * kLdsLd + r + 1] -= c11;
         }
         __syncthreads();
     }
     if (FACTOR) {
-        for (int idx = tid; idx < kNB * kNB; idx += 1024) {
-            int r = idx % kNB, c = idx / kNB;
-            if (c <= r) A[r + c * lda] = a[c * kLdsLd + r];
+        for (int idx = tid; idx < kNB * kNB; idx += 256) {
+            const int r = idx % kNB, c = idx / kNB;
+            if (c <= r) A[r + (int64_t)c * lda] = a[c * kLdsLd + r];
         }
-        __syncthreads();
     }
-
-    // in-place inverse of the lower triangular block, last column first:
-    // column j of L^{-1} below the diagonal is -(1/l_jj) Linv[j+1:, j+1:] l[j+1:, j]
-    for (int j = kNB - 1; j >= 0; --j) {
-        const T djj = T(1) / a[j * kLdsLd + j];
-        for (int r = j + 1 + tid; r < kNB; r += 1024) x[r] = a[j * kLdsLd + r];
-        __syncthreads();
-        for (int r = j + 1 + tid; r < kNB; r += 1024) {
-            T s = T(0);
-            for (int t = j + 1; t <= r; ++t) s += a[t * kLdsLd + r] * x[t];
-            a[j * kLdsLd + r] = -djj * s;
+    // blocked inverse in place (off-diagonal sub-blocks, columns left to right)
+    for (int s = 0; s < kNB / kSB - 1; ++s) {
+        const int s0 = s * kSB;
+        for (int rb = s + 1; rb < kNB / kSB; ++rb) {
+            const int q0 = rb * kSB;
+            // tmp = sum_{t=s}^{rb-1} L[rb][t] W[t][s]  (W[s][s] from the sub-block store)
+            for (int idx = tid; idx < kSB * kSB; idx += 256) {
+                const int i = idx % kSB, j = idx / kSB;
+                T acc = T(0);
+                for (int u = j; u < kSB; ++u)   // t = s: W_ss lower triangular
+                    acc += a[(s0 + u) * kLdsLd + q0 + i] * wsub(a, dW, s0, u, j);
+                for (int tb = s + 1; tb < rb; ++tb)
+                    for (int u = 0; u < kSB; ++u)
+                        acc += a[(tb * kSB + u) * kLdsLd + q0 + i] * a[(s0 + j) * kLdsLd + tb * kSB + u];
+                tmp[j * (kSB + 1) + i] = acc;
+            }
+            __syncthreads();
+            // W[rb][s] = -W_rr tmp
+            for (int idx = tid; idx < kSB * kSB; idx += 256) {
+                const int i = idx % kSB, j = idx / kSB;
+                T acc = T(0);
+                for (int u = 0; u <= i; ++u) acc += wsub(a, dW, q0, i, u) * tmp[j * (kSB + 1) + u];
+                a[(s0 + j) * kLdsLd + q0 + i] = -acc;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (tid == 0) a[j * kLdsLd + j] = djj;
-        __syncthreads();
     }
-    for (int idx = tid; idx < kNB * kNB; idx += 1024) {
-        int r = idx % kNB, c = idx / kNB;
-        W[r + c * kNB] = (c <= r) ? a[c * kLdsLd + r] : T(0);
+    // diagonal sub-blocks and the zero upper triangle
+    for (int idx = tid; idx < kNB * kNB; idx += 256) {
+        const int r = idx % kNB, c = idx / kNB;
+        T v;
+        if (c > r) v = T(0);
+        else if (r / kSB == c / kSB) v = wsub(a, dW, (r / kSB) * kSB, r % kSB, c % kSB);
+        else v = a[c * kLdsLd + r];
+        W[r + c * kNB] = v;
     }
 }
 
@@ -294,113 +432,9 @@ __global__ void panel_copy_kernel(const T *__restrict__ Pw, int64_t ldw, int m, 
 }
 
 // ------------------------------------------------------------------------
-// Triangular solves with M right-hand sides (B: npad x m, FP64, ld ldb).
-// The factor L (type T) and the diagonal inverses W_k (type T) are read in
-// their storage precision and used in FP64 arithmetic.
-// ------------------------------------------------------------------------
-// Shared memory of these kernels is dynamic: kNB x (m + 1) doubles plus,
-// for the backward update, a 64 x (kNB + 1) block of L.
-constexpr int kRhsPerThread = kMaxRhs / 4;
-
-// B_k <- W_k B_k (forward) or W_k^T B_k (backward); one workgroup, 256 threads.
-template <typename T, bool TRANS>
-__global__ __launch_bounds__(256) void diag_apply_kernel(const T *__restrict__ W, double *__restrict__ B,
-                                                         int64_t ldb, int m)
-{
-    extern __shared__ double bs[];   // bs[r * (m + 1) + c]
-    const int ld = m + 1, tid = threadIdx.x;
-    for (int idx = tid; idx < kNB * m; idx += 256) {
-        int r = idx % kNB, c = idx / kNB;
-        bs[r * ld + c] = B[r + (int64_t)c * ldb];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < kNB * m; idx += 256) {
-        int r = idx % kNB, c = idx / kNB;
-        double s = 0.0;
-        if (!TRANS) {
-            for (int t = 0; t <= r; ++t) s += (double)W[r + t * kNB] * bs[t * ld + c];
-        } else {
-            for (int t = r; t < kNB; ++t) s += (double)W[t + r * kNB] * bs[t * ld + c];
-        }
-        B[r + (int64_t)c * ldb] = s;
-    }
-}
-
-// Forward update: B[r, :] -= sum_t L[r, k0+t] Y[t, :] for the 64 rows of this
-// workgroup, Y = B[k0:k0+128, :].  Thread (r, g) accumulates columns g, g+4, ...
-template <typename T>
-__global__ __launch_bounds__(256) void fwd_update_kernel(const T *__restrict__ L, int64_t lda,
-                                                         double *__restrict__ B, int64_t ldb,
-                                                         int k0, int row0, int m)
-{
-    extern __shared__ double ys[];   // ys[t * (m + 1) + c]
-    const int ld = m + 1, tid = threadIdx.x;
-    for (int idx = tid; idx < kNB * m; idx += 256) {
-        int r = idx % kNB, c = idx / kNB;
-        ys[r * ld + c] = B[(k0 + r) + (int64_t)c * ldb];
-    }
-    __syncthreads();
-    const int r = row0 + blockIdx.x * 64 + (tid & 63), g = tid >> 6;
-    double acc[kRhsPerThread];
-#pragma unroll
-    for (int q = 0; q < kRhsPerThread; ++q) acc[q] = 0.0;
-    for (int t = 0; t < kNB; ++t) {
-        const double l = (double)L[r + (int64_t)(k0 + t) * lda];
-#pragma unroll
-        for (int q = 0; q < kRhsPerThread; ++q) {
-            int c = g + 4 * q;
-            if (c < m) acc[q] += l * ys[t * ld + c];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < kRhsPerThread; ++q) {
-        int c = g + 4 * q;
-        if (c < m) B[r + (int64_t)c * ldb] -= acc[q];
-    }
-}
-
-// Backward update: B[c, :] -= sum_t L[k0+t, c] X[t, :] for the 64 rows c < k0
-// of this workgroup, X = B[k0:k0+128, :].
-template <typename T>
-__global__ __launch_bounds__(256) void bwd_update_kernel(const T *__restrict__ L, int64_t lda,
-                                                         double *__restrict__ B, int64_t ldb,
-                                                         int k0, int m)
-{
-    extern __shared__ double xs[];           // xs[t * (m + 1) + c]
-    const int ld = m + 1, tid = threadIdx.x;
-    double *ls = xs + kNB * ld;              // ls[q * (kNB + 1) + t] = L[k0+t, c0+q]
-    for (int idx = tid; idx < kNB * m; idx += 256) {
-        int r = idx % kNB, c = idx / kNB;
-        xs[r * ld + c] = B[(k0 + r) + (int64_t)c * ldb];
-    }
-    const int c0 = blockIdx.x * 64;
-    for (int idx = tid; idx < 64 * kNB; idx += 256) {
-        int t = idx % kNB, q = idx / kNB;
-        ls[q * (kNB + 1) + t] = (double)L[(k0 + t) + (int64_t)(c0 + q) * lda];
-    }
-    __syncthreads();
-    const int q = tid & 63, g = tid >> 6;
-    double acc[kRhsPerThread];
-#pragma unroll
-    for (int p = 0; p < kRhsPerThread; ++p) acc[p] = 0.0;
-    for (int t = 0; t < kNB; ++t) {
-        const double l = ls[q * (kNB + 1) + t];
-#pragma unroll
-        for (int p = 0; p < kRhsPerThread; ++p) {
-            int c = g + 4 * p;
-            if (c < m) acc[p] += l * xs[t * ld + c];
-        }
-    }
-#pragma unroll
-    for (int p = 0; p < kRhsPerThread; ++p) {
-        int c = g + 4 * p;
-        if (c < m) B[(c0 + q) + (int64_t)c * ldb] -= acc[p];
-    }
-}
-
-// ------------------------------------------------------------------------
 // host drivers
 // ------------------------------------------------------------------------
+static size_t diag_smem_bytes(size_t es) { return (size_t)(kNB * kLdsLd + kNB + kSB * (kSB + 1)) * es; }
 static size_t elem_size(int dtype) { return dtype == GBEM_F64 ? 8 : 4; }
 
 size_t chol_winv_bytes(int dtype, int64_t npad) { return (size_t)npad * kNB * elem_size(dtype); }
@@ -415,14 +449,14 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
                            int32_t *info, hipStream_t s)
 {
     const int nb = (int)(npad / kNB);
-    const size_t smem = (size_t)(kNB * kLdsLd + kNB) * sizeof(T);
+    const size_t smem = diag_smem_bytes(sizeof(T));
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     for (int k = 0; k < nb; ++k) {
         const int64_t k0 = (int64_t)k * kNB;
         T *Akk = A + k0 + k0 * lda;
-        hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(1024), smem, s, Akk, lda,
+        hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), smem, s, Akk, lda,
                            Winv + (int64_t)k * kNB * kNB, info, (int)k0);
         const int64_t m = npad - k0 - kNB;
         if (m == 0) break;
@@ -474,51 +508,14 @@ hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv
 }
 
 template <typename T>
-static hipError_t solve_t(int64_t npad, const T *L, int64_t lda, const T *Winv, int m, double *B,
-                          int64_t ldb, hipStream_t s)
-{
-    const int nb = (int)(npad / kNB);
-    const size_t smem_b = (size_t)kNB * (m + 1) * sizeof(double);
-    const size_t smem_l = smem_b + (size_t)64 * (kNB + 1) * sizeof(double);
-    hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)diag_apply_kernel<T, false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_b)) != hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)diag_apply_kernel<T, true>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_b)) != hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)fwd_update_kernel<T>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_b)) != hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)bwd_update_kernel<T>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem_l)) != hipSuccess)
-        return e;
-    for (int k = 0; k < nb; ++k) {
-        const int64_t k0 = (int64_t)k * kNB;
-        hipLaunchKernelGGL((diag_apply_kernel<T, false>), dim3(1), dim3(256), smem_b, s,
-                           Winv + (int64_t)k * kNB * kNB, B + k0, ldb, m);
-        const int64_t rows = npad - k0 - kNB;
-        if (rows > 0)
-            hipLaunchKernelGGL(fwd_update_kernel<T>, dim3((unsigned)(rows / 64)), dim3(256), smem_b, s, L,
-                               lda, B, ldb, (int)k0, (int)(k0 + kNB), m);
-    }
-    for (int k = nb - 1; k >= 0; --k) {
-        const int64_t k0 = (int64_t)k * kNB;
-        hipLaunchKernelGGL((diag_apply_kernel<T, true>), dim3(1), dim3(256), smem_b, s,
-                           Winv + (int64_t)k * kNB * kNB, B + k0, ldb, m);
-        if (k0 > 0)
-            hipLaunchKernelGGL(bwd_update_kernel<T>, dim3((unsigned)(k0 / 64)), dim3(256), smem_l, s, L, lda,
-                               B, ldb, (int)k0, m);
-    }
-    return hipGetLastError();
-}
-
-template <typename T>
 static hipError_t diag_inverses_t(int64_t npad, const T *L, int64_t lda, T *Winv, hipStream_t s)
 {
-    const size_t smem = (size_t)(kNB * kLdsLd + kNB) * sizeof(T);
+    const size_t smem = diag_smem_bytes(sizeof(T));
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     for (int64_t k0 = 0; k0 < npad; k0 += kNB)
-        hipLaunchKernelGGL((diag_kernel<T, false>), dim3(1), dim3(1024), smem, s,
+        hipLaunchKernelGGL((diag_kernel<T, false>), dim3(1), dim3(256), smem, s,
                            const_cast<T *>(L) + k0 + k0 * lda, lda, Winv + k0 * kNB, (int32_t *)nullptr,
                            (int)k0);
     return hipGetLastError();
@@ -530,15 +527,6 @@ hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t ld
     if (npad % kNB) return hipErrorInvalidValue;
     if (dtype == GBEM_F64) return diag_inverses_t<double>(npad, (const double *)L, lda, (double *)Winv, s);
     return diag_inverses_t<float>(npad, (const float *)L, lda, (float *)Winv, s);
-}
-
-hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv, int m,
-                      double *B, int64_t ldb, hipStream_t s)
-{
-    if (npad % kNB || m > kMaxRhs || m <= 0) return hipErrorInvalidValue;
-    if (dtype == GBEM_F64)
-        return solve_t<double>(npad, (const double *)L, lda, (const double *)Winv, m, B, ldb, s);
-    return solve_t<float>(npad, (const float *)L, lda, (const float *)Winv, m, B, ldb, s);
 }
 
 }  // namespace gbem

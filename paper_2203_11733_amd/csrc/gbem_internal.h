@@ -91,8 +91,22 @@ hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule 
 // chol.hip
 hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *panel,
                        void *panel16, int32_t *info, hipStream_t s);
+// Synchronisation words of the persistent triangular solves (device arrays of
+// npad/128 flags per direction, zeroed once when allocated).  err[0] is the
+// error word (zeroed by the caller before a solve, read back after it);
+// err[1], err[2] are the ticket counters of the forward and backward launches.
+struct SolveSync {
+    int32_t *flags_f = nullptr;
+    int32_t *flags_b = nullptr;
+    int32_t *err = nullptr;
+    int32_t epoch = 0;
+    uint32_t base_f = 0, base_b = 0;   // host copies of the two ticket counters
+};
+// solve.hip
 hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv,
-                      int m, double *B, int64_t ldb, hipStream_t s);
+                      int m, double *B, int64_t ldb, SolveSync &sync, hipStream_t s);
+constexpr int kResMaxSplit = 16;
+int residual_splits(int npad);
 size_t chol_winv_bytes(int dtype, int64_t npad);
 size_t chol_panel_bytes(int dtype, int64_t npad);
 size_t chol_panel16_bytes(int dtype, int64_t npad);
@@ -104,9 +118,10 @@ hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t ld
 hipError_t launch_jacobi_scale(const double *A, int64_t lda, int npad, double *s, hipStream_t st);
 hipError_t launch_scale_convert(const double *A, int64_t lda, const double *s, int npad,
                                 float *F, int64_t ldf, hipStream_t st);
+// partial: residual_splits(npad) * m * npad doubles
 hipError_t launch_residual(const double *A, int64_t lda, int npad, const double *X, int64_t ldx,
                            const double *B, int64_t ldb, int m, double *R, int64_t ldr,
-                           hipStream_t st);
+                           double *partial, hipStream_t st);
 hipError_t launch_col_norms(const double *R, int64_t ldr, int npad, int m, double *norms,
                             hipStream_t st);
 hipError_t launch_scale_rows(double *X, int64_t ldx, const double *s, int npad, int m,

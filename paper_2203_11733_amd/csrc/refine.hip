@@ -39,59 +39,6 @@ hipError_t launch_scale_convert(const double *A, int64_t lda, const double *s, i
     return hipGetLastError();
 }
 
-// R = B - A X for 64 rows per workgroup; A symmetric, so row i of A is read
-// as column i (contiguous).  Chunks of 64 along j go through LDS.
-constexpr int kResRows = 64, kResChunk = 32, kResPerThread = kMaxRhs / 4;
-
-__global__ __launch_bounds__(256) void residual_kernel(const double *__restrict__ A, int64_t lda,
-                                                       int npad, const double *__restrict__ X,
-                                                       int64_t ldx, const double *__restrict__ B,
-                                                       int64_t ldb, int m, double *__restrict__ R,
-                                                       int64_t ldr)
-{
-    __shared__ double as[kResRows][kResChunk + 1];   // as[i][jj] = A[j0 + jj, i0 + i]
-    __shared__ double xs[kResChunk][kMaxRhs + 1];    // xs[jj][c] = X[j0 + jj, c]
-    const int tid = threadIdx.x, il = tid & 63, g = tid >> 6;
-    const int i0 = blockIdx.x * kResRows;
-    double acc[kResPerThread];
-#pragma unroll
-    for (int q = 0; q < kResPerThread; ++q) acc[q] = 0.0;
-    for (int j0 = 0; j0 < npad; j0 += kResChunk) {
-        for (int idx = tid; idx < kResRows * kResChunk; idx += 256) {
-            int jj = idx % kResChunk, i = idx / kResChunk;
-            as[i][jj] = A[(j0 + jj) + (int64_t)(i0 + i) * lda];
-        }
-        for (int idx = tid; idx < kResChunk * m; idx += 256) {
-            int jj = idx % kResChunk, c = idx / kResChunk;
-            xs[jj][c] = X[(j0 + jj) + (int64_t)c * ldx];
-        }
-        __syncthreads();
-        for (int jj = 0; jj < kResChunk; ++jj) {
-            const double a = as[il][jj];
-#pragma unroll
-            for (int q = 0; q < kResPerThread; ++q) {
-                int c = g + 4 * q;
-                if (c < m) acc[q] = __builtin_fma(a, xs[jj][c], acc[q]);
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < kResPerThread; ++q) {
-        int c = g + 4 * q;
-        if (c < m) R[(i0 + il) + (int64_t)c * ldr] = B[(i0 + il) + (int64_t)c * ldb] - acc[q];
-    }
-}
-
-hipError_t launch_residual(const double *A, int64_t lda, int npad, const double *X, int64_t ldx,
-                           const double *B, int64_t ldb, int m, double *R, int64_t ldr, hipStream_t st)
-{
-    if (npad % kResRows || m > kMaxRhs) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(residual_kernel, dim3(npad / kResRows), dim3(256), 0, st, A, lda, npad, X, ldx,
-                       B, ldb, m, R, ldr);
-    return hipGetLastError();
-}
-
 // norms[c] = sum_i R[i, c]^2 (fixed-order reduction, one workgroup per column)
 __global__ __launch_bounds__(256) void col_norms_kernel(const double *__restrict__ R, int64_t ldr,
                                                         int npad, double *__restrict__ norms)

@@ -87,6 +87,22 @@ def test_cholesky_solve_vs_numpy(ctx):
     assert rel_err(X, np.linalg.solve(A, B0)) < 1e-11
 
 
+def test_cholesky_solve_sizes_interleaved(ctx):
+    """Persistent solves of different block counts on one context (regression:
+    the ticket base of a launch must not assume earlier launches had its size)."""
+    import torch
+    rng = np.random.default_rng(12)
+    for n in (500, 2000, 300, 2000):
+        say(f"cholesky solve n={n}")
+        M = rng.standard_normal((n, n))
+        A = M @ M.T / n + np.eye(n)
+        L = torch.tensor(np.linalg.cholesky(A).T.copy(), device="cuda")
+        Bt = torch.tensor(rng.standard_normal((3, n)), device="cuda")
+        B0 = Bt.cpu().numpy().T.copy()
+        ctx.cholesky_solve_device(L.T, Bt.T, "f64")
+        assert rel_err(Bt.cpu().numpy().T, np.linalg.solve(A, B0)) < 1e-10
+
+
 def test_cholesky_reports_indefinite(ctx):
     import torch
     n = 200
