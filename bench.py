@@ -29,6 +29,72 @@ MODES = {
 }
 DTYPE_LABEL = {"mixed": "f32+bf16+f64", "mixed_f16": "f32+f16+f64", "mixed_f32": "f32+f64", "f64": "f64"}
 
+# MI355X peaks (dense): HBM3E 8 TB/s; MFMA bf16/f16 2.5 PFLOP/s, fp32 157.3, fp64 78.6;
+# vector fp32 157.3 (packed), fp64 78.6 TFLOP/s.
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"mfma_bf16": 2500.0, "mfma_f16": 2500.0, "mfma_f32": 157.3, "mfma_f64": 78.6,
+               "alu_f32": 157.3, "alu_f64": 78.6}
+# source file of each kernel class (the counters of a committed PMC summary
+# only apply while that file is unchanged)
+CLASS_SOURCE = {"far": "far.hip", "near_list": "near.hip", "near_eval": "near_eval.hip", "diag": "chol.hip",
+                "trsm": "chol.hip", "syrk": "chol.hip", "solve": "solve.hip", "residual": "solve.hip"}
+
+
+def compute_peak(cls, mode):
+    """(bound kind, peak TFLOP/s) of a kernel class in a mode."""
+    fac = MODES[mode]["factor_dtype"]
+    far = MODES[mode]["far_dtype"]
+    if cls == "far":
+        return "alu", PEAK_TFLOPS["alu_" + far]
+    if cls == "syrk":
+        return "mfma", PEAK_TFLOPS["mfma_" + fac]
+    if cls == "trsm":
+        return "mfma", PEAK_TFLOPS["mfma_" + ("f64" if fac == "f64" else "f32")]
+    if cls in ("diag",):
+        return "alu", PEAK_TFLOPS["alu_" + ("f64" if fac == "f64" else "f32")]
+    return "alu", PEAK_TFLOPS["alu_f64"]
+
+
+def roofline_of(profile, mode, layout_name):
+    """Roofline object of the kernel class with the largest GPU time."""
+    cls, d = max(profile.items(), key=lambda kv: kv[1]["ms"])
+    kind, peak_tf = compute_peak(cls, mode)
+    secs = d["ms"] / 1e3
+    t_compute = d["flops"] / (peak_tf * 1e12) if d["flops"] else 0.0
+    t_memory = d["bytes"] / (HBM_PEAK_GBS * 1e9)
+    per_launch = max(1, d["launches"])
+    if t_memory >= t_compute:
+        ach = d["bytes"] / secs / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    else:
+        ach = d["flops"] / secs / 1e12
+        roof = {"bound": kind, "achieved": ach, "peak": peak_tf, "unit": "TFLOP/s", "frac": ach / peak_tf}
+    roof.update({"kernel_class": cls, "launches": d["launches"], "avg_launch_ms": d["ms"] / per_launch,
+                 "algorithmic_flops_per_launch": d["flops"] / per_launch,
+                 "algorithmic_bytes_per_launch": d["bytes"] / per_launch,
+                 "traffic": measured_traffic(cls, mode, layout_name, per_launch)})
+    return roof
+
+
+def measured_traffic(cls, mode, layout_name, launches):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current source of that kernel; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    rec = table.get(f"{cls}/{mode}/{layout_name}")
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2203_11733_amd", "csrc", CLASS_SOURCE.get(cls, "api.cpp"))
+    with open(src, "rb") as f:
+        digest = hashlib.sha1(f.read()).hexdigest()
+    if digest != rec.get("source_sha1"):
+        return None
+    return rec.get("bytes_per_launch")
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -81,6 +147,75 @@ def cpu_baseline(lo, hi, cond, layout, p, eta):
             "extractions_per_s": 1.0 / t_est}
 
 
+def serving(args, binding, np):
+    """Replay the seeded job stream through gbem_submit/gbem_wait.
+
+    Arrivals follow the stream's Poisson times (50 jobs/s); latency is
+    submission -> completion.  A second pass submits every job at t = 0 for
+    the saturation throughput."""
+    import threading
+
+    import gbem_inputs as gi
+    stream = gi.serving_stream(n_jobs=args.jobs)
+    meshes = [(t, lay, *binding.mesh_layout(lay)) for t, lay in stream]
+    opts = binding.make_opts(args.p, args.eta, **MODES[args.mode])
+    n_list = [m[2].shape[0] for m in meshes]
+    log(f"serving: {len(meshes)} jobs, N from {min(n_list)} to {max(n_list)}, mode {args.mode}")
+    out = {"metric": "served extractions/s + p50/p99 latency", "unit": "extractions/s", "n_gpus": 1,
+           "mode": args.mode, "dtype": DTYPE_LABEL[args.mode], "data": "synthetic",
+           "config": {"workload": f"serving stream: {len(meshes)} random Manhattan layouts, "
+                                  f"N {min(n_list)}-{max(n_list)}, Poisson 50 jobs/s"}}
+    with binding.Context(0) as ctx:
+        # warm the workers
+        w = [ctx.submit(m[2], m[3], m[4], m[1].n_conductors, m[1].eps_r, m[1].length_unit_m, opts) for m in meshes[:4]]
+        for j in w:
+            j.wait(300.0)
+            j.free()
+        for phase in ("poisson", "saturation"):
+            submitted = []                     # (submit time, job)
+            finished = {}                      # index -> completion time
+            lock = threading.Lock()
+            stop = threading.Event()
+
+            def watcher():
+                # observe completions as they happen (poll, not wait in order)
+                while not stop.is_set() or len(finished) < len(meshes):
+                    with lock:
+                        pending = [(k, j) for k, (_, j) in enumerate(submitted) if k not in finished]
+                    now = time.perf_counter()
+                    for k, j in pending:
+                        if j.poll() != binding.EBUSY:
+                            finished[k] = now
+                    if stop.is_set() and len(finished) == len(meshes):
+                        break
+                    time.sleep(0.0005)
+
+            th = threading.Thread(target=watcher)
+            th.start()
+            t0 = time.perf_counter()
+            for k, (t_arr, lay, lo, hi, cond) in enumerate(meshes):
+                if phase == "poisson":
+                    delay = t_arr - (time.perf_counter() - t0)
+                    if delay > 0:
+                        time.sleep(delay)
+                j = ctx.submit(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m, opts)
+                with lock:
+                    submitted.append((time.perf_counter(), j))
+            stop.set()
+            th.join(timeout=900)
+            span = max(finished.values()) - t0
+            lat_ms = np.array([(finished[k] - submitted[k][0]) * 1e3 for k in range(len(meshes))])
+            for _, j in submitted:
+                j.wait(600.0)
+                j.free()
+            out[phase] = {"jobs_per_s": len(meshes) / span, "p50_ms": float(np.percentile(lat_ms, 50)),
+                          "p99_ms": float(np.percentile(lat_ms, 99)), "span_s": span}
+            log(f"serving {phase}: {out[phase]}")
+        out["server_stats"] = ctx.server_stats()
+    out["value"] = out["saturation"]["jobs_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +226,9 @@ def main():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--eta", type=float, default=2.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="replay the seeded serving stream (256 jobs, Poisson 50 jobs/s) instead")
+    ap.add_argument("--jobs", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
@@ -100,6 +238,10 @@ def main():
     import torch
 
     from paper_2203_11733_amd import binding
+
+    if args.serving:
+        print(json.dumps(serving(args, binding, np)))
+        return
 
     lay = layout_of(args.layout)
     lo, hi, cond = binding.mesh_layout(lay)
@@ -112,7 +254,7 @@ def main():
     d_C = torch.zeros((m, m), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     ctx = binding.Context(0)
-    opts = binding.make_opts(args.p, args.eta, **MODES[args.mode])
+    opts = binding.make_opts(args.p, args.eta, profile=True, **MODES[args.mode])
 
     # reference: the FP64 path (parity-tested against the CPU oracle)
     rep64 = ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C,
@@ -140,6 +282,13 @@ def main():
     r_last = reps[-1]
     stage = {k: float(np.mean([r[k] for r in reps])) for k in ("t_assemble_ms", "t_factor_ms", "t_solve_ms",
                                                               "t_total_ms")}
+    # per kernel class over the timed steps (HIP events inside the library)
+    profile = {}
+    for r in reps:
+        for cls, d in r["profile"].items():
+            acc = profile.setdefault(cls, {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+            for key in acc:
+                acc[key] += d[key]
     out = {
         "metric": "panel-pair integrals/s (whole extraction)",
         "value": pairs * args.steps / elapsed,
@@ -155,6 +304,8 @@ def main():
         "C_rel_err_vs_f64": err,
         "refine_iters": r_last["refine_iters"], "residual": r_last["residual"],
         "stage_ms": stage,
+        "kernel_ms_per_step": {c: d["ms"] / args.steps for c, d in sorted(profile.items(), key=lambda kv: -kv[1]["ms"])},
+        "roofline": roofline_of(profile, args.mode, lay.name),
         "f64_reference_ms": rep64["t_total_ms"],
     }
     if not args.no_cpu_baseline:

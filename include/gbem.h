@@ -83,7 +83,22 @@ typedef struct {
     int32_t factor_dtype;       /* gbem_dtype of the factorisation (GBEM_F64: no refinement) */
     double refine_tol;          /* refinement stops when max_k |b_k - A x_k|_2 / |b_k|_2 <= tol */
     int32_t max_refine;         /* refinement iteration cap (default 30) */
+    int32_t profile;            /* nonzero: time every kernel class with HIP events (gbem_report.prof_*) */
 } gbem_opts;
+
+/* Kernel classes of gbem_report.prof_* (see the design notes for their work units). */
+enum {
+    GBEM_K_FAR = 0,         /* far-field Gauss tiles */
+    GBEM_K_NEAR_LIST = 1,   /* near/far classification and CSR */
+    GBEM_K_NEAR_EVAL = 2,   /* closed-form near entries */
+    GBEM_K_DIAG = 3,        /* 128 x 128 diagonal-block Cholesky + inverse */
+    GBEM_K_TRSM = 4,        /* panel solve (GEMM with the block inverse) + copy */
+    GBEM_K_SYRK = 5,        /* trailing update (MFMA) */
+    GBEM_K_SOLVE = 6,       /* triangular solves */
+    GBEM_K_RESIDUAL = 7,    /* FP64 residual of the refinement */
+    GBEM_K_OTHER = 8,
+    GBEM_K_COUNT = 9
+};
 
 typedef struct {
     double t_assemble_ms;       /* panel table + near list + far + near kernels */
@@ -96,6 +111,11 @@ typedef struct {
     int32_t factor_used;        /* gbem_dtype actually used (after any fallback) */
     int64_t n_near;             /* near pairs j <= i, diagonal included */
     int64_t n_panels;
+    /* with opts.profile: per kernel class, summed over the extraction */
+    double prof_ms[GBEM_K_COUNT];        /* GPU time between events around the launches */
+    int64_t prof_launches[GBEM_K_COUNT];
+    double prof_flops[GBEM_K_COUNT];     /* algorithmic floating-point operations */
+    double prof_bytes[GBEM_K_COUNT];     /* algorithmic HBM bytes (compulsory reads + writes) */
 } gbem_report;
 
 /* Version string of the library. */
@@ -104,7 +124,8 @@ const char *gbem_version(void);
 const char *gbem_status_str(gbem_status s);
 /* Message of the last failure on the calling thread ("" if none). */
 const char *gbem_last_error(void);
-/* Fill *o with the defaults: p = 3, eta = 2, far FP64, factor FP64, tol 1e-6, 30 iterations. */
+/* Fill *o with the defaults: p = 3, eta = 2, far FP64, factor FP64, tol 1e-6, 30 iterations,
+ * profiling off. */
 void gbem_default_opts(gbem_opts *o);
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libgbem.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENOCONV, EBUSY, ETIMEOUT = range(8)
 F64, F32, F16, BF16 = range(4)
+KERNEL_CLASSES = ["far", "near_list", "near_eval", "diag", "trsm", "syrk", "solve", "residual", "other"]
 DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 
 EXPORTS = [
@@ -42,7 +43,8 @@ class Mesh(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("far_order", ctypes.c_int32), ("near_eta", ctypes.c_double),
                 ("far_dtype", ctypes.c_int32), ("factor_dtype", ctypes.c_int32),
-                ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32)]
+                ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -50,10 +52,21 @@ class Report(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("residual", ctypes.c_double), ("asym", ctypes.c_double),
                 ("refine_iters", ctypes.c_int32), ("factor_used", ctypes.c_int32),
-                ("n_near", ctypes.c_int64), ("n_panels", ctypes.c_int64)]
+                ("n_near", ctypes.c_int64), ("n_panels", ctypes.c_int64),
+                ("prof_ms", ctypes.c_double * 9), ("prof_launches", ctypes.c_int64 * 9),
+                ("prof_flops", ctypes.c_double * 9), ("prof_bytes", ctypes.c_double * 9)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if k.startswith("prof_") else v
+        d["profile"] = {name: {"ms": d["prof_ms"][i], "launches": d["prof_launches"][i],
+                               "flops": d["prof_flops"][i], "bytes": d["prof_bytes"][i]}
+                        for i, name in enumerate(KERNEL_CLASSES) if d["prof_launches"][i]}
+        for k in ("prof_ms", "prof_launches", "prof_flops", "prof_bytes"):
+            del d[k]
+        return d
 
 
 class MeshRule(ctypes.Structure):
@@ -127,9 +140,10 @@ def _ptr(a):
 
 
 def make_opts(far_order=3, near_eta=2.0, far_dtype="f64", factor_dtype="f64", refine_tol=1e-6,
-              max_refine=30) -> Opts:
+              max_refine=30, profile=False) -> Opts:
     return Opts(far_order, near_eta, DTYPES[far_dtype] if isinstance(far_dtype, str) else far_dtype,
-                DTYPES[factor_dtype] if isinstance(factor_dtype, str) else factor_dtype, refine_tol, max_refine)
+                DTYPES[factor_dtype] if isinstance(factor_dtype, str) else factor_dtype, refine_tol, max_refine,
+                1 if profile else 0)
 
 
 def mesh_boxes(box_lo, box_hi, box_cond, rule):

@@ -98,6 +98,7 @@ struct Workspace {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool events_ok = false;
     SolveSync sync;
+    Prof prof;
 
     // flags of the persistent solves: zeroed once when (re)allocated; the
     // epoch restarts with them
@@ -243,12 +244,25 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     double *A = ws.A.as<double>();
     const int64_t lda = npad;
 
+    Prof &pf = ws.prof;
+    pf.on = o.profile != 0;
+    pf.reset();
+    if (rep) {
+        for (int c = 0; c < GBEM_K_COUNT; ++c) {
+            rep->prof_ms[c] = rep->prof_flops[c] = rep->prof_bytes[c] = 0.0;
+            rep->prof_launches[c] = 0;
+        }
+    }
     HIPCHK(hipEventRecord(ws.ev[0], st), "hipEventRecord");
     HIPCHK(hipMemsetAsync(flags, 0, 64, st), "hipMemsetAsync");
+    int tok = pf.start(st);
     HIPCHK(launch_build_panels(dlo, dhi, dcond, n, m, ws.pan.as<Panel>(), flags, st), "build_panels");
+    pf.stop(tok, GBEM_K_OTHER, 0.0, (double)n * (48 + 4 + 64), st);
     const double eta2 = o.near_eta * o.near_eta;
+    const int tok_near = pf.start(st);
     HIPCHK(launch_near_count(dlo, dhi, n, eta2, ws.cnt.as<int64_t>(), st), "near_count");
     HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), st), "scan");
+    pf.stop(tok_near, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8 + 8), st, 2);
     double *B = ws.B.as<double>();
     HIPCHK(launch_rhs(dcond, n, (int)npad, m, B, npad, st), "rhs");
     double *bnorm = ws.norms.as<double>() + kMaxRhs;
@@ -275,19 +289,35 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
 
     HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near rows");
     HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
+    tok = pf.start(st);
     HIPCHK(launch_near_fill(dlo, dhi, n, eta2, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
                             ws.ncol.as<int32_t>(), st), "near_fill");
+    pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8) + (double)nnz * 8, st);
     GaussRule rule;
     gauss_legendre_rule(o.far_order, &rule);
+    tok = pf.start(st);
     HIPCHK(launch_far(ws.pan.as<Panel>(), n, (int)npad, o.far_order, rule, o.far_dtype, A, lda, st), "far");
+    {
+        const double p2 = (double)o.far_order * o.far_order;
+        // 11 flops per evaluation of w_a w_b / |x_a - y_b|: 3 differences, 5 for the
+        // squared norm, 1 reciprocal square root, 2 for the weighted sum
+        pf.stop(tok, GBEM_K_FAR, 11.0 * p2 * p2 * (double)n * (n + 1) / 2.0,
+                (double)npad * npad * 8.0 + (double)n * sizeof(Panel), st);
+    }
+    tok = pf.start(st);
     HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
                             A, lda, st), "near_eval");
+    pf.stop(tok, GBEM_K_NEAR_EVAL, 0.0, (double)nnz * (2 * 8 + 2 * 4 + 2 * 48), st);
     HIPCHK(hipEventRecord(ws.ev[1], st), "hipEventRecord");
     if (rep) {
         rep->n_near = nnz;
         rep->n_panels = n;
     }
-    if (stop == Stop::kAssembled) return GBEM_OK;
+    if (stop == Stop::kAssembled) {
+        HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+        pf.collect(rep);
+        return GBEM_OK;
+    }
 
     HIPCHK(ws.X.ensure((size_t)npad * m * 8), "alloc X");
     HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
@@ -306,12 +336,14 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         if (dtype != GBEM_F64) {
             HIPCHK(ws.F.ensure((size_t)npad * npad * es), "alloc F");
             HIPCHK(ws.s.ensure((size_t)npad * 8), "alloc s");
+            tok = pf.start(st);
             HIPCHK(launch_jacobi_scale(A, lda, (int)npad, ws.s.as<double>(), st), "jacobi");
             HIPCHK(launch_scale_convert(A, lda, ws.s.as<double>(), (int)npad, ws.F.as<float>(), npad, st),
                    "scale_convert");
+            pf.stop(tok, GBEM_K_OTHER, 2.0 * (double)npad * npad / 2.0, (double)npad * npad / 2.0 * 12.0, st, 2);
             Fm = ws.F.p;
         }
-        HIPCHK(chol_factor(dtype, npad, Fm, lda, ws.Winv.p, ws.Pw.p, ws.P16.p, flags + 1, st), "cholesky");
+        HIPCHK(chol_factor(dtype, npad, Fm, lda, ws.Winv.p, ws.Pw.p, ws.P16.p, flags + 1, st, &pf), "cholesky");
         int32_t info = 0;
         HIPCHK(hipMemcpyAsync(&info, flags + 1, 4, hipMemcpyDeviceToHost, st), "D2H info");
         HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -326,13 +358,13 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
         HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
         if (dtype == GBEM_F64) {
-            HIPCHK(chol_solve(dtype, npad, A, lda, ws.Winv.p, m, X, npad, ws.sync, st), "solve");
+            HIPCHK(chol_solve(dtype, npad, A, lda, ws.Winv.p, m, X, npad, ws.sync, st, &pf), "solve");
             break;
         }
         // mixed precision: X = S F^{-1} S B, then FP64 refinement with A
         const double *sv = ws.s.as<double>();
         HIPCHK(launch_scale_rows(X, npad, sv, (int)npad, m, st), "scale");
-        HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, X, npad, ws.sync, st), "solve");
+        HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, X, npad, ws.sync, st, &pf), "solve");
         HIPCHK(launch_scale_rows(X, npad, sv, (int)npad, m, st), "scale");
         HIPCHK(ws.R.ensure((size_t)npad * m * 8), "alloc R");
         HIPCHK(ws.rpart.ensure((size_t)residual_splits((int)npad) * m * npad * 8), "alloc residual partials");
@@ -340,8 +372,11 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         double *rnorm = ws.norms.as<double>();
         bool converged = false;
         for (iters = 0;; ++iters) {
+            tok = pf.start(st);
             HIPCHK(launch_residual(A, lda, (int)npad, X, npad, B, npad, m, R, npad, ws.rpart.as<double>(), st),
                    "residual");
+            pf.stop(tok, GBEM_K_RESIDUAL, 2.0 * (double)npad * npad * m,
+                    (double)npad * npad * 8.0 + 3.0 * (double)npad * m * 8.0, st, 2);
             HIPCHK(launch_col_norms(R, npad, (int)npad, m, rnorm, st), "col_norms");
             double rn[kMaxRhs];
             int32_t serr = 0;
@@ -361,7 +396,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             }
             if (iters >= o.max_refine) break;
             HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
-            HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, R, npad, ws.sync, st), "solve");
+            HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, R, npad, ws.sync, st, &pf), "solve");
             HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
             HIPCHK(launch_axpy_cols(X, npad, R, npad, (int)npad, m, st), "update");
         }
@@ -403,6 +438,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         rep->residual = resid;
         rep->refine_iters = iters;
         rep->factor_used = dtype;
+        pf.collect(rep);
     }
     return GBEM_OK;
 }
@@ -643,6 +679,7 @@ extern "C" void gbem_default_opts(gbem_opts *o)
     o->factor_dtype = GBEM_F64;
     o->refine_tol = 1e-6;
     o->max_refine = 30;
+    o->profile = 0;
 }
 
 extern "C" gbem_status gbem_create(int device, size_t budget, gbem_ctx **out)

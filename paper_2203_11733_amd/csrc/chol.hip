@@ -53,32 +53,37 @@ __device__ __forceinline__ double lane_bcast(double v, int src)
 }
 
 template <typename T, bool FACTOR>
-__device__ void chol_inv32(T *a, T *dW, int32_t *info, int grow)
+__device__ __forceinline__ void chol_inv32(T *a, T *dW, int32_t *info, int grow)
 {
+    // Branch-free on lane-dependent conditions: every lane runs the same
+    // instruction stream and masks with selects.
     const int lane = threadIdx.x & 63;
     const int r = lane & 31;
     T v[kSB], w[kSB];
 #pragma clang loop unroll(full)
-    for (int c = 0; c < kSB; ++c) v[c] = (c <= r) ? a[c * kLdsLd + r] : T(0);
+    for (int c = 0; c < kSB; ++c) {
+        const T x = a[c * kLdsLd + r];
+        v[c] = (c <= r) ? x : T(0);
+    }
     if (FACTOR) {
+        int firstbad = -1;   // wave-uniform: the pivot comes from v_readlane
 #pragma clang loop unroll(full)
         for (int j = 0; j < kSB; ++j) {
             T piv = lane_bcast(v[j], j);
-            if (!(piv > T(0))) {
-                if (lane == 0 && *info == 0) *info = grow + j + 1;
-                piv = T(1);
-            }
+            if (firstbad < 0 && !(piv > T(0))) firstbad = j;
+            piv = (piv > T(0)) ? piv : T(1);
             const T d = sqrt(piv);
-            if (r == j) v[j] = d;
-            else if (r > j) v[j] = v[j] / d;
-            const T lj = v[j];
+            const T rd = T(1) / d;
+            const T lj = (r == j) ? d : ((r > j) ? v[j] * rd : v[j]);
+            v[j] = lj;
 #pragma clang loop unroll(full)
             for (int c = 0; c < kSB; ++c) {
                 if (c <= j) continue;
                 const T lc = lane_bcast(lj, c);
-                if (r >= c) v[c] -= lj * lc;
+                v[c] -= (r >= c) ? lj * lc : T(0);
             }
         }
+        if (firstbad >= 0 && lane == 0 && *info == 0) *info = grow + firstbad + 1;
         if (lane < kSB) {
 #pragma clang loop unroll(full)
             for (int c = 0; c < kSB; ++c)
@@ -90,19 +95,19 @@ __device__ void chol_inv32(T *a, T *dW, int32_t *info, int grow)
     for (int c = 0; c < kSB; ++c) w[c] = (c == r) ? T(1) : T(0);
 #pragma clang loop unroll(full)
     for (int j = 0; j < kSB; ++j) {
-        const T ljj = lane_bcast(v[j], j);
+        const T rjj = T(1) / lane_bcast(v[j], j);
+        const T vj = v[j];
 #pragma clang loop unroll(full)
         for (int c = 0; c < kSB; ++c) {
             if (c > j) continue;
-            if (r == j) w[c] = w[c] / ljj;
-            const T wjc = lane_bcast(w[c], j);
-            if (r > j) w[c] -= v[j] * wjc;
+            const T wc = (r == j) ? w[c] * rjj : w[c];   // row j is final after scaling
+            const T wjc = lane_bcast(wc, j);
+            w[c] = (r > j) ? wc - vj * wjc : wc;
         }
     }
     T wd = T(0);   // w[r] without a dynamic index (keeps w in registers)
 #pragma clang loop unroll(full)
-    for (int c = 0; c < kSB; ++c)
-        if (c == r) wd = w[c];
+    for (int c = 0; c < kSB; ++c) wd = (c == r) ? w[c] : wd;
     if (lane < kSB) {
 #pragma clang loop unroll(full)
         for (int c = 0; c < kSB; ++c)
@@ -141,19 +146,24 @@ __global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t ld
         if (!FACTOR) continue;
         const int r0 = s0 + kSB, nr = kNB - r0;
         if (nr == 0) break;
-        // rows below: X[r][c] = sum_{t<=c} A[r][s0+t] W_ss[c][t]
+        // rows below: X[r][c] = sum_{t<=c} A[r][s0+t] W_ss[c][t]  (fixed trip
+        // count, masked coefficients)
         constexpr int kMaxOut = (kNB - kSB) * kSB / 256;   // 12
         T x[kMaxOut];
 #pragma unroll
         for (int q = 0; q < kMaxOut; ++q) {
             const int idx = tid + 256 * q;
-            x[q] = T(0);
-            if (idx < nr * kSB) {
-                const int r = r0 + idx % nr, c = idx / nr;
-                T acc = T(0);
-                for (int t = 0; t <= c; ++t) acc += a[(s0 + t) * kLdsLd + r] * wsub(a, dW, s0, c, t);
-                x[q] = acc;
+            const bool on = idx < nr * kSB;
+            const int r = r0 + (on ? idx % nr : 0), c = on ? idx / nr : 0;
+            const T dwc = dW[s0 + c];
+            T acc = T(0);
+#pragma unroll 8
+            for (int t = 0; t < kSB; ++t) {
+                const T wct = a[(s0 + c) * kLdsLd + (s0 + t)];   // W_ss[c][t] for t < c
+                const T coef = (t < c) ? wct : ((t == c) ? dwc : T(0));
+                acc += a[(s0 + t) * kLdsLd + r] * coef;
             }
+            x[q] = acc;
         }
         __syncthreads();
 #pragma unroll
@@ -193,20 +203,30 @@ __global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t ld
             if (c <= r) A[r + (int64_t)c * lda] = a[c * kLdsLd + r];
         }
     }
+    // Sub-block inverses complete in LDS: W_ss[c][t] = a[(s0+c)*ld + s0+t]
+    // for t <= c (the L diagonal, already written back, is overwritten).
+    __syncthreads();
+    if (tid < kNB) a[tid * kLdsLd + tid] = dW[tid];
+    __syncthreads();
     // blocked inverse in place (off-diagonal sub-blocks, columns left to right)
     for (int s = 0; s < kNB / kSB - 1; ++s) {
         const int s0 = s * kSB;
         for (int rb = s + 1; rb < kNB / kSB; ++rb) {
             const int q0 = rb * kSB;
-            // tmp = sum_{t=s}^{rb-1} L[rb][t] W[t][s]  (W[s][s] from the sub-block store)
+            // tmp = sum_{t=s}^{rb-1} L[rb][t] W[t][s]
             for (int idx = tid; idx < kSB * kSB; idx += 256) {
                 const int i = idx % kSB, j = idx / kSB;
                 T acc = T(0);
-                for (int u = j; u < kSB; ++u)   // t = s: W_ss lower triangular
-                    acc += a[(s0 + u) * kLdsLd + q0 + i] * wsub(a, dW, s0, u, j);
-                for (int tb = s + 1; tb < rb; ++tb)
+#pragma unroll 8
+                for (int u = 0; u < kSB; ++u) {   // t = s: W_ss lower triangular
+                    const T wuj = a[(s0 + u) * kLdsLd + s0 + j];
+                    acc += a[(s0 + u) * kLdsLd + q0 + i] * (u >= j ? wuj : T(0));
+                }
+                for (int tb = s + 1; tb < rb; ++tb) {
+#pragma unroll 8
                     for (int u = 0; u < kSB; ++u)
                         acc += a[(tb * kSB + u) * kLdsLd + q0 + i] * a[(s0 + j) * kLdsLd + tb * kSB + u];
+                }
                 tmp[j * (kSB + 1) + i] = acc;
             }
             __syncthreads();
@@ -214,20 +234,22 @@ __global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t ld
             for (int idx = tid; idx < kSB * kSB; idx += 256) {
                 const int i = idx % kSB, j = idx / kSB;
                 T acc = T(0);
-                for (int u = 0; u <= i; ++u) acc += wsub(a, dW, q0, i, u) * tmp[j * (kSB + 1) + u];
+#pragma unroll 8
+                for (int u = 0; u < kSB; ++u) {
+                    const T wiu = a[(q0 + i) * kLdsLd + q0 + u];
+                    acc += (u <= i ? wiu : T(0)) * tmp[j * (kSB + 1) + u];
+                }
                 a[(s0 + j) * kLdsLd + q0 + i] = -acc;
             }
             __syncthreads();
         }
     }
-    // diagonal sub-blocks and the zero upper triangle
+    // diagonal sub-blocks (stored transposed) and the zero upper triangle
     for (int idx = tid; idx < kNB * kNB; idx += 256) {
         const int r = idx % kNB, c = idx / kNB;
-        T v;
-        if (c > r) v = T(0);
-        else if (r / kSB == c / kSB) v = wsub(a, dW, (r / kSB) * kSB, r % kSB, c % kSB);
-        else v = a[c * kLdsLd + r];
-        W[r + c * kNB] = v;
+        const T lo_part = a[c * kLdsLd + r], diag_part = a[r * kLdsLd + c];
+        const bool same = (r / kSB) == (c / kSB);
+        W[r + c * kNB] = (c > r) ? T(0) : (same ? diag_part : lo_part);
     }
 }
 
@@ -446,8 +468,10 @@ size_t chol_panel16_bytes(int dtype, int64_t npad)
 
 template <typename T>
 static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, T *Pw, void *P16,
-                           int32_t *info, hipStream_t s)
+                           int32_t *info, hipStream_t s, Prof *prof)
 {
+    const double es = (double)sizeof(T);
+    const double eo = (dtype == GBEM_F16 || dtype == GBEM_BF16) ? 2.0 : es;   // trailing-update operand size
     const int nb = (int)(npad / kNB);
     const size_t smem = diag_smem_bytes(sizeof(T));
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, true>,
@@ -456,13 +480,16 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     for (int k = 0; k < nb; ++k) {
         const int64_t k0 = (int64_t)k * kNB;
         T *Akk = A + k0 + k0 * lda;
+        int tok = prof ? prof->start(s) : -1;
         hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), smem, s, Akk, lda,
                            Winv + (int64_t)k * kNB * kNB, info, (int)k0);
+        if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
         const int64_t m = npad - k0 - kNB;
         if (m == 0) break;
         const int tm = (int)(m / kBM);
         T *Pan = A + (k0 + kNB) + k0 * lda;
         // panel <- A_panel W_k^T
+        tok = prof ? prof->start(s) : -1;
         hipLaunchKernelGGL((gemm_nt_kernel<T, false, false>), dim3(tm), dim3(256), 0, s, tm, kNB,
                            (const T *)Pan, lda, (const T *)(Winv + (int64_t)k * kNB * kNB),
                            (int64_t)kNB, Pw, (int64_t)npad);
@@ -478,8 +505,12 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
             hipLaunchKernelGGL((panel_copy_kernel<T, T>), dim3((unsigned)((m + 255) / 256), kNB),
                                dim3(256), 0, s, (const T *)Pw, (int64_t)npad, (int)m, Pan, lda,
                                (T *)nullptr);
+        if (prof)
+            prof->stop(tok, GBEM_K_TRSM, 2.0 * m * kNB * kNB,
+                       (double)m * kNB * (3.0 * es + (eo < es ? eo : 0.0)) + kNB * kNB * es, s, 2);
         T *Trail = A + (k0 + kNB) + (k0 + kNB) * lda;
         const int64_t ntiles = (int64_t)tm * (tm + 1) / 2;
+        tok = prof ? prof->start(s) : -1;
         if (dtype == GBEM_BF16)
             hipLaunchKernelGGL(syrk16_kernel<__bf16>, dim3((unsigned)ntiles), dim3(256), 0, s, kNB,
                                (const __bf16 *)P16, (int64_t)kNB, (float *)Trail, lda);
@@ -490,6 +521,10 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
             hipLaunchKernelGGL((gemm_nt_kernel<T, true, true>), dim3((unsigned)ntiles), dim3(256), 0, s,
                                tm, kNB, (const T *)Pw, (int64_t)npad, (const T *)Pw, (int64_t)npad, Trail,
                                lda);
+        if (prof) {
+            const double tile_el = (double)ntiles * kBM * kBM;
+            prof->stop(tok, GBEM_K_SYRK, 2.0 * tile_el * kNB, 2.0 * tile_el * es + (double)m * kNB * eo, s);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -497,14 +532,14 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
 }
 
 hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *panel,
-                       void *panel16, int32_t *info, hipStream_t s)
+                       void *panel16, int32_t *info, hipStream_t s, Prof *prof)
 {
     if (npad % kNB) return hipErrorInvalidValue;
     if (dtype == GBEM_F64)
         return factor_t<double>(dtype, npad, (double *)A, lda, (double *)Winv, (double *)panel,
-                                nullptr, info, s);
+                                nullptr, info, s, prof);
     return factor_t<float>(dtype, npad, (float *)A, lda, (float *)Winv, (float *)panel, panel16,
-                           info, s);
+                           info, s, prof);
 }
 
 template <typename T>

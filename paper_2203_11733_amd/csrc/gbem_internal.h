@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "gbem.h"
 
@@ -52,6 +53,61 @@ struct NearRule {
     double w[kNearOrder];
 };
 
+// Event-based per-class kernel timing (opts.profile).  start() records an
+// event on the stream; stop() records the closing event and the algorithmic
+// work of the window; collect() sums the elapsed times after the final sync.
+struct Prof {
+    struct Rec {
+        int cls;
+        int a, b;
+        double flops, bytes;
+        int launches;
+    };
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Rec> recs;
+
+    int event(hipStream_t s)
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            pool.push_back(e);
+        }
+        if (hipEventRecord(pool[used], s) != hipSuccess) return -1;
+        return (int)used++;
+    }
+    int start(hipStream_t s) { return on ? event(s) : -1; }
+    void stop(int tok, int cls, double flops, double bytes, hipStream_t s, int launches = 1)
+    {
+        if (!on || tok < 0) return;
+        int b = event(s);
+        if (b >= 0) recs.push_back(Rec{cls, tok, b, flops, bytes, launches});
+    }
+    void reset()
+    {
+        used = 0;
+        recs.clear();
+    }
+    void collect(gbem_report *rep)
+    {
+        if (!on || !rep) return;
+        for (const Rec &r : recs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pool[r.a], pool[r.b]) != hipSuccess) continue;
+            rep->prof_ms[r.cls] += ms;
+            rep->prof_launches[r.cls] += r.launches;
+            rep->prof_flops[r.cls] += r.flops;
+            rep->prof_bytes[r.cls] += r.bytes;
+        }
+    }
+    ~Prof()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 // ---- host helpers --------------------------------------------------------
 void set_error(const std::string &msg);
 // p-point Gauss-Legendre nodes (ascending) and halved weights on [-1, 1]
@@ -90,7 +146,7 @@ hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule 
 
 // chol.hip
 hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *panel,
-                       void *panel16, int32_t *info, hipStream_t s);
+                       void *panel16, int32_t *info, hipStream_t s, Prof *prof = nullptr);
 // Synchronisation words of the persistent triangular solves (device arrays of
 // npad/128 flags per direction, zeroed once when allocated).  err[0] is the
 // error word (zeroed by the caller before a solve, read back after it);
@@ -104,7 +160,8 @@ struct SolveSync {
 };
 // solve.hip
 hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv,
-                      int m, double *B, int64_t ldb, SolveSync &sync, hipStream_t s);
+                      int m, double *B, int64_t ldb, SolveSync &sync, hipStream_t s,
+                      Prof *prof = nullptr);
 constexpr int kResMaxSplit = 16;
 int residual_splits(int npad);
 size_t chol_winv_bytes(int dtype, int64_t npad);

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void bwd_solve_kernel(const T *__restrict__ L,
 
 template <typename T, int MC>
 static hipError_t solve_mc(int64_t npad, const T *L, int64_t lda, const T *W, int m, double *B, int64_t ldb,
-                           SolveSync &sync, hipStream_t s)
+                           SolveSync &sync, hipStream_t s, Prof *prof)
 {
     const int nb = (int)(npad / kNB);
     const size_t smem = (size_t)2 * kNB * (MC + 1) * sizeof(double);
@@ -220,10 +220,17 @@ static hipError_t solve_mc(int64_t npad, const T *L, int64_t lda, const T *W, in
         return e;
     const int limit = 1 << 26;
     ++sync.epoch;
+    const int tok = prof ? prof->start(s) : -1;
     hipLaunchKernelGGL((fwd_solve_kernel<T, MC>), dim3(nb), dim3(256), smem, s, L, lda, W, B, ldb, m, nb,
                        sync.flags_f, sync.err + 1, sync.base_f, sync.epoch, sync.err, limit);
     hipLaunchKernelGGL((bwd_solve_kernel<T, MC>), dim3(nb), dim3(256), smem, s, L, lda, W, B, ldb, m, nb,
                        sync.flags_b, sync.err + 2, sync.base_b, sync.epoch, sync.err, limit);
+    if (prof) {
+        // L read once per direction (lower half incl. diagonal blocks), W read twice, B read/written
+        const double lbytes = (double)npad * (npad + kNB) / 2.0 * sizeof(T);
+        prof->stop(tok, GBEM_K_SOLVE, 2.0 * 2.0 * (double)npad * npad / 2.0 * m,
+                   2.0 * lbytes + 2.0 * npad * kNB * sizeof(T) + 4.0 * npad * m * 8.0, s, 2);
+    }
     e = hipGetLastError();
     if (e == hipSuccess) {   // both launches queued: each consumes exactly nb tickets
         sync.base_f += (uint32_t)nb;
@@ -234,20 +241,21 @@ static hipError_t solve_mc(int64_t npad, const T *L, int64_t lda, const T *W, in
 
 template <typename T>
 static hipError_t solve_t(int64_t npad, const T *L, int64_t lda, const T *W, int m, double *B, int64_t ldb,
-                          SolveSync &sync, hipStream_t s)
+                          SolveSync &sync, hipStream_t s, Prof *prof)
 {
-    if (m <= 8) return solve_mc<T, 8>(npad, L, lda, W, m, B, ldb, sync, s);
-    if (m <= 16) return solve_mc<T, 16>(npad, L, lda, W, m, B, ldb, sync, s);
-    if (m <= 32) return solve_mc<T, 32>(npad, L, lda, W, m, B, ldb, sync, s);
-    return solve_mc<T, 64>(npad, L, lda, W, m, B, ldb, sync, s);
+    if (m <= 8) return solve_mc<T, 8>(npad, L, lda, W, m, B, ldb, sync, s, prof);
+    if (m <= 16) return solve_mc<T, 16>(npad, L, lda, W, m, B, ldb, sync, s, prof);
+    if (m <= 32) return solve_mc<T, 32>(npad, L, lda, W, m, B, ldb, sync, s, prof);
+    return solve_mc<T, 64>(npad, L, lda, W, m, B, ldb, sync, s, prof);
 }
 
 hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv, int m, double *B,
-                      int64_t ldb, SolveSync &sync, hipStream_t s)
+                      int64_t ldb, SolveSync &sync, hipStream_t s, Prof *prof)
 {
     if (npad % kNB || m > kMaxRhs || m <= 0) return hipErrorInvalidValue;
-    if (dtype == GBEM_F64) return solve_t<double>(npad, (const double *)L, lda, (const double *)Winv, m, B, ldb, sync, s);
-    return solve_t<float>(npad, (const float *)L, lda, (const float *)Winv, m, B, ldb, sync, s);
+    if (dtype == GBEM_F64)
+        return solve_t<double>(npad, (const double *)L, lda, (const double *)Winv, m, B, ldb, sync, s, prof);
+    return solve_t<float>(npad, (const float *)L, lda, (const float *)Winv, m, B, ldb, sync, s, prof);
 }
 
 // ------------------------------------------------------------------------

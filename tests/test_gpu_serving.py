@@ -1,0 +1,91 @@
+"""Serving loop on the GPU: concurrent jobs give the same capacitances as the
+same jobs run alone, admission respects the HBM budget, and jobs that can
+never fit are refused at submission."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import gbem_inputs as gi
+from paper_2203_11733_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_stream(n_jobs=8, n_max=3000, seed=7):
+    return gi.serving_stream(n_jobs=n_jobs, seed=seed, n_min=500, n_max=n_max)
+
+
+@pytest.fixture(scope="module")
+def meshes(gpu_lib):
+    out = []
+    for _, lay in small_stream():
+        lo, hi, cond = binding.mesh_layout(lay)
+        out.append((lay, lo, hi, cond))
+    return out
+
+
+@pytest.mark.parametrize("mode", ["f64", "mixed"])
+def test_mix_equals_alone(meshes, mode):
+    opts = (binding.make_opts() if mode == "f64"
+            else binding.make_opts(3, 2.0, "f32", "bf16", 1e-8, 40))
+    alone = []
+    with binding.Context(0) as ctx:
+        for lay, lo, hi, cond in meshes:
+            C, rep = ctx.extract(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m, opts)
+            alone.append(C)
+    say(f"serving {mode}: {len(meshes)} jobs, N = {[m[1].shape[0] for m in meshes]}")
+    with binding.Context(0) as ctx:
+        jobs = [ctx.submit(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m, opts)
+                for lay, lo, hi, cond in meshes]
+        results = [j.wait(120.0) for j in jobs]
+        stats = ctx.server_stats()
+        for j in jobs:
+            j.free()
+    assert stats["jobs_done"] == len(meshes)
+    for (C, rep), Ca in zip(results, alone):
+        # the kernels use fixed-order reductions only: results do not depend on the mix
+        assert np.array_equal(C, Ca)
+
+
+def test_admission_under_small_budget(meshes):
+    lay, lo, hi, cond = max(meshes, key=lambda m: m[1].shape[0])
+    npad = (lo.shape[0] + 127) // 128 * 128
+    budget = int(2.5 * npad * npad * 8)          # about two jobs of this size at once
+    with binding.Context(0, budget) as ctx:
+        jobs = [ctx.submit(m[1], m[2], m[3], m[0].n_conductors, m[0].eps_r, m[0].length_unit_m)
+                for m in meshes]
+        for j in jobs:
+            j.wait(120.0)
+            j.free()
+        stats = ctx.server_stats()
+    say(f"admission: budget {budget / 1e6:.1f} MB, peak {stats['peak_bytes'] / 1e6:.1f} MB")
+    assert stats["jobs_done"] == len(meshes)
+    assert 0 < stats["peak_bytes"] <= budget
+
+
+def test_oversize_job_refused(meshes):
+    lay, lo, hi, cond = meshes[0]
+    with binding.Context(0, 1 << 20) as ctx:       # 1 MiB budget
+        with pytest.raises(binding.GbemError) as e:
+            ctx.submit(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m)
+    assert e.value.status == binding.ENOMEM
+
+
+def test_poll_and_wait(meshes):
+    lay, lo, hi, cond = meshes[0]
+    with binding.Context(0) as ctx:
+        j = ctx.submit(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m)
+        t0 = time.time()
+        while j.poll() == binding.EBUSY and time.time() - t0 < 60:
+            time.sleep(0.001)
+        assert j.poll() == binding.OK
+        C, rep = j.wait(0.0)
+        j.free()
+    assert C[0, 0] > 0 and rep["t_total_ms"] > 0
