@@ -99,6 +99,14 @@ struct Workspace {
     bool events_ok = false;
     SolveSync sync;
     Prof prof;
+    hipStream_t side = nullptr;         // look-ahead stream of the factorisation
+    std::vector<hipEvent_t> fev;        // its event pool
+
+    hipError_t ensure_side()
+    {
+        if (side) return hipSuccess;
+        return hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    }
 
     // flags of the persistent solves: zeroed once when (re)allocated; the
     // epoch restarts with them
@@ -149,6 +157,8 @@ struct Workspace {
         release_all();
         if (events_ok)
             for (auto &e : ev) (void)hipEventDestroy(e);
+        for (auto &e : fev) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -159,7 +169,7 @@ static size_t footprint(int64_t n, int m, int factor_dtype)
     size_t b = (size_t)npad * npad * 8;                                   // A
     if (factor_dtype != GBEM_F64) b += (size_t)npad * npad * 4;           // FP32 factor
     const size_t es = factor_dtype == GBEM_F64 ? 8 : 4;
-    b += 2 * (size_t)npad * kNB * es + (size_t)npad * kNB * 2;           // W, panel, 16-bit panel
+    b += (size_t)npad * kNB * es + (size_t)npad * 256 * 2 * 2;           // W, 16-bit panels
     b += 4 * (size_t)npad * m * 8 + (size_t)npad * 8;                    // B X R D, s
     b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 8;            // mesh, panels, near list
     return b;
@@ -343,7 +353,9 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             pf.stop(tok, GBEM_K_OTHER, 2.0 * (double)npad * npad / 2.0, (double)npad * npad / 2.0 * 12.0, st, 2);
             Fm = ws.F.p;
         }
-        HIPCHK(chol_factor(dtype, npad, Fm, lda, ws.Winv.p, ws.Pw.p, ws.P16.p, flags + 1, st, &pf), "cholesky");
+        HIPCHK(ws.ensure_side(), "side stream");
+        HIPCHK(chol_factor(dtype, npad, Fm, lda, ws.Winv.p, ws.Pw.p, ws.P16.p, flags + 1, st, ws.side, ws.fev, &pf),
+               "cholesky");
         int32_t info = 0;
         HIPCHK(hipMemcpyAsync(&info, flags + 1, 4, hipMemcpyDeviceToHost, st), "D2H info");
         HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -1040,7 +1052,9 @@ static gbem_status chol_common(gbem_ctx *ctx, int32_t n, int32_t dtype, void *A,
     HIPCHK(launch_identity_pad(Ap.p, npad, n, (int)npad, dtype == GBEM_F64, st), "pad");
     if (!solve) {
         HIPCHK(hipMemsetAsync(ws.flags.p, 0, 64, st), "memset");
-        HIPCHK(chol_factor(dtype, npad, Ap.p, npad, ws.Winv.p, ws.Pw.p, ws.P16.p, ws.flags.as<int32_t>() + 1, st),
+        HIPCHK(ws.ensure_side(), "side stream");
+        HIPCHK(chol_factor(dtype, npad, Ap.p, npad, ws.Winv.p, ws.Pw.p, ws.P16.p, ws.flags.as<int32_t>() + 1, st,
+                           ws.side, ws.fev),
                "cholesky");
         int32_t inf = 0;
         HIPCHK(hipMemcpyAsync(&inf, ws.flags.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost, st), "D2H");

@@ -20,252 +20,20 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));   // 16-byte chunk
 
 // ------------------------------------------------------------------------
-// Step 1: Cholesky of the 128 x 128 diagonal block in LDS and its inverse.
-// The block is processed as 4 x 4 sub-blocks of 32.  For each sub-block
-// column s: one wave factors the 32 x 32 diagonal sub-block and inverts it in
-// registers (lane r owns row r, values broadcast with v_readlane, no
-// barriers); all waves then solve the sub-block rows below against it and
-// apply the rank-32 update to the rest.  The inverse of the whole block is
-// assembled in place from the sub-block inverses W_ss:
-//   W_rs = -W_rr sum_{t=s}^{r-1} L_rt W_ts   (columns s left to right).
-// Sub-block inverses wait in the unused upper triangle (transposed) and in a
-// 128-entry diagonal array until the end.
-// ------------------------------------------------------------------------
-constexpr int kLdsLd = kNB + 1;   // column stride of the LDS block: a[c * kLdsLd + r]
-constexpr int kSB = 32;
-
-// One wave; lanes 0..31 own rows of the 32 x 32 sub-block at a (column
-// stride kLdsLd).  FACTOR: Cholesky in place; then W = L^{-1} is written to
-// the strictly upper part (a[r * ld + c] = W[r][c] for c < r) and dW.
-// Value of v in lane `src` for the whole wave (v_readlane: no LDS round trip).
-__device__ __forceinline__ float lane_bcast(float v, int src)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
-}
-__device__ __forceinline__ double lane_bcast(double v, int src)
-{
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), src);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), src);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
-template <typename T, bool FACTOR>
-__device__ __forceinline__ void chol_inv32(T *a, T *dW, int32_t *info, int grow)
-{
-    // Branch-free on lane-dependent conditions: every lane runs the same
-    // instruction stream and masks with selects.
-    const int lane = threadIdx.x & 63;
-    const int r = lane & 31;
-    T v[kSB], w[kSB];
-#pragma clang loop unroll(full)
-    for (int c = 0; c < kSB; ++c) {
-        const T x = a[c * kLdsLd + r];
-        v[c] = (c <= r) ? x : T(0);
-    }
-    if (FACTOR) {
-        int firstbad = -1;   // wave-uniform: the pivot comes from v_readlane
-#pragma clang loop unroll(full)
-        for (int j = 0; j < kSB; ++j) {
-            T piv = lane_bcast(v[j], j);
-            if (firstbad < 0 && !(piv > T(0))) firstbad = j;
-            piv = (piv > T(0)) ? piv : T(1);
-            const T d = sqrt(piv);
-            const T rd = T(1) / d;
-            const T lj = (r == j) ? d : ((r > j) ? v[j] * rd : v[j]);
-            v[j] = lj;
-#pragma clang loop unroll(full)
-            for (int c = 0; c < kSB; ++c) {
-                if (c <= j) continue;
-                const T lc = lane_bcast(lj, c);
-                v[c] -= (r >= c) ? lj * lc : T(0);
-            }
-        }
-        if (firstbad >= 0 && lane == 0 && *info == 0) *info = grow + firstbad + 1;
-        if (lane < kSB) {
-#pragma clang loop unroll(full)
-            for (int c = 0; c < kSB; ++c)
-                if (c <= r) a[c * kLdsLd + r] = v[c];
-        }
-    }
-    // W = L^{-1}: rows of the identity eliminated top to bottom
-#pragma clang loop unroll(full)
-    for (int c = 0; c < kSB; ++c) w[c] = (c == r) ? T(1) : T(0);
-#pragma clang loop unroll(full)
-    for (int j = 0; j < kSB; ++j) {
-        const T rjj = T(1) / lane_bcast(v[j], j);
-        const T vj = v[j];
-#pragma clang loop unroll(full)
-        for (int c = 0; c < kSB; ++c) {
-            if (c > j) continue;
-            const T wc = (r == j) ? w[c] * rjj : w[c];   // row j is final after scaling
-            const T wjc = lane_bcast(wc, j);
-            w[c] = (r > j) ? wc - vj * wjc : wc;
-        }
-    }
-    T wd = T(0);   // w[r] without a dynamic index (keeps w in registers)
-#pragma clang loop unroll(full)
-    for (int c = 0; c < kSB; ++c) wd = (c == r) ? w[c] : wd;
-    if (lane < kSB) {
-#pragma clang loop unroll(full)
-        for (int c = 0; c < kSB; ++c)
-            if (c < r) a[r * kLdsLd + c] = w[c];
-        dW[r] = wd;
-    }
-}
-
-// W_ss[c][t] for the sub-block inverse stored by chol_inv32 (t <= c)
-template <typename T>
-__device__ __forceinline__ T wsub(const T *a, const T *dW, int s0, int c, int t)
-{
-    return t == c ? dW[s0 + c] : a[(s0 + c) * kLdsLd + (s0 + t)];
-}
-
-template <typename T, bool FACTOR>
-__global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t lda, T *__restrict__ W,
-                                                   int32_t *__restrict__ info, int k0)
-{
-    extern __shared__ unsigned char smem_raw[];
-    T *a = reinterpret_cast<T *>(smem_raw);   // a[c * kLdsLd + r]
-    T *dW = a + kNB * kLdsLd;                 // 128 diagonal entries of the sub-block inverses
-    T *tmp = dW + kNB;                        // 32 x 33 scratch
-    const int tid = threadIdx.x, wave = tid >> 6;
-
-    for (int idx = tid; idx < kNB * kNB; idx += 256) {
-        const int r = idx % kNB, c = idx / kNB;
-        a[c * kLdsLd + r] = (c <= r) ? A[r + (int64_t)c * lda] : T(0);
-    }
-    __syncthreads();
-
-    for (int s = 0; s < kNB / kSB; ++s) {
-        const int s0 = s * kSB;
-        if (wave == 0) chol_inv32<T, FACTOR>(a + s0 * kLdsLd + s0, dW + s0, info, k0 + s0);
-        __syncthreads();
-        if (!FACTOR) continue;
-        const int r0 = s0 + kSB, nr = kNB - r0;
-        if (nr == 0) break;
-        // rows below: X[r][c] = sum_{t<=c} A[r][s0+t] W_ss[c][t]  (fixed trip
-        // count, masked coefficients)
-        constexpr int kMaxOut = (kNB - kSB) * kSB / 256;   // 12
-        T x[kMaxOut];
-#pragma unroll
-        for (int q = 0; q < kMaxOut; ++q) {
-            const int idx = tid + 256 * q;
-            const bool on = idx < nr * kSB;
-            const int r = r0 + (on ? idx % nr : 0), c = on ? idx / nr : 0;
-            const T dwc = dW[s0 + c];
-            T acc = T(0);
-#pragma unroll 8
-            for (int t = 0; t < kSB; ++t) {
-                const T wct = a[(s0 + c) * kLdsLd + (s0 + t)];   // W_ss[c][t] for t < c
-                const T coef = (t < c) ? wct : ((t == c) ? dwc : T(0));
-                acc += a[(s0 + t) * kLdsLd + r] * coef;
-            }
-            x[q] = acc;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kMaxOut; ++q) {
-            const int idx = tid + 256 * q;
-            if (idx < nr * kSB) {
-                const int r = r0 + idx % nr, c = idx / nr;
-                a[(s0 + c) * kLdsLd + r] = x[q];
-            }
-        }
-        __syncthreads();
-        // trailing update of the lower part, 2 x 2 outputs per work item
-        const int nb2 = nr / 2;
-        for (int idx = tid; idx < nb2 * nb2; idx += 256) {
-            const int bi = idx % nb2, bj = idx / nb2;
-            if (bj > bi) continue;
-            const int r = r0 + 2 * bi, c = r0 + 2 * bj;
-            T c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-            for (int t = 0; t < kSB; ++t) {
-                const T* col = a + (s0 + t) * kLdsLd;
-                const T xr0 = col[r], xr1 = col[r + 1], xc0 = col[c], xc1 = col[c + 1];
-                c00 += xr0 * xc0;
-                c01 += xr0 * xc1;
-                c10 += xr1 * xc0;
-                c11 += xr1 * xc1;
-            }
-            a[c * kLdsLd + r] -= c00;
-            a[c * kLdsLd + r + 1] -= c10;
-            if (c + 1 <= r) a[(c + 1) * kLdsLd + r] -= c01;
-            a[(c + 1) * kLdsLd + r + 1] -= c11;
-        }
-        __syncthreads();
-    }
-    if (FACTOR) {
-        for (int idx = tid; idx < kNB * kNB; idx += 256) {
-            const int r = idx % kNB, c = idx / kNB;
-            if (c <= r) A[r + (int64_t)c * lda] = a[c * kLdsLd + r];
-        }
-    }
-    // Sub-block inverses complete in LDS: W_ss[c][t] = a[(s0+c)*ld + s0+t]
-    // for t <= c (the L diagonal, already written back, is overwritten).
-    __syncthreads();
-    if (tid < kNB) a[tid * kLdsLd + tid] = dW[tid];
-    __syncthreads();
-    // blocked inverse in place (off-diagonal sub-blocks, columns left to right)
-    for (int s = 0; s < kNB / kSB - 1; ++s) {
-        const int s0 = s * kSB;
-        for (int rb = s + 1; rb < kNB / kSB; ++rb) {
-            const int q0 = rb * kSB;
-            // tmp = sum_{t=s}^{rb-1} L[rb][t] W[t][s]
-            for (int idx = tid; idx < kSB * kSB; idx += 256) {
-                const int i = idx % kSB, j = idx / kSB;
-                T acc = T(0);
-#pragma unroll 8
-                for (int u = 0; u < kSB; ++u) {   // t = s: W_ss lower triangular
-                    const T wuj = a[(s0 + u) * kLdsLd + s0 + j];
-                    acc += a[(s0 + u) * kLdsLd + q0 + i] * (u >= j ? wuj : T(0));
-                }
-                for (int tb = s + 1; tb < rb; ++tb) {
-#pragma unroll 8
-                    for (int u = 0; u < kSB; ++u)
-                        acc += a[(tb * kSB + u) * kLdsLd + q0 + i] * a[(s0 + j) * kLdsLd + tb * kSB + u];
-                }
-                tmp[j * (kSB + 1) + i] = acc;
-            }
-            __syncthreads();
-            // W[rb][s] = -W_rr tmp
-            for (int idx = tid; idx < kSB * kSB; idx += 256) {
-                const int i = idx % kSB, j = idx / kSB;
-                T acc = T(0);
-#pragma unroll 8
-                for (int u = 0; u < kSB; ++u) {
-                    const T wiu = a[(q0 + i) * kLdsLd + q0 + u];
-                    acc += (u <= i ? wiu : T(0)) * tmp[j * (kSB + 1) + u];
-                }
-                a[(s0 + j) * kLdsLd + q0 + i] = -acc;
-            }
-            __syncthreads();
-        }
-    }
-    // diagonal sub-blocks (stored transposed) and the zero upper triangle
-    for (int idx = tid; idx < kNB * kNB; idx += 256) {
-        const int r = idx % kNB, c = idx / kNB;
-        const T lo_part = a[c * kLdsLd + r], diag_part = a[r * kLdsLd + c];
-        const bool same = (r / kSB) == (c / kSB);
-        W[r + c * kNB] = (c > r) ? T(0) : (same ? diag_part : lo_part);
-    }
-}
-
-// ------------------------------------------------------------------------
-// GEMM C = A B^T (BETA = 0) or C -= A B^T (BETA = 1), FP64/FP32 operands
-// stored column-major.  128 x 128 tile per 256-thread workgroup, 4 waves of
-// 64 x 64, each 4 x 4 MFMA 16x16x4 blocks; K chunks of 16 through LDS.
-// LOWER: tiles of the lower triangle only (M == N), diagonal tiles store r >= c.
+// MFMA 16x16x4 (f64 / f32) with its output layout.  Operand fragments: lane l
+// supplies A[l % 16][k = l / 16] and B[k = l / 16][l % 16].  Output: lane l,
+// register q holds column l % 16 and row row(l, q); the f64 instruction
+// interleaves the rows (l / 16 + 4 q), the f32 one keeps four consecutive rows
+// per lane (4 (l / 16) + q).
 // ------------------------------------------------------------------------
 template <typename T> struct Mfma4;
-// Output block of one 16x16 MFMA: lane l, register r holds column l % 16 and
-// row row(l, r).  The f64 instruction interleaves the rows (l / 16 + 4 r); the
-// f32 and 16-bit ones keep four consecutive rows per lane (4 (l / 16) + r).
 template <> struct Mfma4<double> {
     typedef d4_t acc_t;
-    static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+    static constexpr bool kConsecutiveRows = false;
+    static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
     static __device__ __forceinline__ acc_t run(double a, double b, acc_t c)
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -273,18 +41,303 @@ template <> struct Mfma4<double> {
 };
 template <> struct Mfma4<float> {
     typedef f4_t acc_t;
-    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    static constexpr bool kConsecutiveRows = true;
+    static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
     static __device__ __forceinline__ acc_t run(float a, float b, acc_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
 };
 
-constexpr int kBM = 128, kBK = 16, kLdsPad = 4;
+// ------------------------------------------------------------------------
+// Step 1: Cholesky of the 128 x 128 diagonal block and its inverse, one
+// workgroup, everything in LDS.  The lower triangle is held as 36 blocks of
+// 16 x 16 (column-major, 256 elements each, block (R, S) at R (R + 1) / 2 + S).
+// Column of blocks s:
+//   a. one wave factors the 16 x 16 diagonal block ("leaf") and inverts it;
+//      lanes own rows, values move between lanes with DPP row broadcasts
+//   b. the blocks below are solved against it: X_Rs = A_Rs W_ss^T (MFMA)
+//   c. the trailing blocks are updated, A_RT -= X_Rs X_Ts^T (MFMA); wave 0
+//      updates the next diagonal block first and goes on to factor it while
+//      the other waves finish the update
+// The inverse W = L^{-1} is then built block row by block row:
+//   W_rs = -W_rr (L_rs W_ss + sum_{s<t<r} L_rt W_ts),
+// all columns s of a block row at once, in place of L_rs.
+// ------------------------------------------------------------------------
+constexpr int kLB = 16;                          // leaf block
+constexpr int kNL = kNB / kLB;                   // 8 block rows
+constexpr int kNBlk = kNL * (kNL + 1) / 2;       // 36 lower blocks
+__device__ __forceinline__ int blk(int R, int S) { return (R * (R + 1) / 2 + S) * (kLB * kLB); }
 
-__device__ __forceinline__ void tile_of(int64_t t, bool lower, int tm, int &I, int &J)
+// value of v in lane c of this lane's row of 16 (DPP row_newbcast)
+template <typename T>
+__device__ __forceinline__ T rowbc(T v, int c)
 {
-    if (lower) {
+    switch (c) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x150, 0xF, 0xF, true);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x151, 0xF, 0xF, true);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x152, 0xF, 0xF, true);
+    case 3: return __builtin_amdgcn_mov_dpp(v, 0x153, 0xF, 0xF, true);
+    case 4: return __builtin_amdgcn_mov_dpp(v, 0x154, 0xF, 0xF, true);
+    case 5: return __builtin_amdgcn_mov_dpp(v, 0x155, 0xF, 0xF, true);
+    case 6: return __builtin_amdgcn_mov_dpp(v, 0x156, 0xF, 0xF, true);
+    case 7: return __builtin_amdgcn_mov_dpp(v, 0x157, 0xF, 0xF, true);
+    case 8: return __builtin_amdgcn_mov_dpp(v, 0x158, 0xF, 0xF, true);
+    case 9: return __builtin_amdgcn_mov_dpp(v, 0x159, 0xF, 0xF, true);
+    case 10: return __builtin_amdgcn_mov_dpp(v, 0x15A, 0xF, 0xF, true);
+    case 11: return __builtin_amdgcn_mov_dpp(v, 0x15B, 0xF, 0xF, true);
+    case 12: return __builtin_amdgcn_mov_dpp(v, 0x15C, 0xF, 0xF, true);
+    case 13: return __builtin_amdgcn_mov_dpp(v, 0x15D, 0xF, 0xF, true);
+    case 14: return __builtin_amdgcn_mov_dpp(v, 0x15E, 0xF, 0xF, true);
+    default: return __builtin_amdgcn_mov_dpp(v, 0x15F, 0xF, 0xF, true);
+    }
+}
+
+// One wave; lane r (mod 16) owns row r of the 16 x 16 block Lb (column-major,
+// lower triangle valid).  FACTOR: Cholesky in place (upper part written as
+// zero).  Then Wb = L^{-1} (lower, zero above).  Branch-free on lane-dependent
+// values: the rows of 16 lanes hold identical copies.
+template <typename T, bool FACTOR>
+__device__ __forceinline__ void leaf16(T *Lb, T *Wb, int32_t *info, int grow)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    T v[kLB], rd[kLB];
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kLB; ++c) v[c] = Lb[c * kLB + r];
+    if (FACTOR) {
+        int firstbad = -1;
+#pragma clang loop unroll(full)
+        for (int j = 0; j < kLB; ++j) {
+            T piv = rowbc(v[j], j);
+            firstbad = (firstbad < 0 && !(piv > T(0))) ? j : firstbad;
+            piv = (piv > T(0)) ? piv : T(1);
+            const T d = sqrt(piv);
+            rd[j] = T(1) / d;
+            const T lj = (r == j) ? d : v[j] * rd[j];   // rows above j: unused
+            v[j] = lj;
+#pragma clang loop unroll(full)
+            for (int c = j + 1; c < kLB; ++c) v[c] -= lj * rowbc(lj, c);
+        }
+        if (firstbad >= 0 && lane == 0 && *info == 0) *info = grow + firstbad + 1;
+    } else {
+#pragma clang loop unroll(full)
+        for (int j = 0; j < kLB; ++j) rd[j] = T(1) / rowbc(v[j], j);
+    }
+    // W = L^{-1}: row j of W is (raw row j) / L_jj; rows below subtract
+    // L_rj / L_jj times the raw row j.
+    T w[kLB];
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kLB; ++c) w[c] = (c == r) ? T(1) : T(0);
+#pragma clang loop unroll(full)
+    for (int j = 0; j < kLB; ++j) {
+        const T coef = (r > j) ? v[j] * rd[j] : T(0);
+#pragma clang loop unroll(full)
+        for (int c = 0; c <= j; ++c) w[c] -= coef * rowbc(w[c], j);
+    }
+    T rr = T(0);
+#pragma clang loop unroll(full)
+    for (int j = 0; j < kLB; ++j) rr = (r == j) ? rd[j] : rr;
+    if (lane < kLB) {
+#pragma clang loop unroll(full)
+        for (int c = 0; c < kLB; ++c) {
+            if (FACTOR) Lb[c * kLB + r] = (c <= r) ? v[c] : T(0);
+            Wb[c * kLB + r] = w[c] * rr;
+        }
+    }
+}
+
+// acc (16 x 16, MFMA output layout, transposed: see bstore) += op(P) op(Q),
+// op(P) = TA ? P^T : P, op(Q) = TB ? Q^T : Q; P, Q 16 x 16 column-major in
+// LDS.  The MFMA computes the transposed product (operands swapped) so that
+// lane l's outputs lie in row l % 16: stores are contiguous.
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ void bmm(typename Mfma4<T>::acc_t &acc, const T *P, const T *Q, int lane)
+{
+    const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int k0 = 0; k0 < kLB; k0 += 4) {
+        const int k = k0 + kq;
+        const T qa = TB ? Q[k * kLB + i] : Q[i * kLB + k];   // op(Q)[k][i]
+        const T pb = TA ? P[i * kLB + k] : P[k * kLB + i];   // op(P)[i][k]
+        acc = Mfma4<T>::run(qa, pb, acc);
+    }
+}
+// element (row, col) of the block held by lane l, register q
+template <typename T>
+__device__ __forceinline__ int bidx(int lane, int q) { return Mfma4<T>::row(lane, q) * kLB + (lane & 15); }
+
+template <typename T, bool FACTOR>
+__global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t lda, T *__restrict__ W,
+                                                   int32_t *__restrict__ info, int k0)
+{
+    typedef typename Mfma4<T>::acc_t acc_t;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T *L = reinterpret_cast<T *>(smem_raw);      // 36 blocks
+    T *Wd = L + kNBlk * kLB * kLB;               // 8 diagonal inverse blocks
+    T *Tw = Wd + kNL * kLB * kLB;                // one 16 x 16 scratch block per wave
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // several independent blocks (inverse only): block b of the grid
+    A += (int64_t)blockIdx.x * kNB * (lda + 1);
+    W += (int64_t)blockIdx.x * kNB * kNB;
+    k0 += blockIdx.x * kNB;
+
+    // load the lower blocks: thread = column c, 64 rows h*64.., 16-byte chunks
+    constexpr int VE = 16 / sizeof(T);           // elements per chunk
+    constexpr int NCH = 64 / VE;                 // chunks per thread
+    typedef u4_t v16_t;
+    const int c = tid >> 1, h = tid & 1;
+    const int cb = c / kLB;
+    {
+        v16_t buf[NCH];
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            const int r0 = h * 64 + q * VE;
+            if (r0 + VE - 1 >= cb * kLB) buf[q] = *reinterpret_cast<const v16_t *>(A + r0 + (int64_t)c * lda);
+        }
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            const int r0 = h * 64 + q * VE;
+            const int rb = r0 / kLB;
+            if (rb < cb) continue;
+            T *dst = L + blk(rb, cb) + (c % kLB) * kLB + (r0 % kLB);
+            if (rb > cb || r0 >= c) {
+                *reinterpret_cast<v16_t *>(dst) = buf[q];
+            } else {
+                // zero the rows above the diagonal with a bit mask on the whole chunk
+                u4_t m;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) m[e] = (r0 + e * 4 / (int)sizeof(T) >= c) ? ~0u : 0u;
+                *reinterpret_cast<v16_t *>(dst) = buf[q] & m;
+            }
+        }
+    }
+    __syncthreads();
+
+    if (FACTOR) {
+        if (wave == 0) leaf16<T, true>(L + blk(0, 0), Wd, info, k0);
+        __syncthreads();
+        for (int s = 0; s + 1 < kNL; ++s) {
+            // b. X_Rs = A_Rs W_ss^T
+            for (int R = s + 1 + wave; R < kNL; R += 4) {
+                acc_t acc = acc_t{0, 0, 0, 0};
+                bmm<T, false, true>(acc, L + blk(R, s), Wd + s * kLB * kLB, lane);
+                T *dst = L + blk(R, s);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dst[bidx<T>(lane, q)] = acc[q];
+            }
+            __syncthreads();
+            // c. A_RT -= X_Rs X_Ts^T; wave 0: next diagonal block, then its leaf
+            if (wave == 0) {
+                acc_t acc = acc_t{0, 0, 0, 0};
+                const T *X = L + blk(s + 1, s);
+                bmm<T, false, true>(acc, X, X, lane);
+                T *dst = L + blk(s + 1, s + 1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dst[bidx<T>(lane, q)] -= acc[q];
+                __builtin_amdgcn_wave_barrier();
+                leaf16<T, true>(L + blk(s + 1, s + 1), Wd + (s + 1) * kLB * kLB, info, k0 + (s + 1) * kLB);
+            } else {
+                const int n = kNL - 1 - s;                 // trailing block rows
+                int idx = 0;
+                for (int R = s + 1; R < kNL; ++R)
+                    for (int T2 = s + 1; T2 <= R; ++T2) {
+                        if (R == s + 1 && T2 == s + 1) continue;
+                        if (idx++ % 3 != wave - 1) continue;
+                        acc_t acc = acc_t{0, 0, 0, 0};
+                        bmm<T, false, true>(acc, L + blk(R, s), L + blk(T2, s), lane);
+                        T *dst = L + blk(R, T2);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dst[bidx<T>(lane, q)] -= acc[q];
+                    }
+                (void)n;
+            }
+            __syncthreads();
+        }
+        // L back to global memory, lower triangle only
+        for (int q = 0; q < NCH; ++q) {
+            const int r0 = h * 64 + q * VE;
+            const int rb = r0 / kLB;
+            if (rb < cb || r0 + VE - 1 < c) continue;
+            const T *src = L + blk(rb, cb) + (c % kLB) * kLB + (r0 % kLB);
+            T *dst = A + r0 + (int64_t)c * lda;
+            if (r0 >= c) {
+                *reinterpret_cast<v16_t *>(dst) = *reinterpret_cast<const v16_t *>(src);
+            } else {
+#pragma unroll
+                for (int u = 0; u < VE; ++u)
+                    if (r0 + u >= c) dst[u] = src[u];
+            }
+        }
+    } else {
+        // inverses of the given diagonal blocks, two per wave
+        leaf16<T, false>(L + blk(wave, wave), Wd + wave * kLB * kLB, nullptr, 0);
+        leaf16<T, false>(L + blk(wave + 4, wave + 4), Wd + (wave + 4) * kLB * kLB, nullptr, 0);
+        __syncthreads();
+    }
+
+    // inverse, block row by block row; wave w takes the columns s = w, w + 4
+    for (int r = 1; r < kNL; ++r) {
+        acc_t res[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int s = wave + 4 * u;
+            res[u] = acc_t{0, 0, 0, 0};
+            if (s >= r) continue;
+            acc_t acc = acc_t{0, 0, 0, 0};
+            bmm<T, false, false>(acc, L + blk(r, s), Wd + s * kLB * kLB, lane);
+            for (int t = s + 1; t < r; ++t) bmm<T, false, false>(acc, L + blk(r, t), L + blk(t, s), lane);
+            T *tw = Tw + wave * kLB * kLB;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tw[bidx<T>(lane, q)] = acc[q];
+            __builtin_amdgcn_wave_barrier();
+            bmm<T, false, false>(res[u], Wd + r * kLB * kLB, tw, lane);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int s = wave + 4 * u;
+            if (s >= r) continue;
+            T *dst = L + blk(r, s);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[bidx<T>(lane, q)] = -res[u][q];
+        }
+        __syncthreads();
+    }
+
+    // W (128 x 128, column-major, ld 128), zero above the diagonal
+    for (int q = 0; q < NCH; ++q) {
+        const int r0 = h * 64 + q * VE;
+        const int rb = r0 / kLB;
+        v16_t out = v16_t{0, 0, 0, 0};
+        if (rb >= cb) {
+            const T *src = (rb == cb ? Wd + cb * kLB * kLB : L + blk(rb, cb)) + (c % kLB) * kLB + (r0 % kLB);
+            out = *reinterpret_cast<const v16_t *>(src);
+        }
+        *reinterpret_cast<v16_t *>(W + r0 + (int64_t)c * kNB) = out;
+    }
+}
+
+// ------------------------------------------------------------------------
+// GEMM on 128 x 128 tiles: C -= A B^T (SUB) or C = A B^T, with A (M x K) and
+// B (N x K) column-major (rows contiguous).  256 threads = 4 waves of 64 x 64,
+// each 4 x 4 MFMA 16x16x4 blocks (f64 or f32).  K runs in chunks of 16 through
+// two LDS buffers; the next chunk is loaded into registers (16-byte loads)
+// while the MFMAs work on the current one.
+// Tiles: kTri = lower triangle of a square tile grid (linear index); kRect =
+// tm x tn grid.  MASK: the C origin lies on the matrix diagonal; tiles above
+// it are skipped and diagonal tiles keep rows >= columns only.
+// A may alias C (the in-place panel solve): a tile reads all of its A rows
+// before its epilogue writes them, and no other tile touches those rows.
+// ------------------------------------------------------------------------
+constexpr int kBM = 128, kBK = 16;
+constexpr int kLdsLd = kBM + 16;   // LDS row stride: the four k-rows of a fragment load hit distinct banks
+constexpr int kRect = 0, kTri = 1;
+
+__device__ __forceinline__ void tile_of(int64_t t, int mode, int tm, int &I, int &J)
+{
+    if (mode == kTri) {
         I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
         while ((int64_t)I * (I + 1) / 2 > t) --I;
         while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
@@ -295,20 +348,44 @@ __device__ __forceinline__ void tile_of(int64_t t, bool lower, int tm, int &I, i
     }
 }
 
-template <typename T, bool LOWER, bool BETA>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(int tm, int K, const T *__restrict__ A,
-                                                      int64_t lda, const T *__restrict__ B,
-                                                      int64_t ldb, T *__restrict__ C, int64_t ldc)
+template <typename T>
+static size_t gemm_smem_bytes() { return (size_t)2 * 2 * kBK * kLdsLd * sizeof(T); }
+
+// Epilogue: the old C values a wave needs are read with all loads in flight
+// at once (f32: prefetched before the K loop; f64: two batches), never one
+// read-modify-write at a time.  f64 runs the MFMA with the operands swapped
+// (it produces C^T), so that lane l's outputs lie in row l % 16 and every
+// access covers 16 consecutive rows.
+template <typename T, int MODE, bool MASK, bool SUB>
+__global__ __launch_bounds__(256) void gemm_kernel(int tm, int K, const T *A, int64_t lda, const T *B,
+                                                   int64_t ldb, T *C, int64_t ldc)
 {
     typedef typename Mfma4<T>::acc_t acc_t;
-    __shared__ T As[kBK][kBM + kLdsPad];
-    __shared__ T Bs[kBK][kBM + kLdsPad];
+    constexpr int LD = kLdsLd;
+    constexpr bool kF32 = Mfma4<T>::kConsecutiveRows;
+    constexpr bool kOld = SUB || MASK;            // old C values needed
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);   // [buf][operand][k][row]
     int I, J;
-    tile_of(blockIdx.x, LOWER, tm, I, J);
+    tile_of(blockIdx.x, MODE, tm, I, J);
+    if (MASK && I < J) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const T *Ab = A + (int64_t)I * kBM;
     const T *Bb = B + (int64_t)J * kBM;
+    const bool diag_tile = MASK && I == J;
+    const int row0 = I * kBM + wm * 64, col0 = J * kBM + wn * 64;
+
+    f4_t cpre[4][4];
+    if constexpr (kF32 && kOld) {
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                const int row = row0 + mi * 16 + 4 * (lane >> 4), col = col0 + ni * 16 + (lane & 15);
+                cpre[mi][ni] = *reinterpret_cast<const f4_t *>(C + row + (int64_t)col * ldc);
+            }
+    }
 
     acc_t acc[4][4];
 #pragma unroll
@@ -317,47 +394,113 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(int tm, int K, const T *__
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = acc_t{0, 0, 0, 0};
 
     const int lk = tid >> 4, lr = (tid & 15) * 8;   // loader: column lk, rows lr..lr+7
-    for (int k0 = 0; k0 < K; k0 += kBK) {
-        const T *pa = Ab + lr + (int64_t)(k0 + lk) * lda;
-        const T *pb = Bb + lr + (int64_t)(k0 + lk) * ldb;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            As[lk][lr + e] = pa[e];
-            Bs[lk][lr + e] = pb[e];
-        }
-        __syncthreads();
+    typedef u4_t v16_t;
+    constexpr int NV = 8 * sizeof(T) / 16;          // 16-byte chunks per 8 elements
+    v16_t ra[NV], rb[NV];
+#define GEMM_LOAD(k0)                                                                                \
+    do {                                                                                             \
+        const v16_t *pa = reinterpret_cast<const v16_t *>(Ab + lr + (int64_t)((k0) + lk) * lda);     \
+        const v16_t *pb = reinterpret_cast<const v16_t *>(Bb + lr + (int64_t)((k0) + lk) * ldb);     \
+        _Pragma("unroll") for (int e = 0; e < NV; ++e)                                               \
+        {                                                                                            \
+            ra[e] = pa[e];                                                                           \
+            rb[e] = pb[e];                                                                           \
+        }                                                                                            \
+    } while (0)
+#define GEMM_STORE(buf)                                                                              \
+    do {                                                                                             \
+        v16_t *sa = reinterpret_cast<v16_t *>(lds + (((buf) * 2 + 0) * kBK + lk) * LD + lr);         \
+        v16_t *sb = reinterpret_cast<v16_t *>(lds + (((buf) * 2 + 1) * kBK + lk) * LD + lr);         \
+        _Pragma("unroll") for (int e = 0; e < NV; ++e)                                               \
+        {                                                                                            \
+            sa[e] = ra[e];                                                                           \
+            sb[e] = rb[e];                                                                           \
+        }                                                                                            \
+    } while (0)
+    const int nk = K / kBK;
+    GEMM_LOAD(0);
+    GEMM_STORE(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        if (kc + 1 < nk) GEMM_LOAD((kc + 1) * kBK);
+        const T *As = lds + ((kc & 1) * 2 + 0) * kBK * LD;
+        const T *Bs = lds + ((kc & 1) * 2 + 1) * kBK * LD;
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             T af[4], bf[4];
 #pragma unroll
-            for (int mi = 0; mi < 4; ++mi) af[mi] = As[kk + (lane >> 4)][wm * 64 + mi * 16 + (lane & 15)];
+            for (int mi = 0; mi < 4; ++mi) af[mi] = As[(kk + (lane >> 4)) * LD + wm * 64 + mi * 16 + (lane & 15)];
 #pragma unroll
-            for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[kk + (lane >> 4)][wn * 64 + ni * 16 + (lane & 15)];
+            for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[(kk + (lane >> 4)) * LD + wn * 64 + ni * 16 + (lane & 15)];
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-                for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma4<T>::run(af[mi], bf[ni], acc[mi][ni]);
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = kF32 ? Mfma4<T>::run(af[mi], bf[ni], acc[mi][ni])
+                                       : Mfma4<T>::run(bf[ni], af[mi], acc[mi][ni]);
         }
+        if (kc + 1 < nk) GEMM_STORE((kc + 1) & 1);
         __syncthreads();
     }
+#undef GEMM_LOAD
+#undef GEMM_STORE
+
+    if constexpr (kF32) {
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
+        for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-            const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
+            for (int ni = 0; ni < 4; ++ni) {
+                const int row = row0 + mi * 16 + 4 * (lane >> 4), col = col0 + ni * 16 + (lane & 15);
+                f4_t v;
+                if constexpr (kOld) v = cpre[mi][ni];
+                else v = f4_t{0, 0, 0, 0};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = I * kBM + wm * 64 + mi * 16 + Mfma4<T>::row(lane, r);
-                if (LOWER && I == J && row < col) continue;
-                T *pc = C + row + (int64_t)col * ldc;
-                *pc = BETA ? *pc - acc[mi][ni][r] : acc[mi][ni][r];
+                for (int q = 0; q < 4; ++q) {
+                    const float x = SUB ? v[q] - (float)acc[mi][ni][q] : (float)acc[mi][ni][q];
+                    v[q] = (!diag_tile || row + q >= col) ? x : v[q];
+                }
+                *reinterpret_cast<f4_t *>(C + row + (int64_t)col * ldc) = v;
             }
+    } else {
+        // f64, C^T in the accumulators: row = row0 + mi*16 + lane%16,
+        // col = col0 + ni*16 + row(lane, q)
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            T old[2][4][4];
+            if constexpr (kOld) {
+#pragma unroll
+                for (int m2 = 0; m2 < 2; ++m2)
+#pragma unroll
+                    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int row = row0 + (half * 2 + m2) * 16 + (lane & 15);
+                            const int col = col0 + ni * 16 + Mfma4<T>::row(lane, q);
+                            old[m2][ni][q] = C[row + (int64_t)col * ldc];
+                        }
+            }
+#pragma unroll
+            for (int m2 = 0; m2 < 2; ++m2)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int mi = half * 2 + m2;
+                        const int row = row0 + mi * 16 + (lane & 15);
+                        const int col = col0 + ni * 16 + Mfma4<T>::row(lane, q);
+                        if (diag_tile && row < col) continue;
+                        const T a = acc[mi][ni][q];
+                        C[row + (int64_t)col * ldc] = SUB ? old[m2][ni][q] - a : a;
+                    }
         }
+    }
 }
 
 // ------------------------------------------------------------------------
-// 16-bit trailing update: C (FP32, column-major) -= P P^T with P stored
-// row-major in 16 bits (P[r * ldp + k]); v_mfma_f32_16x16x32, FP32 accumulate.
+// 16-bit outer trailing update: C (FP32, column-major) -= Q Q^T, Q stored
+// row-major in 16 bits with K contiguous (Q[r * ldq + k]);
+// v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation.  Same tiling, modes and
+// double-buffered K chunks (64) as gemm_kernel.
 // ------------------------------------------------------------------------
 template <typename H> struct Mfma32;
 template <> struct Mfma32<__bf16> {
@@ -376,18 +519,33 @@ template <> struct Mfma32<_Float16> {
 };
 
 constexpr int kBK16 = 64, kPad16 = 8;
+static size_t syrk16_smem_bytes() { return (size_t)2 * 2 * kBM * (kBK16 + kPad16) * 2; }
 
-template <typename H>
-__global__ __launch_bounds__(256) void syrk16_kernel(int K, const H *__restrict__ P, int64_t ldp,
+template <typename H, int MODE>
+__global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__restrict__ QA,
+                                                     const H *__restrict__ QB, int64_t ldq,
                                                      float *__restrict__ C, int64_t ldc)
 {
     typedef typename Mfma32<H>::frag_t frag_t;
-    __shared__ __attribute__((aligned(16))) H As[kBM][kBK16 + kPad16];
-    __shared__ __attribute__((aligned(16))) H Bs[kBM][kBK16 + kPad16];
+    constexpr int LD = kBK16 + kPad16;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    H *lds = reinterpret_cast<H *>(smem_raw);   // [buf][operand][row][k]
     int I, J;
-    tile_of(blockIdx.x, true, 0, I, J);
+    tile_of(blockIdx.x, MODE, tm, I, J);
+    if (I < J) return;                          // C origin on the diagonal in every use
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
+
+    // old C values, all loads in flight before the K loop
+    f4_t cpre[4][4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
+            const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4);
+            cpre[mi][ni] = *reinterpret_cast<const f4_t *>(C + row + (int64_t)col * ldc);
+        }
 
     f4_t acc[4][4];
 #pragma unroll
@@ -396,150 +554,271 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int K, const H *__restrict_
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f4_t{0, 0, 0, 0};
 
     const int lr = tid >> 1, lk = (tid & 1) * 32;   // loader: row lr, k lk..lk+31
-    for (int k0 = 0; k0 < K; k0 += kBK16) {
-        const uint4 *pa = reinterpret_cast<const uint4 *>(P + (int64_t)(I * kBM + lr) * ldp + k0 + lk);
-        const uint4 *pb = reinterpret_cast<const uint4 *>(P + (int64_t)(J * kBM + lr) * ldp + k0 + lk);
-        uint4 *sa = reinterpret_cast<uint4 *>(&As[lr][lk]);
-        uint4 *sb = reinterpret_cast<uint4 *>(&Bs[lr][lk]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            sa[e] = pa[e];
-            sb[e] = pb[e];
-        }
-        __syncthreads();
+    u4_t ra[4], rb[4];
+#define S16_LOAD(k0)                                                                                 \
+    do {                                                                                             \
+        const u4_t *pa = reinterpret_cast<const u4_t *>(QA + (int64_t)(I * kBM + lr) * ldq + (k0) + lk); \
+        const u4_t *pb = reinterpret_cast<const u4_t *>(QB + (int64_t)(J * kBM + lr) * ldq + (k0) + lk); \
+        _Pragma("unroll") for (int e = 0; e < 4; ++e)                                                \
+        {                                                                                            \
+            ra[e] = pa[e];                                                                           \
+            rb[e] = pb[e];                                                                           \
+        }                                                                                            \
+    } while (0)
+#define S16_STORE(buf)                                                                               \
+    do {                                                                                             \
+        u4_t *sa = reinterpret_cast<u4_t *>(lds + (((buf) * 2 + 0) * kBM + lr) * LD + lk);         \
+        u4_t *sb = reinterpret_cast<u4_t *>(lds + (((buf) * 2 + 1) * kBM + lr) * LD + lk);         \
+        _Pragma("unroll") for (int e = 0; e < 4; ++e)                                                \
+        {                                                                                            \
+            sa[e] = ra[e];                                                                           \
+            sb[e] = rb[e];                                                                           \
+        }                                                                                            \
+    } while (0)
+    const int nk = K / kBK16;
+    S16_LOAD(0);
+    S16_STORE(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        if (kc + 1 < nk) S16_LOAD((kc + 1) * kBK16);
+        const H *As = lds + ((kc & 1) * 2 + 0) * kBM * LD;
+        const H *Bs = lds + ((kc & 1) * 2 + 1) * kBM * LD;
 #pragma unroll
         for (int kk = 0; kk < kBK16; kk += 32) {
             frag_t af[4], bf[4];
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
-                af[mi] = *reinterpret_cast<const frag_t *>(&As[wm * 64 + mi * 16 + (lane & 15)][kk + 8 * (lane >> 4)]);
+                af[mi] = *reinterpret_cast<const frag_t *>(As + (wm * 64 + mi * 16 + (lane & 15)) * LD + kk + 8 * (lane >> 4));
 #pragma unroll
             for (int ni = 0; ni < 4; ++ni)
-                bf[ni] = *reinterpret_cast<const frag_t *>(&Bs[wn * 64 + ni * 16 + (lane & 15)][kk + 8 * (lane >> 4)]);
+                bf[ni] = *reinterpret_cast<const frag_t *>(Bs + (wn * 64 + ni * 16 + (lane & 15)) * LD + kk + 8 * (lane >> 4));
 #pragma unroll
             for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma32<H>::run(af[mi], bf[ni], acc[mi][ni]);
         }
+        if (kc + 1 < nk) S16_STORE((kc + 1) & 1);
         __syncthreads();
     }
+#undef S16_LOAD
+#undef S16_STORE
+    const bool diag_tile = I == J;
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
             const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
+            const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4);
+            f4_t v = cpre[mi][ni];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4) + r;
-                if (I == J && row < col) continue;
-                float *pc = C + row + (int64_t)col * ldc;
-                *pc = *pc - acc[mi][ni][r];
-            }
+            for (int q = 0; q < 4; ++q) v[q] = (!diag_tile || row + q >= col) ? v[q] - acc[mi][ni][q] : v[q];
+            *reinterpret_cast<f4_t *>(C + row + (int64_t)col * ldc) = v;
         }
 }
 
-// ------------------------------------------------------------------------
-// Step 3: copy the solved panel into A; optionally a 16-bit row-major copy.
-// ------------------------------------------------------------------------
-template <typename T, typename H>
-__global__ void panel_copy_kernel(const T *__restrict__ Pw, int64_t ldw, int m, T *__restrict__ A,
-                                  int64_t lda, H *__restrict__ P16)
+// Q16[(r - r0) * 256 + c] = L[r, c0 + c] for r in [r0, r0 + rows): 64-row
+// blocks transposed through LDS (coalesced reads down columns, 16-byte writes
+// along rows).
+constexpr int kOuter = 256;   // width of an outer panel
+
+template <typename H>
+__global__ __launch_bounds__(256) void panel16_kernel(const float *__restrict__ L, int64_t lda, int64_t r0,
+                                                      int64_t c0, int rows, H *__restrict__ Q)
 {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    int c = blockIdx.y;
-    if (r >= m) return;
-    T v = Pw[r + (int64_t)c * ldw];
-    A[r + (int64_t)c * lda] = v;
-    if (P16) P16[(int64_t)r * kNB + c] = (H)(float)v;
+    __shared__ __attribute__((aligned(16))) H t[64][kOuter + 8];
+    const int tid = threadIdx.x;
+    const int64_t rb = (int64_t)blockIdx.x * 64;
+    const int r = tid & 63;
+    for (int c = tid >> 6; c < kOuter; c += 4) {
+        const float v = (rb + r < rows) ? L[(r0 + rb + r) + (c0 + c) * lda] : 0.f;
+        t[r][c] = (H)v;
+    }
+    __syncthreads();
+    const int wr = tid >> 2, wc = (tid & 3) * 64;
+    if (rb + wr < rows) {
+        u4_t *dst = reinterpret_cast<u4_t *>(Q + (rb + wr) * kOuter + wc);
+        const u4_t *src = reinterpret_cast<const u4_t *>(&t[wr][wc]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[e] = src[e];
+    }
 }
 
 // ------------------------------------------------------------------------
 // host drivers
 // ------------------------------------------------------------------------
-static size_t diag_smem_bytes(size_t es) { return (size_t)(kNB * kLdsLd + kNB + kSB * (kSB + 1)) * es; }
+static size_t diag_smem_bytes(size_t es) { return (size_t)(kNBlk + kNL + 4) * kLB * kLB * es; }
 static size_t elem_size(int dtype) { return dtype == GBEM_F64 ? 8 : 4; }
 
 size_t chol_winv_bytes(int dtype, int64_t npad) { return (size_t)npad * kNB * elem_size(dtype); }
-size_t chol_panel_bytes(int dtype, int64_t npad) { return (size_t)npad * kNB * elem_size(dtype); }
+size_t chol_panel_bytes(int, int64_t) { return 64; }
 size_t chol_panel16_bytes(int dtype, int64_t npad)
 {
-    return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)npad * kNB * 2 : 0;
+    // two outer panels in flight (look-ahead): ping-pong buffers
+    return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)2 * npad * kOuter * 2 : 0;
 }
 
-template <typename T>
-static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, T *Pw, void *P16,
-                           int32_t *info, hipStream_t s, Prof *prof)
+template <typename T, int MODE, bool MASK, bool SUB>
+static hipError_t launch_gemm(int tm, int ntiles, int K, const T *A, int64_t lda, const T *B, int64_t ldb, T *C,
+                              int64_t ldc, hipStream_t s)
 {
-    const double es = (double)sizeof(T);
-    const double eo = (dtype == GBEM_F16 || dtype == GBEM_BF16) ? 2.0 : es;   // trailing-update operand size
-    const int nb = (int)(npad / kNB);
-    const size_t smem = diag_smem_bytes(sizeof(T));
-    hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, true>,
+    const size_t smem = gemm_smem_bytes<T>();
+    hipError_t e = hipFuncSetAttribute((const void *)gemm_kernel<T, MODE, MASK, SUB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    for (int k = 0; k < nb; ++k) {
-        const int64_t k0 = (int64_t)k * kNB;
-        T *Akk = A + k0 + k0 * lda;
+    hipLaunchKernelGGL((gemm_kernel<T, MODE, MASK, SUB>), dim3(ntiles), dim3(256), smem, s, tm, K, A, lda, B, ldb,
+                       C, ldc);
+    return hipGetLastError();
+}
+
+template <typename H, int MODE>
+static hipError_t launch_syrk16(int tm, int ntiles, int K, const H *QA, const H *QB, int64_t ldq, float *C,
+                                int64_t ldc, hipStream_t s)
+{
+    const size_t smem = syrk16_smem_bytes();
+    hipError_t e = hipFuncSetAttribute((const void *)syrk16_kernel<H, MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((syrk16_kernel<H, MODE>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc);
+    return hipGetLastError();
+}
+
+// Factor outer panel `p` (columns p*256 .. p*256+255, rows p*256 .. npad) with
+// 128-wide inner steps: diagonal block, in-place panel solve, update of the
+// panel's remaining columns.  For 16-bit dtypes the rows below the panel are
+// then copied into the row-major 16-bit buffer Q16.
+template <typename T>
+static hipError_t factor_panel(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
+                               int p, hipStream_t s, Prof *prof)
+{
+    const double es = (double)sizeof(T);
+    const int64_t P0 = (int64_t)p * kOuter;
+    for (int j = 0; j < kOuter / kNB; ++j) {
+        const int64_t k0 = P0 + (int64_t)j * kNB;
         int tok = prof ? prof->start(s) : -1;
-        hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), smem, s, Akk, lda,
-                           Winv + (int64_t)k * kNB * kNB, info, (int)k0);
+        hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
+                           A + k0 + k0 * lda, lda, Winv + k0 * kNB, info, (int)k0);
         if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
-        const int64_t m = npad - k0 - kNB;
-        if (m == 0) break;
-        const int tm = (int)(m / kBM);
+        const int64_t mb = npad - k0 - kNB;   // rows below the diagonal block
+        if (mb == 0) break;
+        const int tmb = (int)(mb / kBM);
         T *Pan = A + (k0 + kNB) + k0 * lda;
-        // panel <- A_panel W_k^T
         tok = prof ? prof->start(s) : -1;
-        hipLaunchKernelGGL((gemm_nt_kernel<T, false, false>), dim3(tm), dim3(256), 0, s, tm, kNB,
-                           (const T *)Pan, lda, (const T *)(Winv + (int64_t)k * kNB * kNB),
-                           (int64_t)kNB, Pw, (int64_t)npad);
-        if (dtype == GBEM_BF16)
-            hipLaunchKernelGGL((panel_copy_kernel<T, __bf16>), dim3((unsigned)((m + 255) / 256), kNB),
-                               dim3(256), 0, s, (const T *)Pw, (int64_t)npad, (int)m, Pan, lda,
-                               (__bf16 *)P16);
-        else if (dtype == GBEM_F16)
-            hipLaunchKernelGGL((panel_copy_kernel<T, _Float16>), dim3((unsigned)((m + 255) / 256), kNB),
-                               dim3(256), 0, s, (const T *)Pw, (int64_t)npad, (int)m, Pan, lda,
-                               (_Float16 *)P16);
-        else
-            hipLaunchKernelGGL((panel_copy_kernel<T, T>), dim3((unsigned)((m + 255) / 256), kNB),
-                               dim3(256), 0, s, (const T *)Pw, (int64_t)npad, (int)m, Pan, lda,
-                               (T *)nullptr);
-        if (prof)
-            prof->stop(tok, GBEM_K_TRSM, 2.0 * m * kNB * kNB,
-                       (double)m * kNB * (3.0 * es + (eo < es ? eo : 0.0)) + kNB * kNB * es, s, 2);
-        T *Trail = A + (k0 + kNB) + (k0 + kNB) * lda;
-        const int64_t ntiles = (int64_t)tm * (tm + 1) / 2;
-        tok = prof ? prof->start(s) : -1;
-        if (dtype == GBEM_BF16)
-            hipLaunchKernelGGL(syrk16_kernel<__bf16>, dim3((unsigned)ntiles), dim3(256), 0, s, kNB,
-                               (const __bf16 *)P16, (int64_t)kNB, (float *)Trail, lda);
-        else if (dtype == GBEM_F16)
-            hipLaunchKernelGGL(syrk16_kernel<_Float16>, dim3((unsigned)ntiles), dim3(256), 0, s, kNB,
-                               (const _Float16 *)P16, (int64_t)kNB, (float *)Trail, lda);
-        else
-            hipLaunchKernelGGL((gemm_nt_kernel<T, true, true>), dim3((unsigned)ntiles), dim3(256), 0, s,
-                               tm, kNB, (const T *)Pw, (int64_t)npad, (const T *)Pw, (int64_t)npad, Trail,
-                               lda);
-        if (prof) {
-            const double tile_el = (double)ntiles * kBM * kBM;
-            prof->stop(tok, GBEM_K_SYRK, 2.0 * tile_el * kNB, 2.0 * tile_el * es + (double)m * kNB * eo, s);
-        }
-        e = hipGetLastError();
+        hipError_t e = launch_gemm<T, kRect, false, false>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan,
+                                                           lda, s);
         if (e != hipSuccess) return e;
+        if (prof) prof->stop(tok, GBEM_K_TRSM, 2.0 * mb * kNB * kNB, 2.0 * mb * kNB * es + kNB * kNB * es, s);
+        if (j + 1 < kOuter / kNB) {
+            // remaining columns of this panel: A[k0+128:, k0+128:P0+256] -= L L^T
+            const int64_t ncols = P0 + kOuter - (k0 + kNB);
+            const int tn = (int)(ncols / kBM);
+            tok = prof ? prof->start(s) : -1;
+            e = launch_gemm<T, kRect, true, true>(tmb, tmb * tn, kNB, Pan, lda, Pan, lda,
+                                                  A + (k0 + kNB) + (k0 + kNB) * lda, lda, s);
+            if (e != hipSuccess) return e;
+            if (prof) prof->stop(tok, GBEM_K_SYRK, 2.0 * mb * ncols * kNB, 2.0 * mb * ncols * es, s);
+        }
+    }
+    const int64_t rows = npad - P0 - kOuter;
+    if (Q16 && rows > 0) {
+        int tok = prof ? prof->start(s) : -1;
+        if (dtype == GBEM_BF16)
+            hipLaunchKernelGGL(panel16_kernel<__bf16>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
+                               (const float *)A, lda, P0 + kOuter, P0, (int)rows, (__bf16 *)Q16);
+        else
+            hipLaunchKernelGGL(panel16_kernel<_Float16>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
+                               (const float *)A, lda, P0 + kOuter, P0, (int)rows, (_Float16 *)Q16);
+        if (prof) prof->stop(tok, GBEM_K_TRSM, 0.0, (double)rows * kOuter * (4.0 + 2.0), s);
     }
     return hipGetLastError();
 }
 
-hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *panel,
-                       void *panel16, int32_t *info, hipStream_t s, Prof *prof)
+// Outer update of columns [c0, c0 + ncols) of the trailing matrix with the
+// outer panel whose rows below it start at `qrow`: C = A[c0.., c0..] (origin
+// on the diagonal), rows m = npad - c0.  TRI when the block is square.
+template <typename T>
+static hipError_t outer_update(int dtype, int64_t npad, T *A, int64_t lda, int64_t P0, const void *Q16,
+                               int64_t c0, int64_t ncols, hipStream_t s, Prof *prof)
 {
-    if (npad % kNB) return hipErrorInvalidValue;
+    const int64_t m = npad - c0;
+    const int tm = (int)(m / kBM), tn = (int)(ncols / kBM);
+    const bool tri = ncols == m;
+    const int ntiles = tri ? tm * (tm + 1) / 2 : tm * tn;
+    T *C = A + c0 + c0 * lda;
+    const double es = (double)sizeof(T);
+    const bool b16 = dtype == GBEM_F16 || dtype == GBEM_BF16;
+    const double tiles_el = tri ? (double)tm * (tm + 1) / 2 * kBM * kBM : (double)m * ncols;
+    const int tok = prof ? prof->start(s) : -1;
+    hipError_t e;
+    if (!b16) {
+        const T *Q = A + c0 + P0 * lda;   // L[c0:, P0:P0+256], column-major
+        e = tri ? launch_gemm<T, kTri, true, true>(tm, ntiles, kOuter, Q, lda, Q, lda, C, lda, s)
+                : launch_gemm<T, kRect, true, true>(tm, ntiles, kOuter, Q, lda, Q, lda, C, lda, s);
+    } else {
+        const int64_t q0 = c0 - (P0 + kOuter);   // first row of Q16 used
+        if (dtype == GBEM_BF16) {
+            const __bf16 *Q = (const __bf16 *)Q16 + q0 * kOuter;
+            e = tri ? launch_syrk16<__bf16, kTri>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s)
+                    : launch_syrk16<__bf16, kRect>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s);
+        } else {
+            const _Float16 *Q = (const _Float16 *)Q16 + q0 * kOuter;
+            e = tri ? launch_syrk16<_Float16, kTri>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s)
+                    : launch_syrk16<_Float16, kRect>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s);
+        }
+    }
+    if (prof) prof->stop(tok, GBEM_K_SYRK, 2.0 * tiles_el * kOuter, 2.0 * tiles_el * es + (double)m * kOuter * (b16 ? 2.0 : es), s);
+    return e;
+}
+
+// Right-looking Cholesky with 256-wide outer panels and one panel of
+// look-ahead: after the outer update of the next panel's columns (main
+// stream), the next panel is factored on the side stream while the main
+// stream applies the rest of the outer update.
+template <typename T>
+static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
+                           hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
+{
+    const int nbo = (int)(npad / kOuter);
+    hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_smem_bytes(sizeof(T)));
+    if (e != hipSuccess) return e;
+    while ((int)ev.size() < 2 * nbo + 2) {
+        hipEvent_t x;
+        if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return e;
+        ev.push_back(x);
+    }
+    const bool b16 = dtype == GBEM_F16 || dtype == GBEM_BF16;
+    auto q16 = [&](int p) -> void * {
+        return b16 ? (void *)((char *)Q16 + (size_t)(p & 1) * npad * kOuter * 2) : nullptr;
+    };
+    if ((e = factor_panel<T>(dtype, npad, A, lda, Winv, q16(0), info, 0, s, prof)) != hipSuccess) return e;
+    for (int K = 0; K + 1 < nbo; ++K) {
+        const int64_t P0 = (int64_t)K * kOuter;
+        // (a) next panel's columns
+        if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), P0 + kOuter, kOuter, s, prof)) != hipSuccess)
+            return e;
+        if ((e = hipEventRecord(ev[2 * K], s)) != hipSuccess) return e;
+        // factor panel K+1 on the side stream
+        if ((e = hipStreamWaitEvent(side, ev[2 * K], 0)) != hipSuccess) return e;
+        if ((e = factor_panel<T>(dtype, npad, A, lda, Winv, q16(K + 1), info, K + 1, side, prof)) != hipSuccess)
+            return e;
+        if ((e = hipEventRecord(ev[2 * K + 1], side)) != hipSuccess) return e;
+        // (b) the rest of the trailing matrix
+        const int64_t c0 = P0 + 2 * kOuter;
+        if (c0 < npad)
+            if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), c0, npad - c0, s, prof)) != hipSuccess)
+                return e;
+        if ((e = hipStreamWaitEvent(s, ev[2 * K + 1], 0)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *, void *panel16,
+                       int32_t *info, hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
+{
+    if (npad % kOuter) return hipErrorInvalidValue;
     if (dtype == GBEM_F64)
-        return factor_t<double>(dtype, npad, (double *)A, lda, (double *)Winv, (double *)panel,
-                                nullptr, info, s, prof);
-    return factor_t<float>(dtype, npad, (float *)A, lda, (float *)Winv, (float *)panel, panel16,
-                           info, s, prof);
+        return factor_t<double>(dtype, npad, (double *)A, lda, (double *)Winv, nullptr, info, s, side, ev, prof);
+    return factor_t<float>(dtype, npad, (float *)A, lda, (float *)Winv, panel16, info, s, side, ev, prof);
 }
 
 template <typename T>
@@ -549,10 +828,9 @@ static hipError_t diag_inverses_t(int64_t npad, const T *L, int64_t lda, T *Winv
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    for (int64_t k0 = 0; k0 < npad; k0 += kNB)
-        hipLaunchKernelGGL((diag_kernel<T, false>), dim3(1), dim3(256), smem, s,
-                           const_cast<T *>(L) + k0 + k0 * lda, lda, Winv + k0 * kNB, (int32_t *)nullptr,
-                           (int)k0);
+    // the diagonal blocks are independent: one workgroup each
+    hipLaunchKernelGGL((diag_kernel<T, false>), dim3((unsigned)(npad / kNB)), dim3(256), smem, s,
+                       const_cast<T *>(L), lda, Winv, (int32_t *)nullptr, 0);
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ namespace gbem {
 // identity block, so the factorisation and solves need no edge cases.
 constexpr int kFarTile = 64;
 constexpr int kNB = 128;          // Cholesky block (diagonal block lives in LDS)
-constexpr int kPad = 128;         // padding of the matrix order
+constexpr int kPad = 256;         // padding of the matrix order (one outer Cholesky panel)
 constexpr int kMaxOrder = 8;      // largest Gauss order of the far rule
 constexpr int kMaxRhs = 64;       // right-hand sides handled per solve pass
 
@@ -145,8 +145,10 @@ hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule 
                       int far_dtype, double *A, int64_t lda, hipStream_t s);
 
 // chol.hip
+// side: second stream for the look-ahead panel factorisation; ev: event pool
 hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *panel,
-                       void *panel16, int32_t *info, hipStream_t s, Prof *prof = nullptr);
+                       void *panel16, int32_t *info, hipStream_t s, hipStream_t side,
+                       std::vector<hipEvent_t> &ev, Prof *prof = nullptr);
 // Synchronisation words of the persistent triangular solves (device arrays of
 // npad/128 flags per direction, zeroed once when allocated).  err[0] is the
 // error word (zeroed by the caller before a solve, read back after it);
