@@ -206,6 +206,297 @@ __global__ __launch_bounds__(256) void bwd_solve_kernel(const T *__restrict__ L,
     publish(flags + k, epoch);
 }
 
+// ------------------------------------------------------------------------
+// FP32 storage (the low-precision factors): the same persistent scheme with
+// the block products on MFMA (v_mfma_f32_16x16x4f32, FP32 accumulation; the
+// solve only has to match the precision of the factor, the FP64 refinement
+// supplies the rest).  Per workgroup:
+//   - 128 x 128 tiles of L (then W_k) stream through one LDS tile; the next
+//     tile is loaded into registers while the MFMAs work on the current one;
+//   - published blocks are read and written with agent-scope atomic loads and
+//     stores (they bypass the non-coherent per-XCD L2), so publishing needs
+//     only the completion of those stores before the flag, and consuming needs
+//     no cache invalidation;
+//   - a published block k implies that every block before it (in solve
+//     order) is published, so one observed flag covers all earlier blocks.
+// Waves split the 128-long inner dimension (and the rows when MC = 64); their
+// partial sums are added through LDS once per block row.
+// ------------------------------------------------------------------------
+template <int MC, bool FWD> struct SolveCfg {
+    static constexpr int CB = MC / 16;                 // 16-column blocks of the RHS
+    static constexpr int NKG = MC <= 32 ? 4 : 2;      // wave groups over the inner dimension
+    static constexpr int NRG = 4 / NKG;               // wave groups over the rows
+    static constexpr int RB = 8 / NRG;                // 16-row blocks per wave
+    static constexpr int KW = kNB / NKG;              // inner range per wave
+    static constexpr int TLD = FWD ? 144 : 132;       // LDS tile stride (conflict-free fragment reads)
+    static constexpr int YLD = MC == 16 ? 16 : (MC == 32 ? 48 : 80);
+    static constexpr int RLD = MC + 4;                // partial-sum stride
+    static constexpr int EPT = kNB * MC / 256;        // (row, column) elements per thread
+    static constexpr size_t kTileBytes = (size_t)kNB * 144 * 4;
+    static constexpr size_t kSmem = kTileBytes + (size_t)2 * kNB * YLD * 4 + 64;
+};
+typedef float f4s_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u4s_t __attribute__((ext_vector_type(4)));
+
+// 128 x 128 block at P (column-major, ld) -> registers: thread = column c,
+// rows h*64 .. h*64+63 as 16-byte chunks
+__device__ __forceinline__ void tile_load(u4s_t (&tr)[16], const float *P, int64_t ld)
+{
+    const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
+    const u4s_t *src = reinterpret_cast<const u4s_t *>(P + h * 64 + (int64_t)c * ld);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tr[q] = src[q];
+}
+template <int TLD>
+__device__ __forceinline__ void tile_store(float *tile, const u4s_t (&tr)[16])
+{
+    const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
+    u4s_t *dst = reinterpret_cast<u4s_t *>(tile + c * TLD + h * 64);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dst[q] = tr[q];
+}
+
+// acc[rb][cb] += A(i, t) Y(t, n) over this wave's inner range; A(i, t) =
+// tile[t*TLD + i] (FWD: L_kj, W_k) or tile[i*TLD + t] (BWD: L_jk^T, W_k^T)
+template <int MC, bool FWD, int RB, int CB>
+__device__ __forceinline__ void tile_product(f4s_t (&acc)[RB][CB], const float *tile, const float *ys)
+{
+    typedef SolveCfg<MC, FWD> C;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rg = w % C::NRG, kg = w / C::NRG;
+#pragma unroll 4
+    for (int kk = 0; kk < C::KW; kk += 4) {
+        const int t = kg * C::KW + kk + (lane >> 4);
+        float b[C::CB];
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb) b[cb] = ys[t * C::YLD + cb * 16 + (lane & 15)];
+#pragma unroll
+        for (int rb = 0; rb < C::RB; ++rb) {
+            const int i = (rg * C::RB + rb) * 16 + (lane & 15);
+            const float a = FWD ? tile[t * C::TLD + i] : tile[i * C::TLD + t];
+#pragma unroll
+            for (int cb = 0; cb < C::CB; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[cb], acc[rb][cb], 0, 0, 0);
+        }
+    }
+}
+
+// partial sums of all waves -> red (reusing the tile), then each thread adds
+// the groups for its elements e = tid + 256 u: row e % 128, column e / 128
+template <int MC, bool FWD, int EPT, int RB, int CB>
+__device__ __forceinline__ void reduce_partials(float (&out)[EPT], f4s_t (&acc)[RB][CB], float *red)
+{
+    typedef SolveCfg<MC, FWD> C;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rg = w % C::NRG, kg = w / C::NRG;
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = (rg * C::RB + rb) * 16 + 4 * (lane >> 4) + q, n = cb * 16 + (lane & 15);
+                red[(kg * kNB + row) * C::RLD + n] = acc[rb][cb][q];
+            }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
+        float s = 0.f;
+#pragma unroll
+        for (int g = 0; g < C::NKG; ++g) s += red[(g * kNB + row) * C::RLD + n];
+        out[u] = s;
+    }
+}
+
+template <int MC, bool FWD>
+__global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__ L, int64_t lda,
+                                                       const float *__restrict__ W, double *B, int64_t ldb, int m,
+                                                       int nb, int32_t *flags, int32_t *__restrict__ counter,
+                                                       uint32_t base, int32_t epoch, int32_t *err, int limit)
+{
+    typedef SolveCfg<MC, FWD> C;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    float *tile = reinterpret_cast<float *>(smem_raw);
+    float *ysb = reinterpret_cast<float *>(smem_raw + C::kTileBytes);   // two Y buffers
+    int *ready_s = reinterpret_cast<int *>(smem_raw + C::kTileBytes + (size_t)2 * kNB * C::YLD * 4);
+    const int tk = take_ticket(counter, base);
+    if (tk < 0 || tk >= nb) {
+        if (threadIdx.x == 0) __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    // solve order: FWD blocks 0, 1, ..; BWD blocks nb-1, nb-2, ..
+    const int k = FWD ? tk : nb - 1 - tk, k0 = k * kNB;
+    const int cnt = tk;                                  // blocks this one depends on
+    auto jof = [&](int idx) { return FWD ? idx : nb - 1 - idx; };
+    // block of the matrix multiplying Y_j: FWD L[k, j] at (k0, j0); BWD L[j, k] at (j0, k0)
+    auto lblock = [&](int j) -> const float * {
+        return FWD ? L + k0 + (int64_t)j * kNB * lda : L + (int64_t)j * kNB + (int64_t)k0 * lda;
+    };
+    const float *Wk = W + (int64_t)k * kNB * kNB;
+
+    // right-hand side of this block (read once, FP64)
+    double bk[C::EPT];
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
+        bk[u] = n < m ? B[(k0 + row) + (int64_t)n * ldb] : 0.0;
+    }
+
+    // wait until the idx-th block in solve order is published (thread 0
+    // polls; the observed index is shared through LDS)
+    int ready = -1;
+    auto ensure_ready = [&](int idx) -> bool {
+        if (idx <= ready) return true;
+        if (threadIdx.x == 0) {
+            int got = -2;
+            if (wait_flag(flags + jof(idx), epoch, err, limit)) {
+                got = idx;
+                // blocks are published in solve order: probe further ahead
+                // (all loads in flight at once) and keep the newest published
+                int32_t f[8];
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const int q = min(cnt - 1, idx + (1 << (p + 1)) - 1);
+                    f[p] = __hip_atomic_load(flags + jof(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+                for (int p = 0; p < 8; ++p)
+                    if (f[p] == epoch) got = max(got, min(cnt - 1, idx + (1 << (p + 1)) - 1));
+            }
+            *ready_s = got;
+        }
+        __syncthreads();
+        ready = *ready_s;
+        return ready >= idx;
+    };
+    // Y_j (FP64, published) -> registers
+    auto y_load = [&](double (&yr)[C::EPT], int j) {
+#pragma unroll
+        for (int u = 0; u < C::EPT; ++u) {
+            const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
+            yr[u] = n < m ? __hip_atomic_load(B + (j * kNB + row) + (int64_t)n * ldb, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : 0.0;
+        }
+    };
+    auto y_store = [&](float *ys, const double (&yr)[C::EPT]) {
+#pragma unroll
+        for (int u = 0; u < C::EPT; ++u) {
+            const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
+            ys[row * C::YLD + n] = (float)yr[u];
+        }
+    };
+
+    f4s_t acc[C::RB][C::CB];
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb) acc[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
+
+    u4s_t tr[16];
+    double yr[C::EPT];
+    bool ok = true;
+    if (cnt > 0) {
+        tile_load(tr, lblock(jof(0)), lda);
+        ok = ensure_ready(0);
+        if (ok) y_load(yr, jof(0));
+        tile_store<C::TLD>(tile, tr);
+        y_store(ysb, yr);
+        tile_load(tr, cnt > 1 ? lblock(jof(1)) : Wk, cnt > 1 ? lda : (int64_t)kNB);
+        __syncthreads();
+        for (int idx = 0; idx < cnt && ok; ++idx) {
+            const bool more = idx + 1 < cnt;
+            // the next Y block: loaded ahead of the product when already
+            // published, else waited for after it
+            const bool early = more && idx + 1 <= ready;
+            if (early) y_load(yr, jof(idx + 1));
+            tile_product<MC, FWD>(acc, tile, ysb + (idx & 1) * kNB * C::YLD);
+            if (more && !early) {
+                ok = ensure_ready(idx + 1);
+                if (ok) y_load(yr, jof(idx + 1));
+            }
+            __syncthreads();
+            tile_store<C::TLD>(tile, tr);
+            if (more) {
+                y_store(ysb + ((idx + 1) & 1) * kNB * C::YLD, yr);
+                if (idx + 2 < cnt) tile_load(tr, lblock(jof(idx + 2)), lda);
+                else tile_load(tr, Wk, kNB);
+            }
+            __syncthreads();
+        }
+        if (!ok) return;   // error word set; the host reports it
+        // tile holds L of the last block or W_k: W_k is in tr when cnt > 0
+    } else {
+        tile_load(tr, Wk, kNB);
+    }
+    // r = B_k - sum_j (...) Y_j  -> ys[0]
+    float part[C::EPT];
+    __syncthreads();
+    reduce_partials<MC, FWD>(part, acc, tile);
+    float *ys = ysb;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
+        ys[row * C::YLD + n] = (float)(bk[u] - (double)part[u]);
+    }
+    tile_store<C::TLD>(tile, tr);   // W_k
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < C::CB; ++cb) acc[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
+    tile_product<MC, FWD>(acc, tile, ys);
+    __syncthreads();
+    reduce_partials<MC, FWD>(part, acc, tile);
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
+        if (n < m)
+            __hip_atomic_store(B + (k0 + row) + (int64_t)n * ldb, (double)part[u], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the stores above complete before the flag is raised
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + k, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int MC>
+static hipError_t solve32_mc(int64_t npad, const float *L, int64_t lda, const float *W, int m, double *B,
+                             int64_t ldb, SolveSync &sync, hipStream_t s, Prof *prof)
+{
+    const int nb = (int)(npad / kNB);
+    const size_t smem = SolveCfg<MC, true>::kSmem;
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)tsolve32_kernel<MC, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)) != hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)tsolve32_kernel<MC, false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)SolveCfg<MC, false>::kSmem)) !=
+            hipSuccess)
+        return e;
+    const int limit = 1 << 26;
+    const size_t smem_b = SolveCfg<MC, false>::kSmem;
+    ++sync.epoch;
+    const int tok = prof ? prof->start(s) : -1;
+    hipLaunchKernelGGL((tsolve32_kernel<MC, true>), dim3(nb), dim3(256), smem, s, L, lda, W, B, ldb, m, nb,
+                       sync.flags_f, sync.err + 1, sync.base_f, sync.epoch, sync.err, limit);
+    hipLaunchKernelGGL((tsolve32_kernel<MC, false>), dim3(nb), dim3(256), smem_b, s, L, lda, W, B, ldb, m, nb,
+                       sync.flags_b, sync.err + 2, sync.base_b, sync.epoch, sync.err, limit);
+    if (prof) {
+        const double lbytes = (double)npad * (npad + kNB) / 2.0 * 4.0;
+        prof->stop(tok, GBEM_K_SOLVE, 2.0 * 2.0 * (double)npad * npad / 2.0 * m,
+                   2.0 * lbytes + 2.0 * npad * kNB * 4.0 + 4.0 * npad * m * 8.0, s, 2);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        sync.base_f += (uint32_t)nb;
+        sync.base_b += (uint32_t)nb;
+    }
+    return e;
+}
+
 template <typename T, int MC>
 static hipError_t solve_mc(int64_t npad, const T *L, int64_t lda, const T *W, int m, double *B, int64_t ldb,
                            SolveSync &sync, hipStream_t s, Prof *prof)
@@ -255,7 +546,10 @@ hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const
     if (npad % kNB || m > kMaxRhs || m <= 0) return hipErrorInvalidValue;
     if (dtype == GBEM_F64)
         return solve_t<double>(npad, (const double *)L, lda, (const double *)Winv, m, B, ldb, sync, s, prof);
-    return solve_t<float>(npad, (const float *)L, lda, (const float *)Winv, m, B, ldb, sync, s, prof);
+    const float *Lf = (const float *)L, *Wf = (const float *)Winv;
+    if (m <= 16) return solve32_mc<16>(npad, Lf, lda, Wf, m, B, ldb, sync, s, prof);
+    if (m <= 32) return solve32_mc<32>(npad, Lf, lda, Wf, m, B, ldb, sync, s, prof);
+    return solve32_mc<64>(npad, Lf, lda, Wf, m, B, ldb, sync, s, prof);
 }
 
 // ------------------------------------------------------------------------

@@ -103,6 +103,26 @@ def test_cholesky_solve_sizes_interleaved(ctx):
         assert rel_err(Bt.cpu().numpy().T, np.linalg.solve(A, B0)) < 1e-10
 
 
+@pytest.mark.parametrize("n,r", [(500, 1), (1000, 10), (700, 17), (600, 40), (520, 64)])
+def test_cholesky_solve_f32_storage(ctx, n, r):
+    """Solves with an FP32 factor (MFMA block products, FP32 accumulation):
+    compared with the exact solution for that factor, at FP32 accuracy, over
+    tile counts with a ragged tail and every right-hand-side width class."""
+    import torch
+    say(f"cholesky solve f32 n={n} r={r}")
+    rng = np.random.default_rng(n + r)
+    M = rng.standard_normal((n, n))
+    A = M @ M.T / n + np.eye(n)
+    L32 = np.linalg.cholesky(A).astype(np.float32)
+    L = torch.tensor(L32.T.copy(), device="cuda")                       # column-major L
+    Bt = torch.tensor(rng.standard_normal((r, n)), device="cuda")       # column-major n x r
+    B0 = Bt.cpu().numpy().T.copy()
+    ctx.cholesky_solve_device(L.T, Bt.T, "f32")
+    L64 = L32.astype(np.float64)
+    X = Bt.cpu().numpy().T
+    assert rel_err(X, np.linalg.solve(L64 @ L64.T, B0)) < 2e-5
+
+
 def test_cholesky_reports_indefinite(ctx):
     import torch
     n = 200
