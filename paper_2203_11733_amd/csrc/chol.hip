@@ -14,6 +14,8 @@
 // v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
 #include "gbem_internal.h"
 
+#include <type_traits>
+
 namespace gbem {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -356,9 +358,14 @@ static size_t gemm_smem_bytes() { return (size_t)2 * 2 * kBK * kLdsLd * sizeof(T
 // read-modify-write at a time.  f64 runs the MFMA with the operands swapped
 // (it produces C^T), so that lane l's outputs lie in row l % 16 and every
 // access covers 16 consecutive rows.
-template <typename T, int MODE, bool MASK, bool SUB>
+// Q16 (f32 only; 1: bf16, 2: f16): the tile is also written, rounded to 16
+// bits, row-major into Q (row stride 256): tile row R goes to Q row R + qrow
+// (skipped when negative), tile column c to Q column qcol + c.  The tile is
+// transposed through LDS so that Q is written 16 bytes at a time.
+template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
 __global__ __launch_bounds__(256) void gemm_kernel(int tm, int K, const T *A, int64_t lda, const T *B,
-                                                   int64_t ldb, T *C, int64_t ldc)
+                                                   int64_t ldb, T *C, int64_t ldc, void *Q = nullptr, int qrow = 0,
+                                                   int qcol = 0)
 {
     typedef typename Mfma4<T>::acc_t acc_t;
     constexpr int LD = kLdsLd;
@@ -460,7 +467,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(int tm, int K, const T *A, in
                     v[q] = (!diag_tile || row + q >= col) ? x : v[q];
                 }
                 *reinterpret_cast<f4_t *>(C + row + (int64_t)col * ldc) = v;
+                if constexpr (Q16 != 0) {
+                    typedef typename std::conditional<Q16 == 1, __bf16, _Float16>::type H;
+                    H *t16 = reinterpret_cast<H *>(smem_raw);   // LDS is free after the K loop
+                    const int rl = row - I * kBM, cl = col - J * kBM;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) t16[(rl + q) * (kBM + 8) + cl] = (H)v[q];
+                }
             }
+        if constexpr (Q16 != 0) {
+            typedef typename std::conditional<Q16 == 1, __bf16, _Float16>::type H;
+            const H *t16 = reinterpret_cast<const H *>(smem_raw);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = tid + 256 * u, rl = idx >> 4, cc = (idx & 15) * 8;
+                const int64_t qr = (int64_t)I * kBM + rl + qrow;
+                if (qr >= 0)
+                    *reinterpret_cast<u4_t *>(reinterpret_cast<H *>(Q) + qr * 256 + qcol + J * kBM + cc) =
+                        *reinterpret_cast<const u4_t *>(t16 + rl * (kBM + 8) + cc);
+            }
+        }
     } else {
         // f64, C^T in the accumulators: row = row0 + mi*16 + lane%16,
         // col = col0 + ni*16 + row(lane, q)
@@ -616,32 +643,7 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
         }
 }
 
-// Q16[(r - r0) * 256 + c] = L[r, c0 + c] for r in [r0, r0 + rows): 64-row
-// blocks transposed through LDS (coalesced reads down columns, 16-byte writes
-// along rows).
 constexpr int kOuter = 256;   // width of an outer panel
-
-template <typename H>
-__global__ __launch_bounds__(256) void panel16_kernel(const float *__restrict__ L, int64_t lda, int64_t r0,
-                                                      int64_t c0, int rows, H *__restrict__ Q)
-{
-    __shared__ __attribute__((aligned(16))) H t[64][kOuter + 8];
-    const int tid = threadIdx.x;
-    const int64_t rb = (int64_t)blockIdx.x * 64;
-    const int r = tid & 63;
-    for (int c = tid >> 6; c < kOuter; c += 4) {
-        const float v = (rb + r < rows) ? L[(r0 + rb + r) + (c0 + c) * lda] : 0.f;
-        t[r][c] = (H)v;
-    }
-    __syncthreads();
-    const int wr = tid >> 2, wc = (tid & 3) * 64;
-    if (rb + wr < rows) {
-        u4_t *dst = reinterpret_cast<u4_t *>(Q + (rb + wr) * kOuter + wc);
-        const u4_t *src = reinterpret_cast<const u4_t *>(&t[wr][wc]);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) dst[e] = src[e];
-    }
-}
 
 // ------------------------------------------------------------------------
 // host drivers
@@ -657,16 +659,16 @@ size_t chol_panel16_bytes(int dtype, int64_t npad)
     return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)2 * npad * kOuter * 2 : 0;
 }
 
-template <typename T, int MODE, bool MASK, bool SUB>
+template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
 static hipError_t launch_gemm(int tm, int ntiles, int K, const T *A, int64_t lda, const T *B, int64_t ldb, T *C,
-                              int64_t ldc, hipStream_t s)
+                              int64_t ldc, hipStream_t s, void *Q = nullptr, int qrow = 0, int qcol = 0)
 {
     const size_t smem = gemm_smem_bytes<T>();
-    hipError_t e = hipFuncSetAttribute((const void *)gemm_kernel<T, MODE, MASK, SUB>,
+    hipError_t e = hipFuncSetAttribute((const void *)gemm_kernel<T, MODE, MASK, SUB, Q16>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((gemm_kernel<T, MODE, MASK, SUB>), dim3(ntiles), dim3(256), smem, s, tm, K, A, lda, B, ldb,
-                       C, ldc);
+    hipLaunchKernelGGL((gemm_kernel<T, MODE, MASK, SUB, Q16>), dim3(ntiles), dim3(256), smem, s, tm, K, A, lda, B,
+                       ldb, C, ldc, Q, qrow, qcol);
     return hipGetLastError();
 }
 
@@ -703,10 +705,22 @@ static hipError_t factor_panel(int dtype, int64_t npad, T *A, int64_t lda, T *Wi
         const int tmb = (int)(mb / kBM);
         T *Pan = A + (k0 + kNB) + k0 * lda;
         tok = prof ? prof->start(s) : -1;
-        hipError_t e = launch_gemm<T, kRect, false, false>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan,
-                                                           lda, s);
+        // panel solve in place; for 16-bit dtypes the rows below the outer
+        // panel also go to Q16 (row r -> Q16 row r - P0 - 256, column j*128 + c)
+        const int qrow = (int)(k0 + kNB - (P0 + kOuter)), qcol = j * kNB;
+        hipError_t e;
+        if (Q16 && dtype == GBEM_BF16)
+            e = launch_gemm<T, kRect, false, false, 1>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan, lda, s,
+                                                       Q16, qrow, qcol);
+        else if (Q16 && dtype == GBEM_F16)
+            e = launch_gemm<T, kRect, false, false, 2>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan, lda, s,
+                                                       Q16, qrow, qcol);
+        else
+            e = launch_gemm<T, kRect, false, false>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan, lda, s);
         if (e != hipSuccess) return e;
-        if (prof) prof->stop(tok, GBEM_K_TRSM, 2.0 * mb * kNB * kNB, 2.0 * mb * kNB * es + kNB * kNB * es, s);
+        if (prof)
+            prof->stop(tok, GBEM_K_TRSM, 2.0 * mb * kNB * kNB,
+                       2.0 * mb * kNB * es + kNB * kNB * es + (Q16 ? 2.0 * mb * kNB : 0.0), s);
         if (j + 1 < kOuter / kNB) {
             // remaining columns of this panel: A[k0+128:, k0+128:P0+256] -= L L^T
             const int64_t ncols = P0 + kOuter - (k0 + kNB);
@@ -717,17 +731,6 @@ static hipError_t factor_panel(int dtype, int64_t npad, T *A, int64_t lda, T *Wi
             if (e != hipSuccess) return e;
             if (prof) prof->stop(tok, GBEM_K_SYRK, 2.0 * mb * ncols * kNB, 2.0 * mb * ncols * es, s);
         }
-    }
-    const int64_t rows = npad - P0 - kOuter;
-    if (Q16 && rows > 0) {
-        int tok = prof ? prof->start(s) : -1;
-        if (dtype == GBEM_BF16)
-            hipLaunchKernelGGL(panel16_kernel<__bf16>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
-                               (const float *)A, lda, P0 + kOuter, P0, (int)rows, (__bf16 *)Q16);
-        else
-            hipLaunchKernelGGL(panel16_kernel<_Float16>, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
-                               (const float *)A, lda, P0 + kOuter, P0, (int)rows, (_Float16 *)Q16);
-        if (prof) prof->stop(tok, GBEM_K_TRSM, 0.0, (double)rows * kOuter * (4.0 + 2.0), s);
     }
     return hipGetLastError();
 }

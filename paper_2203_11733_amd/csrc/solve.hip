@@ -16,7 +16,7 @@
 // the backward pass walks down columns (contiguous per lane).
 //
 // Residual: R = B - A X with the FP64 matrix (row i of the symmetric A is read
-// as column i).  The j range is split over kResSplit workgroups per row block;
+// as column i).  The j range is split over several workgroups per row block;
 // partial sums are added in a fixed order by a second kernel.
 #include "gbem_internal.h"
 
@@ -553,49 +553,93 @@ hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const
 }
 
 // ------------------------------------------------------------------------
-// Residual R = B - A X, split over j.
+// Residual R = B - A X, split over j.  Row i of the symmetric A is read as
+// column i (contiguous in j).  A workgroup takes 128 values of i (32 per
+// wave) and a range of j; each wave multiplies on v_mfma_f64_16x16x4f64
+// without LDS or barriers: the summation index is permuted so that lane l
+// (k-slot q = l / 16) reads the 8 consecutive j = j0 + 8q .. j0 + 8q + 7 of
+// a 32-long chunk as four 16-byte loads, from A (column i0 + l % 16) and from
+// X (column c0 + l % 16) alike; the next chunk is loaded while the current
+// one is multiplied.  With X as the first operand the outputs of lane l lie
+// in row i0 + l % 16, so partial sums are stored 16 rows at a time.
 // ------------------------------------------------------------------------
-constexpr int kRRows = 64, kRChunk = 32, kRPerThread = kMaxRhs / 4;
+constexpr int kRRows = 128, kRChunk = 32;
+typedef double d4r_t __attribute__((ext_vector_type(4)));
+typedef double d2r_t __attribute__((ext_vector_type(2)));
 
+template <int MC>
 __global__ __launch_bounds__(256) void residual_partial_kernel(const double *__restrict__ A, int64_t lda,
                                                                int npad, const double *__restrict__ X,
                                                                int64_t ldx, int m, int jspan,
                                                                double *__restrict__ P)
 {
-    __shared__ double as[kRRows][kRChunk + 1];    // as[i][jj] = A[j0 + jj, i0 + i]
-    __shared__ double xs[kRChunk][kMaxRhs + 1];   // xs[jj][c] = X[j0 + jj, c]
-    const int tid = threadIdx.x, il = tid & 63, g = tid >> 6;
-    const int i0 = blockIdx.x * kRRows, s = blockIdx.y;
+    constexpr int CB = MC / 16;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane >> 4, li = lane & 15;
+    const int i0 = blockIdx.x * kRRows + w * 32, s = blockIdx.y;
     const int jb = s * jspan, je = min(npad, jb + jspan);
-    double acc[kRPerThread];
+    d4r_t acc[2][CB];
 #pragma unroll
-    for (int q = 0; q < kRPerThread; ++q) acc[q] = 0.0;
-    // loader: column i0 + tid/4, 8 contiguous rows
-    const int lc = tid >> 2, lr = (tid & 3) * 8;
-    for (int j0 = jb; j0 < je; j0 += kRChunk) {
-        const double *src = A + (j0 + lr) + (int64_t)(i0 + lc) * lda;
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) as[lc][lr + e] = src[e];
-        for (int idx = tid; idx < kRChunk * m; idx += 256) {
-            const int jj = idx % kRChunk, c = idx / kRChunk;
-            xs[jj][c] = X[(j0 + jj) + (int64_t)c * ldx];
-        }
-        __syncthreads();
-        for (int jj = 0; jj < kRChunk; ++jj) {
-            const double a = as[il][jj];
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = d4r_t{0, 0, 0, 0};
+    if (jb >= je) {
+        // empty range: zero partials keep the fixed-order sum exact
+    } else {
+        d2r_t ra[2][2][4], rx[2][CB][4];   // [buffer][block][16-byte piece]
+        auto load = [&](int buf, int j0) __attribute__((always_inline)) {
+            const int j = j0 + 8 * q;
 #pragma unroll
-            for (int q = 0; q < kRPerThread; ++q) {
-                const int c = g + 4 * q;
-                if (c < m) acc[q] = __builtin_fma(a, xs[jj][c], acc[q]);
+            for (int rb = 0; rb < 2; ++rb) {
+                const d2r_t *pa = reinterpret_cast<const d2r_t *>(A + j + (int64_t)(i0 + rb * 16 + li) * lda);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ra[buf][rb][e] = pa[e];
             }
-        }
-        __syncthreads();
-    }
 #pragma unroll
-    for (int q = 0; q < kRPerThread; ++q) {
-        const int c = g + 4 * q;
-        if (c < m) P[((int64_t)s * m + c) * npad + i0 + il] = acc[q];
+            for (int cb = 0; cb < CB; ++cb) {
+                const int c = cb * 16 + li;
+                if (c < m) {
+                    const d2r_t *px = reinterpret_cast<const d2r_t *>(X + j + (int64_t)c * ldx);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) rx[buf][cb][e] = px[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) rx[buf][cb][e] = d2r_t{0, 0};
+                }
+            }
+        };
+        auto mult = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(rx[buf][cb][e][h], ra[buf][rb][e][h],
+                                                                               acc[rb][cb], 0, 0, 0);
+        };
+        load(0, jb);
+        // two chunks per trip: the register buffers are indexed by constants
+        for (int j0 = jb; j0 < je; j0 += 2 * kRChunk) {
+            if (j0 + kRChunk < je) load(1, j0 + kRChunk);
+            mult(0);
+            if (j0 + kRChunk >= je) break;
+            if (j0 + 2 * kRChunk < je) load(0, j0 + 2 * kRChunk);
+            mult(1);
+        }
     }
+    // lane l, register r: row i0 + rb*16 + l%16, column cb*16 + l/16 + 4r
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = cb * 16 + q + 4 * r;
+                if (c < m) P[((int64_t)s * m + c) * npad + i0 + rb * 16 + li] = acc[rb][cb][r];
+            }
 }
 
 __global__ void residual_finish_kernel(const double *__restrict__ P, int nsplit, int npad, int m,
@@ -614,11 +658,16 @@ int residual_splits(int npad) { return max(1, min(kResMaxSplit, npad / 2048)); }
 hipError_t launch_residual(const double *A, int64_t lda, int npad, const double *X, int64_t ldx, const double *B,
                            int64_t ldb, int m, double *R, int64_t ldr, double *partial, hipStream_t st)
 {
-    if (npad % kRRows || m > kMaxRhs) return hipErrorInvalidValue;
+    if (npad % kRRows || m > kMaxRhs || m <= 0) return hipErrorInvalidValue;
     const int ns = residual_splits(npad);
     const int jspan = (int)round_up((npad + ns - 1) / ns, kRChunk);
-    hipLaunchKernelGGL(residual_partial_kernel, dim3(npad / kRRows, ns), dim3(256), 0, st, A, lda, npad, X, ldx, m,
-                       jspan, partial);
+    const dim3 grid(npad / kRRows, ns);
+    if (m <= 16)
+        hipLaunchKernelGGL(residual_partial_kernel<16>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
+    else if (m <= 32)
+        hipLaunchKernelGGL(residual_partial_kernel<32>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
+    else
+        hipLaunchKernelGGL(residual_partial_kernel<64>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
     hipLaunchKernelGGL(residual_finish_kernel, dim3((npad + 255) / 256, m), dim3(256), 0, st, partial, ns, npad, m, B,
                        ldb, R, ldr);
     return hipGetLastError();

@@ -220,6 +220,26 @@ def test_capacitance_mixed_vs_oracle(ctx, factor):
     assert rep["residual"] <= 1e-8
 
 
+@pytest.mark.parametrize("layout,factor", [
+    (gi.crossing_bars_in_box(), "bf16"),
+    (gi.three_layer_bus(n_per_layer=8, h=0.25), "f16"),
+    (gi.three_layer_bus(n_per_layer=16, h=0.3), "f32"),
+], ids=["bars_in_box-bf16", "bus24-f16", "bus48-f32"])
+def test_refinement_reaches_f64_solution(ctx, layout, factor):
+    """Same FP64 matrix, low-precision factor + FP64 refinement: the charges
+    converge to the all-FP64 solution (exercises the FP32 solves and the FP64
+    residual for 2, 24 and 48 right-hand sides)."""
+    lo, hi, cond = mesh(layout)
+    m = layout.n_conductors
+    C64, _ = ctx.extract(lo, hi, cond, m, layout.eps_r, layout.length_unit_m, binding.make_opts())
+    o = binding.make_opts(3, 2.0, "f64", factor, 1e-12, 60)
+    C, rep = ctx.extract(lo, hi, cond, m, layout.eps_r, layout.length_unit_m, o)
+    say(f"  {layout.name} N={lo.shape[0]} M={m} {factor}: rel {rel_err(C, C64):.3e} "
+        f"iters {rep['refine_iters']} resid {rep['residual']:.2e}")
+    assert rep["residual"] <= 1e-12
+    assert rel_err(C, C64) < 1e-9
+
+
 def test_invalid_inputs(ctx):
     lay = gi.two_plates(h=0.5)
     lo, hi, cond = mesh(lay)
