@@ -94,7 +94,7 @@ struct DevBuf {
 
 struct Workspace {
     DevBuf lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, D, s, partial, C,
-        flags, norms, sflags, rpart;
+        flags, norms, sflags, rpart, semi;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool events_ok = false;
     SolveSync sync;
@@ -131,7 +131,7 @@ struct Workspace {
     size_t bytes() const
     {
         const DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
-                               &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart};
+                               &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi};
         size_t t = 0;
         for (auto *b : all) t += b->cap;
         return t;
@@ -139,7 +139,7 @@ struct Workspace {
     void release_all()
     {
         DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
-                         &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart};
+                         &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi};
         for (auto *b : all) b->release();
     }
     hipError_t init_events()
@@ -171,7 +171,7 @@ static size_t footprint(int64_t n, int m, int factor_dtype)
     const size_t es = factor_dtype == GBEM_F64 ? 8 : 4;
     b += (size_t)npad * kNB * es + (size_t)npad * 256 * 2 * 2;           // W, 16-bit panels
     b += 4 * (size_t)npad * m * 8 + (size_t)npad * 8;                    // B X R D, s
-    b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 8;            // mesh, panels, near list
+    b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 12;           // mesh, panels, near list + queue
     return b;
 }
 
@@ -299,6 +299,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
 
     HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near rows");
     HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
+    HIPCHK(ws.semi.ensure(near_semi_bytes(nnz)), "alloc near queue");
     tok = pf.start(st);
     HIPCHK(launch_near_fill(dlo, dhi, n, eta2, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
                             ws.ncol.as<int32_t>(), st), "near_fill");
@@ -316,7 +317,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     }
     tok = pf.start(st);
     HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
-                            A, lda, st), "near_eval");
+                            A, lda, ws.semi.as<int32_t>(), st), "near_eval");
     pf.stop(tok, GBEM_K_NEAR_EVAL, 0.0, (double)nnz * (2 * 8 + 2 * 4 + 2 * 48), st);
     HIPCHK(hipEventRecord(ws.ev[1], st), "hipEventRecord");
     if (rep) {

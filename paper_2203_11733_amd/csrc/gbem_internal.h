@@ -135,10 +135,12 @@ hipError_t launch_exclusive_scan(const int64_t *cnt, int n, int64_t *row_ptr, hi
 hipError_t launch_near_fill(const double *lo, const double *hi, int n, double eta2,
                             const int64_t *row_ptr, int32_t *row, int32_t *col, hipStream_t s);
 
-// near_eval.hip: closed-form Galerkin integrals of the near pairs
+// near_eval.hip: closed-form Galerkin integrals of the near pairs.
+// semi_buf: near_semi_bytes(nnz) bytes of scratch (queue of semi-analytic pairs)
 hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
                             const int32_t *row, const int32_t *col, int64_t nnz, double *A,
-                            int64_t lda, hipStream_t s);
+                            int64_t lda, int32_t *semi_buf, hipStream_t s);
+inline size_t near_semi_bytes(int64_t nnz) { return (size_t)(64 + nnz) * sizeof(int32_t); }
 
 // far.hip
 hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule &rule,

@@ -95,45 +95,6 @@ __device__ __forceinline__ double corner_potential(double u, double v, double w)
     return t;
 }
 
-// Int over rectangle (lj, hj) with normal nj of 1/|x - y| dy.
-__device__ double rect_potential(const double *x, const double *lj, const double *hj, int nj)
-{
-    const int t1 = nj == 0 ? 1 : 0, t2 = nj == 2 ? 1 : 2;
-    const double w = x[nj] - lj[nj];
-    const double u[2] = {lj[t1] - x[t1], hj[t1] - x[t1]};
-    const double v[2] = {lj[t2] - x[t2], hj[t2] - x[t2]};
-    double s = 0.0;
-    for (int a = 0; a < 2; ++a)
-        for (int c = 0; c < 2; ++c) {
-            const double f = corner_potential(u[a], v[c], w);
-            s += ((a + c) & 1) ? -f : f;
-        }
-    return s;
-}
-
-// Gauss rule over the small panel (ls, hs, normal ns) of the potential of the
-// big one; returns Int Int 1/|x-y|.
-__device__ double pair_integral_semi(const double *ls, const double *hs, int ns, const double *lb,
-                                     const double *hb, int nb, const NearRule &g)
-{
-    const int t1 = ns == 0 ? 1 : 0, t2 = ns == 2 ? 1 : 2;
-    const double c1 = 0.5 * (ls[t1] + hs[t1]), h1 = 0.5 * (hs[t1] - ls[t1]);
-    const double c2 = 0.5 * (ls[t2] + hs[t2]), h2 = 0.5 * (hs[t2] - ls[t2]);
-    double x[3];
-    x[ns] = ls[ns];
-    double acc = 0.0;
-    for (int a = 0; a < kNearOrder; ++a) {
-        x[t1] = c1 + h1 * g.x[a];
-        double in = 0.0;
-        for (int b = 0; b < kNearOrder; ++b) {
-            x[t2] = c2 + h2 * g.x[b];
-            in += g.w[b] * rect_potential(x, lb, hb, nb);
-        }
-        acc += g.w[a] * in;
-    }
-    return acc * (4.0 * h1 * h2);
-}
-
 // Int_{I_i} Int_{I_j} 1/|x-y| for axis-aligned rectangles given by lo/hi.
 __device__ double pair_integral_closed(const double *li, const double *hi_, int ni,
                                        const double *lj, const double *hj, int nj)
@@ -203,46 +164,138 @@ __device__ bool use_semi(const double *li, const double *hi_, const double *lj, 
     return gap2 >= 2.25 * ms * ms;
 }
 
+// Gauss rule of the semi-analytic route (set before each launch; the same
+// values every time)
+__constant__ NearRule c_near;
+
+// component k of a 3-vector without a dynamic index (keeps it in registers)
+__device__ __forceinline__ double comp(const double *v, int k) { return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]); }
+
+// Pass 1: one thread per near pair.  Pairs on the closed-form route are
+// evaluated here; semi-analytic pairs are queued (wave-aggregated slots) for
+// pass 2, so that their 100-point rule does not stall the closed-form lanes
+// of the same wave.
 __global__ __launch_bounds__(256) void near_eval_kernel(const double *__restrict__ lo,
                                                         const double *__restrict__ hi,
                                                         const Panel *__restrict__ pan,
                                                         const int32_t *__restrict__ row,
                                                         const int32_t *__restrict__ col,
                                                         int64_t nnz, double *__restrict__ A,
-                                                        int64_t lda, NearRule g)
+                                                        int64_t lda, int32_t *__restrict__ semi_list,
+                                                        int32_t *__restrict__ semi_count)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nnz) return;
-    const int i = row[t], j = col[t];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = t < nnz;
+    int i = 0, j = 0;
     double li[3], hi_[3], lj[3], hj[3];
-    for (int k = 0; k < 3; ++k) {
-        li[k] = lo[3 * i + k];
-        hi_[k] = hi[3 * i + k];
-        lj[k] = lo[3 * j + k];
-        hj[k] = hi[3 * j + k];
+    bool semi = false, small_is_i = true;
+    if (live) {
+        i = row[t];
+        j = col[t];
+        for (int k = 0; k < 3; ++k) {
+            li[k] = lo[3 * i + k];
+            hi_[k] = hi[3 * i + k];
+            lj[k] = lo[3 * j + k];
+            hj[k] = hi[3 * j + k];
+        }
+        semi = use_semi(li, hi_, lj, hj, small_is_i);
     }
-    const int ni = pan[i].nrm, nj = pan[j].nrm;
-    bool small_is_i = true;
-    double G;
-    if (use_semi(li, hi_, lj, hj, small_is_i))
-        G = small_is_i ? pair_integral_semi(li, hi_, ni, lj, hj, nj, g)
-                       : pair_integral_semi(lj, hj, nj, li, hi_, ni, g);
-    else
-        G = pair_integral_closed(li, hi_, ni, lj, hj, nj);
+    const unsigned long long ballot = __ballot(semi);
+    if (ballot) {
+        const int lane = threadIdx.x & 63;
+        int base = 0;
+        if (lane == __ffsll((long long)ballot) - 1) base = atomicAdd(semi_count, __popcll(ballot));
+        base = __shfl(base, __ffsll((long long)ballot) - 1);
+        if (semi) semi_list[base + __popcll(ballot & ((1ull << lane) - 1))] = (int32_t)t;
+    }
+    if (!live || semi) return;
+    const double G = pair_integral_closed(li, hi_, pan[i].nrm, lj, hj, pan[j].nrm);
     const double a = G / (4.0 * M_PI * pan[i].area * pan[j].area);
     A[i + j * lda] = a;
     A[j + i * lda] = a;
 }
 
+// Pass 2: one wave per queued pair.  The 100 Gauss points x 4 corners of the
+// rectangle potential are spread over the lanes and summed by a fixed
+// butterfly, so the value does not depend on scheduling.
+__global__ __launch_bounds__(256) void near_semi_kernel(const double *__restrict__ lo,
+                                                        const double *__restrict__ hi,
+                                                        const Panel *__restrict__ pan,
+                                                        const int32_t *__restrict__ row,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ semi_list,
+                                                        const int32_t *__restrict__ semi_count,
+                                                        double *__restrict__ A, int64_t lda)
+{
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
+    const int count = *semi_count;
+    for (int p = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < count; p += nwaves) {
+        const int64_t t = semi_list[p];
+        const int i = row[t], j = col[t];
+        double li[3], hi_[3], lj[3], hj[3];
+        for (int k = 0; k < 3; ++k) {
+            li[k] = lo[3 * i + k];
+            hi_[k] = hi[3 * i + k];
+            lj[k] = lo[3 * j + k];
+            hj[k] = hi[3 * j + k];
+        }
+        bool small_is_i = true;
+        (void)use_semi(li, hi_, lj, hj, small_is_i);
+        double ls[3], hs[3], lb[3], hb[3];
+        for (int k = 0; k < 3; ++k) {
+            ls[k] = small_is_i ? li[k] : lj[k];
+            hs[k] = small_is_i ? hi_[k] : hj[k];
+            lb[k] = small_is_i ? lj[k] : li[k];
+            hb[k] = small_is_i ? hj[k] : hi_[k];
+        }
+        const int ns = small_is_i ? pan[i].nrm : pan[j].nrm, nb = small_is_i ? pan[j].nrm : pan[i].nrm;
+        const int t1 = ns == 0 ? 1 : 0, t2 = ns == 2 ? 1 : 2;
+        const double c1 = 0.5 * (comp(ls, t1) + comp(hs, t1)), h1 = 0.5 * (comp(hs, t1) - comp(ls, t1));
+        const double c2 = 0.5 * (comp(ls, t2) + comp(hs, t2)), h2 = 0.5 * (comp(hs, t2) - comp(ls, t2));
+        const double xn = comp(ls, ns);
+        const int b1 = nb == 0 ? 1 : 0, b2 = nb == 2 ? 1 : 2;
+        const double lbn = comp(lb, nb);
+        double acc = 0.0;
+        for (int e = lane; e < kNearOrder * kNearOrder * 4; e += 64) {
+            const int pt = e >> 2, a = pt / kNearOrder, b = pt % kNearOrder, ca = (e >> 1) & 1, cc = e & 1;
+            const double xa = c1 + h1 * c_near.x[a], xb = c2 + h2 * c_near.x[b];
+            // point x: coordinate ns = xn, t1 = xa, t2 = xb
+            double x[3];
+            for (int k = 0; k < 3; ++k) x[k] = k == ns ? xn : (k == t1 ? xa : xb);
+            const double w = comp(x, nb) - lbn;
+            const double u = (ca ? comp(hb, b1) : comp(lb, b1)) - comp(x, b1);
+            const double v = (cc ? comp(hb, b2) : comp(lb, b2)) - comp(x, b2);
+            const double f = corner_potential(u, v, w);
+            acc += c_near.w[a] * c_near.w[b] * (((ca + cc) & 1) ? -f : f);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) {
+            const double a = acc * (4.0 * h1 * h2) / (4.0 * M_PI * pan[i].area * pan[j].area);
+            A[i + j * lda] = a;
+            A[j + i * lda] = a;
+        }
+    }
+}
+
 hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
                             const int32_t *row, const int32_t *col, int64_t nnz, double *A,
-                            int64_t lda, hipStream_t s)
+                            int64_t lda, int32_t *semi_buf, hipStream_t s)
 {
     if (nnz <= 0) return hipSuccess;
     NearRule g;
     gauss_legendre(kNearOrder, g.x, g.w);
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_near), &g, sizeof(g), 0, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    int32_t *count = semi_buf, *list = semi_buf + 64;
+    e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(near_eval_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, lo, hi,
-                       pan, row, col, nnz, A, lda, g);
+                       pan, row, col, nnz, A, lda, list, count);
+    const int64_t waves = std::min<int64_t>(nnz, 4096);
+    hipLaunchKernelGGL(near_semi_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, lo, hi, pan, row, col,
+                       list, count, A, lda);
     return hipGetLastError();
 }
 
