@@ -37,7 +37,8 @@ PEAK_TFLOPS = {"mfma_bf16": 2500.0, "mfma_f16": 2500.0, "mfma_f32": 157.3, "mfma
 # source file of each kernel class (the counters of a committed PMC summary
 # only apply while that file is unchanged)
 CLASS_SOURCE = {"far": "far.hip", "near_list": "near.hip", "near_eval": "near_eval.hip", "diag": "chol.hip",
-                "trsm": "chol.hip", "syrk": "chol.hip", "solve": "solve.hip", "residual": "solve.hip"}
+                "trsm": "chol.hip", "syrk": "chol.hip", "panel": "chol.hip", "solve": "solve.hip",
+                "residual": "solve.hip"}
 
 
 def compute_peak(cls, mode):
@@ -229,6 +230,8 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="replay the seeded serving stream (256 jobs, Poisson 50 jobs/s) instead")
     ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
@@ -308,6 +311,14 @@ def main():
         "roofline": roofline_of(profile, args.mode, lay.name),
         "f64_reference_ms": rep64["t_total_ms"],
     }
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 256 MiB read + 256 MiB written per launch
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(lo, hi, cond, lay, args.p, args.eta)

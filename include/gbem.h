@@ -93,11 +93,12 @@ enum {
     GBEM_K_NEAR_EVAL = 2,   /* closed-form near entries */
     GBEM_K_DIAG = 3,        /* 128 x 128 diagonal-block Cholesky + inverse */
     GBEM_K_TRSM = 4,        /* panel solve (GEMM with the block inverse) + copy */
-    GBEM_K_SYRK = 5,        /* trailing update (MFMA) */
+    GBEM_K_SYRK = 5,        /* trailing update of the matrix beyond the next panel (MFMA) */
     GBEM_K_SOLVE = 6,       /* triangular solves */
     GBEM_K_RESIDUAL = 7,    /* FP64 residual of the refinement */
-    GBEM_K_OTHER = 8,
-    GBEM_K_COUNT = 9
+    GBEM_K_PANEL = 8,       /* updates inside and of the next outer panel (look-ahead path) */
+    GBEM_K_OTHER = 9,
+    GBEM_K_COUNT = 10
 };
 
 typedef struct {

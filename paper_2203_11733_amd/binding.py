@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_PKG, "libgbem.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTPD, ENOCONV, EBUSY, ETIMEOUT = range(8)
 F64, F32, F16, BF16 = range(4)
-KERNEL_CLASSES = ["far", "near_list", "near_eval", "diag", "trsm", "syrk", "solve", "residual", "other"]
+KERNEL_CLASSES = ["far", "near_list", "near_eval", "diag", "trsm", "syrk", "solve", "residual", "panel", "other"]
+NCLS = len(KERNEL_CLASSES)   # GBEM_K_COUNT
 DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 
 EXPORTS = [
@@ -53,8 +54,8 @@ class Report(ctypes.Structure):
                 ("residual", ctypes.c_double), ("asym", ctypes.c_double),
                 ("refine_iters", ctypes.c_int32), ("factor_used", ctypes.c_int32),
                 ("n_near", ctypes.c_int64), ("n_panels", ctypes.c_int64),
-                ("prof_ms", ctypes.c_double * 9), ("prof_launches", ctypes.c_int64 * 9),
-                ("prof_flops", ctypes.c_double * 9), ("prof_bytes", ctypes.c_double * 9)]
+                ("prof_ms", ctypes.c_double * NCLS), ("prof_launches", ctypes.c_int64 * NCLS),
+                ("prof_flops", ctypes.c_double * NCLS), ("prof_bytes", ctypes.c_double * NCLS)]
 
     def as_dict(self):
         d = {}

@@ -729,7 +729,7 @@ static hipError_t factor_panel(int dtype, int64_t npad, T *A, int64_t lda, T *Wi
             e = launch_gemm<T, kRect, true, true>(tmb, tmb * tn, kNB, Pan, lda, Pan, lda,
                                                   A + (k0 + kNB) + (k0 + kNB) * lda, lda, s);
             if (e != hipSuccess) return e;
-            if (prof) prof->stop(tok, GBEM_K_SYRK, 2.0 * mb * ncols * kNB, 2.0 * mb * ncols * es, s);
+            if (prof) prof->stop(tok, GBEM_K_PANEL, 2.0 * mb * ncols * kNB, 2.0 * mb * ncols * es, s);
         }
     }
     return hipGetLastError();
@@ -740,7 +740,7 @@ static hipError_t factor_panel(int dtype, int64_t npad, T *A, int64_t lda, T *Wi
 // on the diagonal), rows m = npad - c0.  TRI when the block is square.
 template <typename T>
 static hipError_t outer_update(int dtype, int64_t npad, T *A, int64_t lda, int64_t P0, const void *Q16,
-                               int64_t c0, int64_t ncols, hipStream_t s, Prof *prof)
+                               int64_t c0, int64_t ncols, hipStream_t s, Prof *prof, int cls)
 {
     const int64_t m = npad - c0;
     const int tm = (int)(m / kBM), tn = (int)(ncols / kBM);
@@ -768,7 +768,7 @@ static hipError_t outer_update(int dtype, int64_t npad, T *A, int64_t lda, int64
                     : launch_syrk16<_Float16, kRect>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s);
         }
     }
-    if (prof) prof->stop(tok, GBEM_K_SYRK, 2.0 * tiles_el * kOuter, 2.0 * tiles_el * es + (double)m * kOuter * (b16 ? 2.0 : es), s);
+    if (prof) prof->stop(tok, cls, 2.0 * tiles_el * kOuter, 2.0 * tiles_el * es + (double)m * kOuter * (b16 ? 2.0 : es), s);
     return e;
 }
 
@@ -797,7 +797,8 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     for (int K = 0; K + 1 < nbo; ++K) {
         const int64_t P0 = (int64_t)K * kOuter;
         // (a) next panel's columns
-        if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), P0 + kOuter, kOuter, s, prof)) != hipSuccess)
+        if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), P0 + kOuter, kOuter, s, prof, GBEM_K_PANEL)) !=
+            hipSuccess)
             return e;
         if ((e = hipEventRecord(ev[2 * K], s)) != hipSuccess) return e;
         // factor panel K+1 on the side stream
@@ -808,7 +809,8 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
         // (b) the rest of the trailing matrix
         const int64_t c0 = P0 + 2 * kOuter;
         if (c0 < npad)
-            if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), c0, npad - c0, s, prof)) != hipSuccess)
+            if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), c0, npad - c0, s, prof, GBEM_K_SYRK)) !=
+                hipSuccess)
                 return e;
         if ((e = hipStreamWaitEvent(s, ev[2 * K + 1], 0)) != hipSuccess) return e;
     }
