@@ -169,20 +169,17 @@ __device__ __forceinline__ void bmm(typename Mfma4<T>::acc_t &acc, const T *P, c
 template <typename T>
 __device__ __forceinline__ int bidx(int lane, int q) { return Mfma4<T>::row(lane, q) * kLB + (lane & 15); }
 
+// One 128 x 128 diagonal block by the whole workgroup (256 threads); lds:
+// diag_smem_bytes(sizeof(T)) bytes of LDS.
 template <typename T, bool FACTOR>
-__global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t lda, T *__restrict__ W,
-                                                   int32_t *__restrict__ info, int k0)
+__device__ __forceinline__ void diag_block(T *__restrict__ A, int64_t lda, T *__restrict__ W,
+                                           int32_t *__restrict__ info, int k0, unsigned char *lds)
 {
     typedef typename Mfma4<T>::acc_t acc_t;
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    T *L = reinterpret_cast<T *>(smem_raw);      // 36 blocks
+    T *L = reinterpret_cast<T *>(lds);           // 36 blocks
     T *Wd = L + kNBlk * kLB * kLB;               // 8 diagonal inverse blocks
     T *Tw = Wd + kNL * kLB * kLB;                // one 16 x 16 scratch block per wave
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // several independent blocks (inverse only): block b of the grid
-    A += (int64_t)blockIdx.x * kNB * (lda + 1);
-    W += (int64_t)blockIdx.x * kNB * kNB;
-    k0 += blockIdx.x * kNB;
 
     // load the lower blocks: thread = column c, 64 rows h*64.., 16-byte chunks
     constexpr int VE = 16 / sizeof(T);           // elements per chunk
@@ -321,6 +318,16 @@ __global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t ld
     }
 }
 
+template <typename T, bool FACTOR>
+__global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t lda, T *__restrict__ W,
+                                                   int32_t *__restrict__ info, int k0)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    // several independent blocks (inverse only): block b of the grid
+    diag_block<T, FACTOR>(A + (int64_t)blockIdx.x * kNB * (lda + 1), lda, W + (int64_t)blockIdx.x * kNB * kNB, info,
+                          k0 + blockIdx.x * kNB, smem_raw);
+}
+
 // ------------------------------------------------------------------------
 // GEMM on 128 x 128 tiles: C -= A B^T (SUB) or C = A B^T, with A (M x K) and
 // B (N x K) column-major (rows contiguous).  256 threads = 4 waves of 64 x 64,
@@ -334,19 +341,43 @@ __global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t ld
 // before its epilogue writes them, and no other tile touches those rows.
 // ------------------------------------------------------------------------
 constexpr int kBM = 128, kBK = 16;
+constexpr int kOuter = 256;   // width of an outer panel (K of the trailing update)
 constexpr int kLdsLd = kBM + 16;   // LDS row stride: the four k-rows of a fragment load hit distinct banks
 constexpr int kRect = 0, kTri = 1;
 
-__device__ __forceinline__ void tile_of(int64_t t, int mode, int tm, int &I, int &J)
+// Workgroup b -> tile (I, J).  Workgroups are handed to the 8 XCDs in turn
+// (b % 8); each XCD gets a contiguous range of the tile order, so the tiles it
+// runs at the same time share operand rows in its L2.  kTri orders the lower
+// triangle in groups of 8 tile rows: within a group, column by column, so a
+// window of consecutive tiles touches about 8 row blocks of each operand.
+__device__ __forceinline__ int64_t tri_group_start(int64_t g) { return 32 * g * (g - 1) + 36 * g; }
+
+__device__ __forceinline__ void tile_of(int64_t b, int mode, int tm, int &I, int &J)
 {
     if (mode == kTri) {
-        I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-        while ((int64_t)I * (I + 1) / 2 > t) --I;
-        while ((int64_t)(I + 1) * (I + 2) / 2 <= t) ++I;
-        J = (int)(t - (int64_t)I * (I + 1) / 2);
+        const int64_t n = (int64_t)tm * (tm + 1) / 2, q = n / 8, r = n % 8, x = b % 8, k = b / 8;
+        const int64_t v = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+        int64_t g = v > 0 ? (int64_t)((sqrt(16.0 + 128.0 * (double)v) - 4.0) / 64.0) : 0;
+        while (g > 0 && tri_group_start(g) > v) --g;
+        while (8 * (g + 1) < tm && tri_group_start(g + 1) <= v) ++g;
+        const int I0 = (int)(8 * g), Gg = min(8, tm - I0);
+        int64_t w = v - tri_group_start(g);
+        if (w < (int64_t)I0 * Gg) {
+            I = I0 + (int)(w % Gg);
+            J = (int)(w / Gg);
+            return;
+        }
+        w -= (int64_t)I0 * Gg;
+        int c = I0;
+        while (w >= I0 + Gg - c) {
+            w -= I0 + Gg - c;
+            ++c;
+        }
+        I = c + (int)w;
+        J = c;
     } else {
-        I = (int)(t % tm);
-        J = (int)(t / tm);
+        I = (int)(b % tm);
+        J = (int)(b / tm);
     }
 }
 
@@ -362,20 +393,18 @@ static size_t gemm_smem_bytes() { return (size_t)2 * 2 * kBK * kLdsLd * sizeof(T
 // bits, row-major into Q (row stride 256): tile row R goes to Q row R + qrow
 // (skipped when negative), tile column c to Q column qcol + c.  The tile is
 // transposed through LDS so that Q is written 16 bytes at a time.
-template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
-__global__ __launch_bounds__(256) void gemm_kernel(int tm, int K, const T *A, int64_t lda, const T *B,
-                                                   int64_t ldb, T *C, int64_t ldc, void *Q = nullptr, int qrow = 0,
-                                                   int qcol = 0)
+// One 128 x 128 tile (I, J) by the whole workgroup; smem: gemm_smem_bytes<T>()
+// bytes of LDS.  MASK: the tile lies on or below the diagonal of C's origin
+// (I >= J), diagonal tiles keep rows >= columns.
+template <typename T, bool MASK, bool SUB, int Q16 = 0>
+__device__ __forceinline__ void gemm_tile(int I, int J, int K, const T *A, int64_t lda, const T *B, int64_t ldb,
+                                          T *C, int64_t ldc, void *Q, int qrow, int qcol, unsigned char *smem_raw)
 {
     typedef typename Mfma4<T>::acc_t acc_t;
     constexpr int LD = kLdsLd;
     constexpr bool kF32 = Mfma4<T>::kConsecutiveRows;
     constexpr bool kOld = SUB || MASK;            // old C values needed
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);   // [buf][operand][k][row]
-    int I, J;
-    tile_of(blockIdx.x, MODE, tm, I, J);
-    if (MASK && I < J) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const T *Ab = A + (int64_t)I * kBM;
@@ -523,6 +552,58 @@ __global__ __launch_bounds__(256) void gemm_kernel(int tm, int K, const T *A, in
     }
 }
 
+template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
+__global__ __launch_bounds__(256) void gemm_kernel(int tm, int K, const T *A, int64_t lda, const T *B,
+                                                   int64_t ldb, T *C, int64_t ldc, void *Q = nullptr, int qrow = 0,
+                                                   int qcol = 0)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    int I, J;
+    tile_of(blockIdx.x, MODE, tm, I, J);
+    if (MASK && I < J) return;
+    gemm_tile<T, MASK, SUB, Q16>(I, J, K, A, lda, B, ldb, C, ldc, Q, qrow, qcol, smem_raw);
+}
+
+// ------------------------------------------------------------------------
+// Factorisation of one 256-wide outer panel (columns P0 .. P0+255) after the
+// diagonal block 0 (rows/columns P0 .. P0+127) is done:
+// panel_b: tile I solves rows P0+128+128I of the first 128 columns in place,
+//   X0 = A W0^T; tile 0 (rows P0+128 .. P0+255, the second diagonal block)
+//   then updates its diagonal block, A11 -= X0_1 X0_1^T, and factors it.
+// panel_c: tile I (rows P0+256+128I) updates the second 128 columns,
+//   A_I1 -= X0_I X0_1^T, and solves them in place, X1 = A_I1 W1^T.
+// For 16-bit trailing updates both solves also write the 16-bit copy of the
+// rows below the panel (columns 0..127 and 128..255 of Q).
+// ------------------------------------------------------------------------
+template <typename T, int Q16>
+__global__ __launch_bounds__(256) void panel_b_kernel(T *A, int64_t lda, const T *W0, T *W1, int32_t *info,
+                                                      int k1, void *Q)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int I = blockIdx.x;
+    // A points at (P0 + 128, P0): the rows below the first diagonal block
+    gemm_tile<T, false, false, Q16>(I, 0, kNB, A, lda, W0, kNB, A, lda, Q, -kNB, 0, smem_raw);
+    if (I != 0) return;
+    __syncthreads();   // this workgroup's X0_1 is complete and visible to it
+    T *A11 = A + (int64_t)kNB * lda;
+    gemm_tile<T, true, true, 0>(0, 0, kNB, A, lda, A, lda, A11, lda, nullptr, 0, 0, smem_raw);
+    __syncthreads();
+    diag_block<T, true>(A11, lda, W1, info, k1, smem_raw);
+}
+
+template <typename T, int Q16>
+__global__ __launch_bounds__(256) void panel_c_kernel(T *A, int64_t lda, const T *W1, void *Q)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int I = blockIdx.x;
+    // A points at (P0 + 128, P0): X0_1 = rows 0..127; tile I uses rows 128 + 128 I
+    const T *X0 = A + kNB;
+    T *C = A + kNB + (int64_t)kNB * lda;
+    gemm_tile<T, false, true, 0>(I, 0, kNB, X0, lda, A, lda, C, lda, nullptr, 0, 0, smem_raw);
+    __syncthreads();
+    gemm_tile<T, false, false, Q16>(I, 0, kNB, C, lda, W1, kNB, C, lda, Q, 0, kNB, smem_raw);
+}
+
 // ------------------------------------------------------------------------
 // 16-bit outer trailing update: C (FP32, column-major) -= Q Q^T, Q stored
 // row-major in 16 bits with K contiguous (Q[r * ldq + k]);
@@ -643,8 +724,6 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
         }
 }
 
-constexpr int kOuter = 256;   // width of an outer panel
-
 // ------------------------------------------------------------------------
 // host drivers
 // ------------------------------------------------------------------------
@@ -684,55 +763,55 @@ static hipError_t launch_syrk16(int tm, int ntiles, int K, const H *QA, const H 
     return hipGetLastError();
 }
 
-// Factor outer panel `p` (columns p*256 .. p*256+255, rows p*256 .. npad) with
-// 128-wide inner steps: diagonal block, in-place panel solve, update of the
-// panel's remaining columns.  For 16-bit dtypes the rows below the panel are
-// then copied into the row-major 16-bit buffer Q16.
+// Factor outer panel `p` (columns p*256 .. p*256+255, rows p*256 .. npad):
+// diagonal block 0, then panel_b (panel solve of the first 128 columns; the
+// second diagonal block), then panel_c (update and panel solve of the second
+// 128 columns).  For 16-bit dtypes the solves also fill the row-major 16-bit
+// copy Q16 of the rows below the panel.
+template <typename T, int Q16T>
+static hipError_t launch_panel(int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info, int64_t P0,
+                               hipStream_t s, Prof *prof)
+{
+    const double es = (double)sizeof(T);
+    const size_t smem_b = std::max(gemm_smem_bytes<T>(), diag_smem_bytes(sizeof(T)));
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)panel_b_kernel<T, Q16T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)smem_b)) != hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)panel_c_kernel<T, Q16T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)gemm_smem_bytes<T>())) != hipSuccess)
+        return e;
+    T *W0 = Winv + P0 * kNB, *W1 = Winv + (P0 + kNB) * kNB;
+    int tok = prof ? prof->start(s) : -1;
+    hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
+                       A + P0 + P0 * lda, lda, W0, info, (int)P0);
+    if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
+    const int64_t m0 = npad - P0 - kNB, m1 = npad - P0 - kOuter;   // rows below each diagonal block
+    T *Pan = A + (P0 + kNB) + P0 * lda;
+    tok = prof ? prof->start(s) : -1;
+    hipLaunchKernelGGL((panel_b_kernel<T, Q16T>), dim3((unsigned)(m0 / kNB)), dim3(256), smem_b, s, Pan, lda,
+                       (const T *)W0, W1, info, (int)(P0 + kNB), Q16);
+    if (prof)
+        prof->stop(tok, GBEM_K_TRSM, 2.0 * m0 * kNB * kNB + kNB * kNB * kNB * (1.0 + 2.0 / 3.0),
+                   2.0 * m0 * kNB * es + 5.0 * kNB * kNB * es + (Q16 ? 2.0 * m1 * kNB : 0.0), s);
+    if (m1 > 0) {
+        tok = prof ? prof->start(s) : -1;
+        hipLaunchKernelGGL((panel_c_kernel<T, Q16T>), dim3((unsigned)(m1 / kNB)), dim3(256), gemm_smem_bytes<T>(), s,
+                           Pan, lda, (const T *)W1, Q16);
+        if (prof)
+            prof->stop(tok, GBEM_K_PANEL, 4.0 * m1 * kNB * kNB,
+                       5.0 * m1 * kNB * es + kNB * kNB * es + (Q16 ? 2.0 * m1 * kNB : 0.0), s);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t factor_panel(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
                                int p, hipStream_t s, Prof *prof)
 {
-    const double es = (double)sizeof(T);
     const int64_t P0 = (int64_t)p * kOuter;
-    for (int j = 0; j < kOuter / kNB; ++j) {
-        const int64_t k0 = P0 + (int64_t)j * kNB;
-        int tok = prof ? prof->start(s) : -1;
-        hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
-                           A + k0 + k0 * lda, lda, Winv + k0 * kNB, info, (int)k0);
-        if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
-        const int64_t mb = npad - k0 - kNB;   // rows below the diagonal block
-        if (mb == 0) break;
-        const int tmb = (int)(mb / kBM);
-        T *Pan = A + (k0 + kNB) + k0 * lda;
-        tok = prof ? prof->start(s) : -1;
-        // panel solve in place; for 16-bit dtypes the rows below the outer
-        // panel also go to Q16 (row r -> Q16 row r - P0 - 256, column j*128 + c)
-        const int qrow = (int)(k0 + kNB - (P0 + kOuter)), qcol = j * kNB;
-        hipError_t e;
-        if (Q16 && dtype == GBEM_BF16)
-            e = launch_gemm<T, kRect, false, false, 1>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan, lda, s,
-                                                       Q16, qrow, qcol);
-        else if (Q16 && dtype == GBEM_F16)
-            e = launch_gemm<T, kRect, false, false, 2>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan, lda, s,
-                                                       Q16, qrow, qcol);
-        else
-            e = launch_gemm<T, kRect, false, false>(tmb, tmb, kNB, Pan, lda, Winv + k0 * kNB, kNB, Pan, lda, s);
-        if (e != hipSuccess) return e;
-        if (prof)
-            prof->stop(tok, GBEM_K_TRSM, 2.0 * mb * kNB * kNB,
-                       2.0 * mb * kNB * es + kNB * kNB * es + (Q16 ? 2.0 * mb * kNB : 0.0), s);
-        if (j + 1 < kOuter / kNB) {
-            // remaining columns of this panel: A[k0+128:, k0+128:P0+256] -= L L^T
-            const int64_t ncols = P0 + kOuter - (k0 + kNB);
-            const int tn = (int)(ncols / kBM);
-            tok = prof ? prof->start(s) : -1;
-            e = launch_gemm<T, kRect, true, true>(tmb, tmb * tn, kNB, Pan, lda, Pan, lda,
-                                                  A + (k0 + kNB) + (k0 + kNB) * lda, lda, s);
-            if (e != hipSuccess) return e;
-            if (prof) prof->stop(tok, GBEM_K_PANEL, 2.0 * mb * ncols * kNB, 2.0 * mb * ncols * es, s);
-        }
-    }
-    return hipGetLastError();
+    if (Q16 && dtype == GBEM_BF16) return launch_panel<T, 1>(npad, A, lda, Winv, Q16, info, P0, s, prof);
+    if (Q16 && dtype == GBEM_F16) return launch_panel<T, 2>(npad, A, lda, Winv, Q16, info, P0, s, prof);
+    return launch_panel<T, 0>(npad, A, lda, Winv, nullptr, info, P0, s, prof);
 }
 
 // Outer update of columns [c0, c0 + ncols) of the trailing matrix with the
