@@ -220,6 +220,50 @@ def serving(args, binding, np):
     return out
 
 
+def sweep(args, binding, np):
+    """Precision sweep (p x eta x factor dtype) on one layout: time of one
+    extraction and capacitance error against the FP64 path with p = 8, eta = 4
+    (the FP64 path is parity-tested against the CPU oracle; the oracle itself
+    is far too slow at this size).  One JSON object per configuration."""
+    import torch
+    lay = layout_of(args.layout)
+    lo, hi, cond = binding.mesh_layout(lay)
+    n, m = lo.shape[0], lay.n_conductors
+    dev = torch.device("cuda:0")
+    d_lo, d_hi = torch.tensor(lo, device=dev), torch.tensor(hi, device=dev)
+    d_cond = torch.tensor(cond, device=dev)
+    d_C = torch.zeros((m, m), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    rows = []
+    with binding.Context(0) as ctx:
+        def run(o):
+            rep = ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C, o, stream)
+            torch.cuda.synchronize()
+            return d_C.cpu().numpy().copy(), rep
+        log(f"sweep: {lay.name} N={n} M={m}: reference FP64 p=8 eta=4")
+        Cref, rref = run(binding.make_opts(8, 4.0))
+        rows.append({"p": 8, "eta": 4.0, "factor": "f64", "far": "f64", "ms": rref["t_total_ms"],
+                     "C_rel_err_vs_ref": 0.0, "n_near": rref["n_near"], "reference": True})
+        for p in (2, 3, 4):
+            for eta in (1.0, 2.0, 4.0):
+                for fac in ("f64", "f32", "f16", "bf16"):
+                    far = "f64" if fac == "f64" else "f32"
+                    o = binding.make_opts(p, eta, far, fac, 1e-6, 30)
+                    run(o)                                   # warm (allocations, code objects)
+                    t0 = time.perf_counter()
+                    C, rep = run(o)
+                    wall = (time.perf_counter() - t0) * 1e3
+                    err = float(np.abs(C - Cref).max() / np.abs(Cref).max())
+                    row = {"p": p, "eta": eta, "factor": fac, "far": far, "ms": wall,
+                           "t_assemble_ms": rep["t_assemble_ms"], "t_factor_ms": rep["t_factor_ms"],
+                           "t_solve_ms": rep["t_solve_ms"], "refine_iters": rep["refine_iters"],
+                           "factor_used": rep["factor_used"], "n_near": rep["n_near"], "C_rel_err_vs_ref": err}
+                    rows.append(row)
+                    log(f"sweep: {row}")
+    return {"metric": "precision sweep", "config": {"workload": f"{lay.name}: N={n}, M={m}"},
+            "reference": "FP64 path, p=8, eta=4", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +277,10 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="replay the seeded serving stream (256 jobs, Poisson 50 jobs/s) instead")
     ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the library's per-launch HIP events (no roofline)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="precision sweep p x eta x factor dtype on --layout (default three_layer_bus)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference for HBM byte counters)")
     args = ap.parse_args()
@@ -248,6 +296,11 @@ def main():
     if args.serving:
         print(json.dumps(serving(args, binding, np)))
         return
+    if args.sweep:
+        if args.layout == "crossing_bus":
+            args.layout = "three_layer_bus"
+        print(json.dumps(sweep(args, binding, np)))
+        return
 
     lay = layout_of(args.layout)
     lo, hi, cond = binding.mesh_layout(lay)
@@ -260,7 +313,10 @@ def main():
     d_C = torch.zeros((m, m), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     ctx = binding.Context(0)
-    opts = binding.make_opts(args.p, args.eta, profile=True, **MODES[args.mode])
+    # warmup; the last warmup step times every kernel class once (untimed) to
+    # find the dominant one; the timed steps record HIP events around that
+    # class's launches only (events around every launch cost ~7 % here)
+    opts_all = binding.make_opts(args.p, args.eta, profile=True, **MODES[args.mode])
 
     # reference: the FP64 path (parity-tested against the CPU oracle)
     rep64 = ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C,
@@ -268,10 +324,16 @@ def main():
     C64 = d_C.cpu().numpy().copy()
     log(f"bench: f64 reference done in {rep64['t_total_ms']:.1f} ms")
 
-    for _ in range(args.warmup):
-        ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C, opts, stream)
+    rep_all = None
+    for w in range(max(1, args.warmup)):
+        rep_all = ctx.extract_device(d_lo, d_hi, d_cond, m, lay.eps_r, lay.length_unit_m, d_C,
+                                     opts_all if w == max(1, args.warmup) - 1 else
+                                     binding.make_opts(args.p, args.eta, **MODES[args.mode]), stream)
     torch.cuda.synchronize()
-    log("bench: warmup done")
+    dominant = max(rep_all["profile"].items(), key=lambda kv: kv[1]["ms"])[0]
+    opts = binding.make_opts(args.p, args.eta, profile=None if args.no_profile else [dominant],
+                             **MODES[args.mode])
+    log(f"bench: warmup done; dominant kernel class {dominant}")
     lat, reps = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -311,9 +373,22 @@ def main():
         "refine_iters": r_last["refine_iters"], "residual": r_last["residual"],
         "stage_ms": stage,
         "kernel_ms_per_step": {c: d["ms"] / args.steps for c, d in sorted(profile.items(), key=lambda kv: -kv[1]["ms"])},
-        "roofline": roofline_of(profile, args.mode, lay.name),
+        "roofline": roofline_of(profile, args.mode, lay.name) if profile else None,
+        "kernel_ms_untimed_step": {c: d["ms"] for c, d in sorted(rep_all["profile"].items(), key=lambda kv: -kv[1]["ms"])},
         "f64_reference_ms": rep64["t_total_ms"],
     }
+    # stage rates (per step, from the library's HIP events)
+    nnz = r_last["n_near"]
+    far_pairs = pairs - nnz
+    rates = {"near_pairs": nnz, "far_pairs": far_pairs, "from": "the all-class profiled warmup step"}
+    pa = rep_all["profile"]
+    if "far" in pa:
+        far_s = pa["far"]["ms"] / 1e3
+        rates["far_pair_integrals_per_s"] = far_pairs / far_s
+        rates["far_kernel_evals_per_s"] = far_pairs * args.p ** 4 / far_s
+    if "near_eval" in pa:
+        rates["near_pairs_per_s"] = nnz / (pa["near_eval"]["ms"] / 1e3)
+    out["rates"] = rates
     if args.copy_calibration:
         # a plain copy kernel of known size: 256 MiB read + 256 MiB written per launch
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)

@@ -83,7 +83,8 @@ typedef struct {
     int32_t factor_dtype;       /* gbem_dtype of the factorisation (GBEM_F64: no refinement) */
     double refine_tol;          /* refinement stops when max_k |b_k - A x_k|_2 / |b_k|_2 <= tol */
     int32_t max_refine;         /* refinement iteration cap (default 30) */
-    int32_t profile;            /* nonzero: time every kernel class with HIP events (gbem_report.prof_*) */
+    int32_t profile;            /* bit c set: time the launches of kernel class c (gbem_kernel_class) with
+                                   HIP events on their streams (gbem_report.prof_*); 0: no events */
 } gbem_opts;
 
 /* Kernel classes of gbem_report.prof_* (see the design notes for their work units). */

@@ -140,11 +140,21 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data)
 
 
+def profile_mask(profile) -> int:
+    """opts.profile: True = every kernel class, False/None = none, or an
+    iterable of class names (KERNEL_CLASSES)."""
+    if profile is True:
+        return (1 << NCLS) - 1
+    if not profile:
+        return 0
+    return sum(1 << KERNEL_CLASSES.index(c) for c in profile)
+
+
 def make_opts(far_order=3, near_eta=2.0, far_dtype="f64", factor_dtype="f64", refine_tol=1e-6,
               max_refine=30, profile=False) -> Opts:
     return Opts(far_order, near_eta, DTYPES[far_dtype] if isinstance(far_dtype, str) else far_dtype,
                 DTYPES[factor_dtype] if isinstance(factor_dtype, str) else factor_dtype, refine_tol, max_refine,
-                1 if profile else 0)
+                profile_mask(profile))
 
 
 def mesh_boxes(box_lo, box_hi, box_cond, rule):

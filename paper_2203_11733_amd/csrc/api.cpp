@@ -256,6 +256,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
 
     Prof &pf = ws.prof;
     pf.on = o.profile != 0;
+    pf.mask = (uint32_t)o.profile;
     pf.reset();
     if (rep) {
         for (int c = 0; c < GBEM_K_COUNT; ++c) {
@@ -265,11 +266,11 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     }
     HIPCHK(hipEventRecord(ws.ev[0], st), "hipEventRecord");
     HIPCHK(hipMemsetAsync(flags, 0, 64, st), "hipMemsetAsync");
-    int tok = pf.start(st);
+    int tok = pf.start(st, GBEM_K_OTHER);
     HIPCHK(launch_build_panels(dlo, dhi, dcond, n, m, ws.pan.as<Panel>(), flags, st), "build_panels");
     pf.stop(tok, GBEM_K_OTHER, 0.0, (double)n * (48 + 4 + 64), st);
     const double eta2 = o.near_eta * o.near_eta;
-    const int tok_near = pf.start(st);
+    const int tok_near = pf.start(st, GBEM_K_NEAR_LIST);
     HIPCHK(launch_near_count(dlo, dhi, n, eta2, ws.cnt.as<int64_t>(), st), "near_count");
     HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), st), "scan");
     pf.stop(tok_near, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8 + 8), st, 2);
@@ -300,13 +301,13 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near rows");
     HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
     HIPCHK(ws.semi.ensure(near_semi_bytes(nnz)), "alloc near queue");
-    tok = pf.start(st);
+    tok = pf.start(st, GBEM_K_NEAR_LIST);
     HIPCHK(launch_near_fill(dlo, dhi, n, eta2, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
                             ws.ncol.as<int32_t>(), st), "near_fill");
     pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8) + (double)nnz * 8, st);
     GaussRule rule;
     gauss_legendre_rule(o.far_order, &rule);
-    tok = pf.start(st);
+    tok = pf.start(st, GBEM_K_FAR);
     HIPCHK(launch_far(ws.pan.as<Panel>(), n, (int)npad, o.far_order, rule, o.far_dtype, A, lda, st), "far");
     {
         const double p2 = (double)o.far_order * o.far_order;
@@ -315,7 +316,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         pf.stop(tok, GBEM_K_FAR, 11.0 * p2 * p2 * (double)n * (n + 1) / 2.0,
                 (double)npad * npad * 8.0 + (double)n * sizeof(Panel), st);
     }
-    tok = pf.start(st);
+    tok = pf.start(st, GBEM_K_NEAR_EVAL);
     HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
                             A, lda, ws.semi.as<int32_t>(), st), "near_eval");
     pf.stop(tok, GBEM_K_NEAR_EVAL, 0.0, (double)nnz * (2 * 8 + 2 * 4 + 2 * 48), st);
@@ -347,7 +348,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         if (dtype != GBEM_F64) {
             HIPCHK(ws.F.ensure((size_t)npad * npad * es), "alloc F");
             HIPCHK(ws.s.ensure((size_t)npad * 8), "alloc s");
-            tok = pf.start(st);
+            tok = pf.start(st, GBEM_K_OTHER);
             HIPCHK(launch_jacobi_scale(A, lda, (int)npad, ws.s.as<double>(), st), "jacobi");
             HIPCHK(launch_scale_convert(A, lda, ws.s.as<double>(), (int)npad, ws.F.as<float>(), npad, st),
                    "scale_convert");
@@ -385,7 +386,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         double *rnorm = ws.norms.as<double>();
         bool converged = false;
         for (iters = 0;; ++iters) {
-            tok = pf.start(st);
+            tok = pf.start(st, GBEM_K_RESIDUAL);
             HIPCHK(launch_residual(A, lda, (int)npad, X, npad, B, npad, m, R, npad, ws.rpart.as<double>(), st),
                    "residual");
             pf.stop(tok, GBEM_K_RESIDUAL, 2.0 * (double)npad * npad * m,

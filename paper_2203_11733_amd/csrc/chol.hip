@@ -781,20 +781,20 @@ static hipError_t launch_panel(int64_t npad, T *A, int64_t lda, T *Winv, void *Q
                                  (int)gemm_smem_bytes<T>())) != hipSuccess)
         return e;
     T *W0 = Winv + P0 * kNB, *W1 = Winv + (P0 + kNB) * kNB;
-    int tok = prof ? prof->start(s) : -1;
+    int tok = prof ? prof->start(s, GBEM_K_DIAG) : -1;
     hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
                        A + P0 + P0 * lda, lda, W0, info, (int)P0);
     if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
     const int64_t m0 = npad - P0 - kNB, m1 = npad - P0 - kOuter;   // rows below each diagonal block
     T *Pan = A + (P0 + kNB) + P0 * lda;
-    tok = prof ? prof->start(s) : -1;
+    tok = prof ? prof->start(s, GBEM_K_TRSM) : -1;
     hipLaunchKernelGGL((panel_b_kernel<T, Q16T>), dim3((unsigned)(m0 / kNB)), dim3(256), smem_b, s, Pan, lda,
                        (const T *)W0, W1, info, (int)(P0 + kNB), Q16);
     if (prof)
         prof->stop(tok, GBEM_K_TRSM, 2.0 * m0 * kNB * kNB + kNB * kNB * kNB * (1.0 + 2.0 / 3.0),
                    2.0 * m0 * kNB * es + 5.0 * kNB * kNB * es + (Q16 ? 2.0 * m1 * kNB : 0.0), s);
     if (m1 > 0) {
-        tok = prof ? prof->start(s) : -1;
+        tok = prof ? prof->start(s, GBEM_K_PANEL) : -1;
         hipLaunchKernelGGL((panel_c_kernel<T, Q16T>), dim3((unsigned)(m1 / kNB)), dim3(256), gemm_smem_bytes<T>(), s,
                            Pan, lda, (const T *)W1, Q16);
         if (prof)
@@ -829,7 +829,7 @@ static hipError_t outer_update(int dtype, int64_t npad, T *A, int64_t lda, int64
     const double es = (double)sizeof(T);
     const bool b16 = dtype == GBEM_F16 || dtype == GBEM_BF16;
     const double tiles_el = tri ? (double)tm * (tm + 1) / 2 * kBM * kBM : (double)m * ncols;
-    const int tok = prof ? prof->start(s) : -1;
+    const int tok = prof ? prof->start(s, cls) : -1;
     hipError_t e;
     if (!b16) {
         const T *Q = A + c0 + P0 * lda;   // L[c0:, P0:P0+256], column-major
@@ -863,7 +863,7 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_smem_bytes(sizeof(T)));
     if (e != hipSuccess) return e;
-    while ((int)ev.size() < 2 * nbo + 2) {
+    while ((int)ev.size() < 2 * nbo + 2) {   // evP[0..nbo), evB[0..nbo]
         hipEvent_t x;
         if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return e;
         ev.push_back(x);
@@ -872,27 +872,37 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     auto q16 = [&](int p) -> void * {
         return b16 ? (void *)((char *)Q16 + (size_t)(p & 1) * npad * kOuter * 2) : nullptr;
     };
-    if ((e = factor_panel<T>(dtype, npad, A, lda, Winv, q16(0), info, 0, s, prof)) != hipSuccess) return e;
+    // Side stream: the latency-critical chain (update of the next panel's
+    // columns, then its factorisation).  Main stream: the rest of each outer
+    // update.  Events: evP[K] = panel K factored (side -> main), evB[K] =
+    // main's update with panel K done (main -> side, needed before the side
+    // stream updates the columns of panel K+2).
+    hipEvent_t *evP = ev.data(), *evB = ev.data() + nbo + 1;
+    if ((e = hipEventRecord(evB[nbo], s)) != hipSuccess) return e;   // inputs of this call are ready
+    if ((e = hipStreamWaitEvent(side, evB[nbo], 0)) != hipSuccess) return e;
+    if ((e = factor_panel<T>(dtype, npad, A, lda, Winv, q16(0), info, 0, side, prof)) != hipSuccess) return e;
+    if ((e = hipEventRecord(evP[0], side)) != hipSuccess) return e;
     for (int K = 0; K + 1 < nbo; ++K) {
         const int64_t P0 = (int64_t)K * kOuter;
-        // (a) next panel's columns
-        if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), P0 + kOuter, kOuter, s, prof, GBEM_K_PANEL)) !=
-            hipSuccess)
+        // side: (a) panel K+1's columns with panel K, then factor panel K+1
+        if (K > 0 && (e = hipStreamWaitEvent(side, evB[K - 1], 0)) != hipSuccess) return e;
+        if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), P0 + kOuter, kOuter, side, prof,
+                                 GBEM_K_PANEL)) != hipSuccess)
             return e;
-        if ((e = hipEventRecord(ev[2 * K], s)) != hipSuccess) return e;
-        // factor panel K+1 on the side stream
-        if ((e = hipStreamWaitEvent(side, ev[2 * K], 0)) != hipSuccess) return e;
         if ((e = factor_panel<T>(dtype, npad, A, lda, Winv, q16(K + 1), info, K + 1, side, prof)) != hipSuccess)
             return e;
-        if ((e = hipEventRecord(ev[2 * K + 1], side)) != hipSuccess) return e;
-        // (b) the rest of the trailing matrix
+        if ((e = hipEventRecord(evP[K + 1], side)) != hipSuccess) return e;
+        // main: (b) the columns beyond panel K+1 with panel K
         const int64_t c0 = P0 + 2 * kOuter;
-        if (c0 < npad)
+        if (c0 < npad) {
+            if ((e = hipStreamWaitEvent(s, evP[K], 0)) != hipSuccess) return e;
             if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), c0, npad - c0, s, prof, GBEM_K_SYRK)) !=
                 hipSuccess)
                 return e;
-        if ((e = hipStreamWaitEvent(s, ev[2 * K + 1], 0)) != hipSuccess) return e;
+        }
+        if ((e = hipEventRecord(evB[K], s)) != hipSuccess) return e;
     }
+    if ((e = hipStreamWaitEvent(s, evP[nbo - 1], 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
 

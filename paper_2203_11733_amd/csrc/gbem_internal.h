@@ -64,6 +64,7 @@ struct Prof {
         int launches;
     };
     bool on = false;
+    uint32_t mask = 0;             // classes timed (bit c = class c)
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<Rec> recs;
@@ -78,7 +79,7 @@ struct Prof {
         if (hipEventRecord(pool[used], s) != hipSuccess) return -1;
         return (int)used++;
     }
-    int start(hipStream_t s) { return on ? event(s) : -1; }
+    int start(hipStream_t s, int cls) { return on && (mask >> cls & 1u) ? event(s) : -1; }
     void stop(int tok, int cls, double flops, double bytes, hipStream_t s, int launches = 1)
     {
         if (!on || tok < 0) return;

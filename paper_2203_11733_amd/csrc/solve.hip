@@ -479,7 +479,7 @@ static hipError_t solve32_mc(int64_t npad, const float *L, int64_t lda, const fl
     const int limit = 1 << 26;
     const size_t smem_b = SolveCfg<MC, false>::kSmem;
     ++sync.epoch;
-    const int tok = prof ? prof->start(s) : -1;
+    const int tok = prof ? prof->start(s, GBEM_K_SOLVE) : -1;
     hipLaunchKernelGGL((tsolve32_kernel<MC, true>), dim3(nb), dim3(256), smem, s, L, lda, W, B, ldb, m, nb,
                        sync.flags_f, sync.err + 1, sync.base_f, sync.epoch, sync.err, limit);
     hipLaunchKernelGGL((tsolve32_kernel<MC, false>), dim3(nb), dim3(256), smem_b, s, L, lda, W, B, ldb, m, nb,
@@ -511,7 +511,7 @@ static hipError_t solve_mc(int64_t npad, const T *L, int64_t lda, const T *W, in
         return e;
     const int limit = 1 << 26;
     ++sync.epoch;
-    const int tok = prof ? prof->start(s) : -1;
+    const int tok = prof ? prof->start(s, GBEM_K_SOLVE) : -1;
     hipLaunchKernelGGL((fwd_solve_kernel<T, MC>), dim3(nb), dim3(256), smem, s, L, lda, W, B, ldb, m, nb,
                        sync.flags_f, sync.err + 1, sync.base_f, sync.epoch, sync.err, limit);
     hipLaunchKernelGGL((bwd_solve_kernel<T, MC>), dim3(nb), dim3(256), smem, s, L, lda, W, B, ldb, m, nb,
