@@ -553,7 +553,7 @@ __device__ __forceinline__ void gemm_tile(int I, int J, int K, const T *A, int64
 }
 
 template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
-__global__ __launch_bounds__(256) void gemm_kernel(int tm, int K, const T *A, int64_t lda, const T *B,
+__global__ __launch_bounds__(256, 2) void gemm_kernel(int tm, int K, const T *A, int64_t lda, const T *B,
                                                    int64_t ldb, T *C, int64_t ldc, void *Q = nullptr, int qrow = 0,
                                                    int qcol = 0)
 {
