@@ -644,53 +644,43 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    // old C values, all loads in flight before the K loop
-    f4_t cpre[4][4];
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-            const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
-            const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4);
-            cpre[mi][ni] = *reinterpret_cast<const f4_t *>(C + row + (int64_t)col * ldc);
-        }
-
     f4_t acc[4][4];
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f4_t{0, 0, 0, 0};
 
-    const int lr = tid >> 1, lk = (tid & 1) * 32;   // loader: row lr, k lk..lk+31
-    u4_t ra[4], rb[4];
-#define S16_LOAD(k0)                                                                                 \
+    // K = 256 in four chunks of 64, fully unrolled.  Two register buffers
+    // keep each chunk's loads two MFMA phases ahead of its use (one phase is
+    // far shorter than the memory latency); the old C values are requested
+    // during chunk 2.  Loads complete in order, so C goes last.
+    constexpr int NK = kOuter / kBK16;
+    static_assert(NK == 4, "the schedule below is written for four chunks");
+    const int lr = tid >> 1, lk = (tid & 1) * 32;   // loader: row lr, k lk..lk+31 of a chunk
+    u4_t r0[2][4], r1[2][4];                        // [operand][piece], chunks 0, 2 / 1, 3
+#define S16_LOAD(R, c)                                                                               \
     do {                                                                                             \
-        const u4_t *pa = reinterpret_cast<const u4_t *>(QA + (int64_t)(I * kBM + lr) * ldq + (k0) + lk); \
-        const u4_t *pb = reinterpret_cast<const u4_t *>(QB + (int64_t)(J * kBM + lr) * ldq + (k0) + lk); \
+        const u4_t *pa = reinterpret_cast<const u4_t *>(QA + (int64_t)(I * kBM + lr) * ldq + (c) * kBK16 + lk); \
+        const u4_t *pb = reinterpret_cast<const u4_t *>(QB + (int64_t)(J * kBM + lr) * ldq + (c) * kBK16 + lk); \
         _Pragma("unroll") for (int e = 0; e < 4; ++e)                                                \
         {                                                                                            \
-            ra[e] = pa[e];                                                                           \
-            rb[e] = pb[e];                                                                           \
+            R[0][e] = pa[e];                                                                         \
+            R[1][e] = pb[e];                                                                         \
         }                                                                                            \
     } while (0)
-#define S16_STORE(buf)                                                                               \
+#define S16_STORE(R, buf)                                                                            \
     do {                                                                                             \
         u4_t *sa = reinterpret_cast<u4_t *>(lds + (((buf) * 2 + 0) * kBM + lr) * LD + lk);         \
         u4_t *sb = reinterpret_cast<u4_t *>(lds + (((buf) * 2 + 1) * kBM + lr) * LD + lk);         \
         _Pragma("unroll") for (int e = 0; e < 4; ++e)                                                \
         {                                                                                            \
-            sa[e] = ra[e];                                                                           \
-            sb[e] = rb[e];                                                                           \
+            sa[e] = R[0][e];                                                                         \
+            sb[e] = R[1][e];                                                                         \
         }                                                                                            \
     } while (0)
-    const int nk = K / kBK16;
-    S16_LOAD(0);
-    S16_STORE(0);
-    __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
-        if (kc + 1 < nk) S16_LOAD((kc + 1) * kBK16);
-        const H *As = lds + ((kc & 1) * 2 + 0) * kBM * LD;
-        const H *Bs = lds + ((kc & 1) * 2 + 1) * kBM * LD;
+    auto mma = [&](int buf) __attribute__((always_inline)) {
+        const H *As = lds + (buf * 2 + 0) * kBM * LD;
+        const H *Bs = lds + (buf * 2 + 1) * kBM * LD;
 #pragma unroll
         for (int kk = 0; kk < kBK16; kk += 32) {
             frag_t af[4], bf[4];
@@ -705,12 +695,35 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
 #pragma unroll
                 for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma32<H>::run(af[mi], bf[ni], acc[mi][ni]);
         }
-        if (kc + 1 < nk) S16_STORE((kc + 1) & 1);
-        __syncthreads();
-    }
+    };
+    S16_LOAD(r0, 0);
+    S16_LOAD(r1, 1);
+    S16_STORE(r0, 0);
+    __syncthreads();
+    S16_LOAD(r0, 2);
+    mma(0);
+    S16_STORE(r1, 1);
+    __syncthreads();
+    S16_LOAD(r1, 3);
+    mma(1);
+    S16_STORE(r0, 0);
+    __syncthreads();
+    f4_t cpre[4][4];   // old C values
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+            const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
+            const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4);
+            cpre[mi][ni] = *reinterpret_cast<const f4_t *>(C + row + (int64_t)col * ldc);
+        }
+    mma(0);
+    S16_STORE(r1, 1);
+    __syncthreads();
+    mma(1);
 #undef S16_LOAD
 #undef S16_STORE
-    const bool diag_tile = I == J;
+    const bool diag_tile = I == J;   // uniform over the workgroup
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -718,8 +731,12 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
             const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
             const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4);
             f4_t v = cpre[mi][ni];
+            if (!diag_tile) {
+                v -= acc[mi][ni];
+            } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = (!diag_tile || row + q >= col) ? v[q] - acc[mi][ni][q] : v[q];
+                for (int q = 0; q < 4; ++q) v[q] = row + q >= col ? v[q] - acc[mi][ni][q] : v[q];
+            }
             *reinterpret_cast<f4_t *>(C + row + (int64_t)col * ldc) = v;
         }
 }
