@@ -169,7 +169,7 @@ static size_t footprint(int64_t n, int m, int factor_dtype)
     size_t b = (size_t)npad * npad * 8;                                   // A
     if (factor_dtype != GBEM_F64) b += (size_t)npad * npad * 4;           // FP32 factor
     const size_t es = factor_dtype == GBEM_F64 ? 8 : 4;
-    b += (size_t)npad * kNB * es + (size_t)npad * 256 * 2 * 2;           // W, 16-bit panels
+    b += (size_t)npad * kNB * es + (size_t)npad * kPad * 2 * 2;          // W, 16-bit panels
     b += 4 * (size_t)npad * m * 8 + (size_t)npad * 8;                    // B X R D, s
     b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 12;           // mesh, panels, near list + queue
     return b;

@@ -1,17 +1,23 @@
-// Blocked right-looking Cholesky A = L L^T and the block triangular solves.
+// Blocked right-looking Cholesky A = L L^T.
 //
 // A is symmetric positive definite (section 3.2, Theorem 1), so the paper
 // solves A X = B by Cholesky.  Matrices here are column-major, lower triangle
-// referenced, order npad (a multiple of 128, padded with an identity block).
-// Step k of the factorisation, k0 = 128 k, m = npad - k0 - 128:
-//   1. diag_kernel: L_kk = chol(A_kk) in LDS, then W_k = L_kk^{-1} in place;
-//      L_kk goes back to A, W_k is kept for the solves.
-//   2. panel = A[k0+128:, k0:k0+128] W_k^T          (GEMM, MFMA)
-//   3. copy the panel into A (and to a 16-bit row-major copy for F16/BF16)
-//   4. A[k0+128:, k0+128:] -= panel panel^T, lower tiles only (MFMA)
+// referenced, order npad (a multiple of the outer panel width, padded with
+// an identity block).  Outer panels of ow = 256 or 512 columns (the wider
+// panels halve the trailing matrix's read-modify-write traffic and pay off
+// once the trailing updates outweigh the panel work), each made of
+// 128-wide column blocks j:
+//   diag_kernel / diag_block: L_jj = chol(A_jj) and W_j = L_jj^{-1} in LDS
+//     (W_j is kept: the panel solves and the triangular solves use it)
+//   panel_step_kernel j: update of column block j by blocks 0..j-1 of the
+//     panel, panel solve X = A W_j^T in place (MFMA), and the next diagonal
+//     block
+//   outer update of the columns beyond the panel, A -= X X^T over lower tiles
+//     (MFMA), with one panel of look-ahead on a second stream
 // dtype F64: FP64 storage, v_mfma_f64_16x16x4; F32: FP32 storage,
-// v_mfma_f32_16x16x4f32; F16/BF16: FP32 storage and FP32 steps 1-3, step 4 on
-// v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation.
+// v_mfma_f32_16x16x4f32; F16/BF16: FP32 storage and FP32 panel work, the
+// outer update on v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation from a
+// 16-bit row-major copy of the panel.
 #include "gbem_internal.h"
 
 #include <type_traits>
@@ -341,7 +347,8 @@ __global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t ld
 // before its epilogue writes them, and no other tile touches those rows.
 // ------------------------------------------------------------------------
 constexpr int kBM = 128, kBK = 16;
-constexpr int kOuter = 256;   // width of an outer panel (K of the trailing update)
+// outer panel width for a matrix of order npad
+static int outer_width(int64_t npad) { return npad >= 32768 ? 512 : 256; }
 constexpr int kLdsLd = kBM + 16;   // LDS row stride: the four k-rows of a fragment load hit distinct banks
 constexpr int kRect = 0, kTri = 1;
 
@@ -390,7 +397,7 @@ static size_t gemm_smem_bytes() { return (size_t)2 * 2 * kBK * kLdsLd * sizeof(T
 // (it produces C^T), so that lane l's outputs lie in row l % 16 and every
 // access covers 16 consecutive rows.
 // Q16 (f32 only; 1: bf16, 2: f16): the tile is also written, rounded to 16
-// bits, row-major into Q (row stride 256): tile row R goes to Q row R + qrow
+// bits, row-major into Q (row stride qld): tile row R goes to Q row R + qrow
 // (skipped when negative), tile column c to Q column qcol + c.  The tile is
 // transposed through LDS so that Q is written 16 bytes at a time.
 // One 128 x 128 tile (I, J) by the whole workgroup; smem: gemm_smem_bytes<T>()
@@ -398,7 +405,8 @@ static size_t gemm_smem_bytes() { return (size_t)2 * 2 * kBK * kLdsLd * sizeof(T
 // (I >= J), diagonal tiles keep rows >= columns.
 template <typename T, bool MASK, bool SUB, int Q16 = 0>
 __device__ __forceinline__ void gemm_tile(int I, int J, int K, const T *A, int64_t lda, const T *B, int64_t ldb,
-                                          T *C, int64_t ldc, void *Q, int qrow, int qcol, unsigned char *smem_raw)
+                                          T *C, int64_t ldc, void *Q, int qrow, int qcol, unsigned char *smem_raw,
+                                          int qld = 0)
 {
     typedef typename Mfma4<T>::acc_t acc_t;
     constexpr int LD = kLdsLd;
@@ -513,7 +521,7 @@ __device__ __forceinline__ void gemm_tile(int I, int J, int K, const T *A, int64
                 const int idx = tid + 256 * u, rl = idx >> 4, cc = (idx & 15) * 8;
                 const int64_t qr = (int64_t)I * kBM + rl + qrow;
                 if (qr >= 0)
-                    *reinterpret_cast<u4_t *>(reinterpret_cast<H *>(Q) + qr * 256 + qcol + J * kBM + cc) =
+                    *reinterpret_cast<u4_t *>(reinterpret_cast<H *>(Q) + qr * qld + qcol + J * kBM + cc) =
                         *reinterpret_cast<const u4_t *>(t16 + rl * (kBM + 8) + cc);
             }
         }
@@ -565,43 +573,39 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int tm, int K, const T *A,
 }
 
 // ------------------------------------------------------------------------
-// Factorisation of one 256-wide outer panel (columns P0 .. P0+255) after the
-// diagonal block 0 (rows/columns P0 .. P0+127) is done:
-// panel_b: tile I solves rows P0+128+128I of the first 128 columns in place,
-//   X0 = A W0^T; tile 0 (rows P0+128 .. P0+255, the second diagonal block)
-//   then updates its diagonal block, A11 -= X0_1 X0_1^T, and factors it.
-// panel_c: tile I (rows P0+256+128I) updates the second 128 columns,
-//   A_I1 -= X0_I X0_1^T, and solves them in place, X1 = A_I1 W1^T.
-// For 16-bit trailing updates both solves also write the 16-bit copy of the
-// rows below the panel (columns 0..127 and 128..255 of Q).
+// Factorisation of one outer panel (ow columns from P0, ns = ow/128
+// column blocks) after its diagonal block 0 is factored.  Step j (one
+// launch, j = 0 .. ns-1), P = the panel's top-left corner, tile I covering
+// the rows 128 (j + 1 + I) .. of the panel:
+//   - column block j of those rows receives the updates of blocks 0..j-1,
+//     A[R, j] -= X[R, 0..j-1] X[j, 0..j-1]^T          (K = 128 j)
+//   - panel solve in place, X[R, j] = A[R, j] W_j^T   (W_j = L_jj^{-1})
+//   - tile 0 (the rows of diagonal block j+1) then updates that block with
+//     blocks 0..j and factors it (L, W_{j+1}).
+// For 16-bit trailing updates the solve also writes the 16-bit copy of the
+// rows below the panel (row-major Q, columns 128 j ..).
 // ------------------------------------------------------------------------
 template <typename T, int Q16>
-__global__ __launch_bounds__(256) void panel_b_kernel(T *A, int64_t lda, const T *W0, T *W1, int32_t *info,
-                                                      int k1, void *Q)
+__global__ __launch_bounds__(256) void panel_step_kernel(T *P, int64_t lda, int j, int ns, const T *Wj, T *Wn,
+                                                         int32_t *info, int kn, void *Q)   // ns = ow / 128
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int I = blockIdx.x;
-    // A points at (P0 + 128, P0): the rows below the first diagonal block
-    gemm_tile<T, false, false, Q16>(I, 0, kNB, A, lda, W0, kNB, A, lda, Q, -kNB, 0, smem_raw);
-    if (I != 0) return;
-    __syncthreads();   // this workgroup's X0_1 is complete and visible to it
-    T *A11 = A + (int64_t)kNB * lda;
-    gemm_tile<T, true, true, 0>(0, 0, kNB, A, lda, A, lda, A11, lda, nullptr, 0, 0, smem_raw);
+    const int64_t r0 = (int64_t)kNB * (j + 1 + I);   // first row of the tile within the panel
+    T *C = P + r0 + (int64_t)kNB * j * lda;
+    if (j > 0) {
+        gemm_tile<T, false, true, 0>(0, 0, kNB * j, P + r0, lda, P + (int64_t)kNB * j, lda, C, lda, nullptr, 0, 0,
+                                     smem_raw);
+        __syncthreads();   // this workgroup's updated tile is complete and visible to it
+    }
+    gemm_tile<T, false, false, Q16>(0, 0, kNB, C, lda, Wj, kNB, C, lda, Q, (int)(r0 - kNB * ns), kNB * j, smem_raw,
+                                    kNB * ns);
+    if (I != 0 || j + 1 >= ns) return;
     __syncthreads();
-    diag_block<T, true>(A11, lda, W1, info, k1, smem_raw);
-}
-
-template <typename T, int Q16>
-__global__ __launch_bounds__(256) void panel_c_kernel(T *A, int64_t lda, const T *W1, void *Q)
-{
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    const int I = blockIdx.x;
-    // A points at (P0 + 128, P0): X0_1 = rows 0..127; tile I uses rows 128 + 128 I
-    const T *X0 = A + kNB;
-    T *C = A + kNB + (int64_t)kNB * lda;
-    gemm_tile<T, false, true, 0>(I, 0, kNB, X0, lda, A, lda, C, lda, nullptr, 0, 0, smem_raw);
+    T *D = P + r0 + r0 * lda;   // diagonal block j + 1
+    gemm_tile<T, true, true, 0>(0, 0, kNB * (j + 1), P + r0, lda, P + r0, lda, D, lda, nullptr, 0, 0, smem_raw);
     __syncthreads();
-    gemm_tile<T, false, false, Q16>(I, 0, kNB, C, lda, W1, kNB, C, lda, Q, 0, kNB, smem_raw);
+    diag_block<T, true>(D, lda, Wn, info, kn, smem_raw);
 }
 
 // ------------------------------------------------------------------------
@@ -629,7 +633,7 @@ template <> struct Mfma32<_Float16> {
 constexpr int kBK16 = 64, kPad16 = 8;
 static size_t syrk16_smem_bytes() { return (size_t)2 * 2 * kBM * (kBK16 + kPad16) * 2; }
 
-template <typename H, int MODE>
+template <typename H, int MODE, int NK>
 __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__restrict__ QA,
                                                      const H *__restrict__ QB, int64_t ldq,
                                                      float *__restrict__ C, int64_t ldc)
@@ -650,14 +654,13 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = f4_t{0, 0, 0, 0};
 
-    // K = 256 in four chunks of 64, fully unrolled.  Two register buffers
-    // keep each chunk's loads two MFMA phases ahead of its use (one phase is
-    // far shorter than the memory latency); the old C values are requested
-    // during chunk 2.  Loads complete in order, so C goes last.
-    constexpr int NK = kOuter / kBK16;
-    static_assert(NK == 4, "the schedule below is written for four chunks");
+    // K = 64 NK in chunks of 64, fully unrolled.  Two register buffers keep
+    // each chunk's loads two MFMA phases ahead of its use (one phase is far
+    // shorter than the memory latency); the old C values are requested two
+    // chunks before the end.  Loads complete in order, so C goes last.
+    static_assert(NK >= 2 && NK % 2 == 0, "an even number of chunks");
     const int lr = tid >> 1, lk = (tid & 1) * 32;   // loader: row lr, k lk..lk+31 of a chunk
-    u4_t r0[2][4], r1[2][4];                        // [operand][piece], chunks 0, 2 / 1, 3
+    u4_t r0[2][4], r1[2][4];                        // [operand][piece], even / odd chunks
 #define S16_LOAD(R, c)                                                                               \
     do {                                                                                             \
         const u4_t *pa = reinterpret_cast<const u4_t *>(QA + (int64_t)(I * kBM + lr) * ldq + (c) * kBK16 + lk); \
@@ -700,27 +703,30 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
     S16_LOAD(r1, 1);
     S16_STORE(r0, 0);
     __syncthreads();
-    S16_LOAD(r0, 2);
-    mma(0);
-    S16_STORE(r1, 1);
-    __syncthreads();
-    S16_LOAD(r1, 3);
-    mma(1);
-    S16_STORE(r0, 0);
-    __syncthreads();
     f4_t cpre[4][4];   // old C values
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-            const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
-            const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4);
-            cpre[mi][ni] = *reinterpret_cast<const f4_t *>(C + row + (int64_t)col * ldc);
+    for (int c = 0; c < NK; ++c) {
+        if (c + 2 < NK) {
+            if (c % 2 == 0) S16_LOAD(r0, c + 2);
+            else S16_LOAD(r1, c + 2);
         }
-    mma(0);
-    S16_STORE(r1, 1);
-    __syncthreads();
-    mma(1);
+        if (c == NK - 2) {
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni) {
+                    const int col = J * kBM + wn * 64 + ni * 16 + (lane & 15);
+                    const int row = I * kBM + wm * 64 + mi * 16 + 4 * (lane >> 4);
+                    cpre[mi][ni] = *reinterpret_cast<const f4_t *>(C + row + (int64_t)col * ldc);
+                }
+        }
+        mma(c % 2);
+        if (c + 1 < NK) {
+            if ((c + 1) % 2 == 0) S16_STORE(r0, 0);
+            else S16_STORE(r1, 1);
+            __syncthreads();
+        }
+    }
 #undef S16_LOAD
 #undef S16_STORE
     const bool diag_tile = I == J;   // uniform over the workgroup
@@ -752,7 +758,7 @@ size_t chol_panel_bytes(int, int64_t) { return 64; }
 size_t chol_panel16_bytes(int dtype, int64_t npad)
 {
     // two outer panels in flight (look-ahead): ping-pong buffers
-    return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)2 * npad * kOuter * 2 : 0;
+    return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)2 * npad * outer_width(npad) * 2 : 0;
 }
 
 template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
@@ -773,69 +779,64 @@ static hipError_t launch_syrk16(int tm, int ntiles, int K, const H *QA, const H 
                                 int64_t ldc, hipStream_t s)
 {
     const size_t smem = syrk16_smem_bytes();
-    hipError_t e = hipFuncSetAttribute((const void *)syrk16_kernel<H, MODE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    const void *fn = K == 512 ? (const void *)syrk16_kernel<H, MODE, 8> : (const void *)syrk16_kernel<H, MODE, 4>;
+    if (K != 512 && K != 256) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((syrk16_kernel<H, MODE>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc);
+    if (K == 512)
+        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 8>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc);
+    else
+        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 4>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc);
     return hipGetLastError();
 }
 
-// Factor outer panel `p` (columns p*256 .. p*256+255, rows p*256 .. npad):
-// diagonal block 0, then panel_b (panel solve of the first 128 columns; the
-// second diagonal block), then panel_c (update and panel solve of the second
-// 128 columns).  For 16-bit dtypes the solves also fill the row-major 16-bit
-// copy Q16 of the rows below the panel.
+// Factor the outer panel at P0 (ow columns, rows P0 .. npad):
+// diagonal block 0, then one panel_step launch per column block.
 template <typename T, int Q16T>
-static hipError_t launch_panel(int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info, int64_t P0,
-                               hipStream_t s, Prof *prof)
+static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
+                               int64_t P0, hipStream_t s, Prof *prof)
 {
     const double es = (double)sizeof(T);
-    const size_t smem_b = std::max(gemm_smem_bytes<T>(), diag_smem_bytes(sizeof(T)));
-    hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)panel_b_kernel<T, Q16T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)smem_b)) != hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)panel_c_kernel<T, Q16T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)gemm_smem_bytes<T>())) != hipSuccess)
-        return e;
-    T *W0 = Winv + P0 * kNB, *W1 = Winv + (P0 + kNB) * kNB;
+    const int ns = ow / kNB;
+    const size_t smem = std::max(gemm_smem_bytes<T>(), diag_smem_bytes(sizeof(T)));
+    hipError_t e = hipFuncSetAttribute((const void *)panel_step_kernel<T, Q16T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
     int tok = prof ? prof->start(s, GBEM_K_DIAG) : -1;
     hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
-                       A + P0 + P0 * lda, lda, W0, info, (int)P0);
+                       A + P0 + P0 * lda, lda, Winv + P0 * kNB, info, (int)P0);
     if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
-    const int64_t m0 = npad - P0 - kNB, m1 = npad - P0 - kOuter;   // rows below each diagonal block
-    T *Pan = A + (P0 + kNB) + P0 * lda;
-    tok = prof ? prof->start(s, GBEM_K_TRSM) : -1;
-    hipLaunchKernelGGL((panel_b_kernel<T, Q16T>), dim3((unsigned)(m0 / kNB)), dim3(256), smem_b, s, Pan, lda,
-                       (const T *)W0, W1, info, (int)(P0 + kNB), Q16);
-    if (prof)
-        prof->stop(tok, GBEM_K_TRSM, 2.0 * m0 * kNB * kNB + kNB * kNB * kNB * (1.0 + 2.0 / 3.0),
-                   2.0 * m0 * kNB * es + 5.0 * kNB * kNB * es + (Q16 ? 2.0 * m1 * kNB : 0.0), s);
-    if (m1 > 0) {
-        tok = prof ? prof->start(s, GBEM_K_PANEL) : -1;
-        hipLaunchKernelGGL((panel_c_kernel<T, Q16T>), dim3((unsigned)(m1 / kNB)), dim3(256), gemm_smem_bytes<T>(), s,
-                           Pan, lda, (const T *)W1, Q16);
+    T *P = A + P0 + P0 * lda;
+    for (int j = 0; j < ns; ++j) {
+        const int64_t m = npad - P0 - (int64_t)kNB * (j + 1);   // rows below diagonal block j
+        if (m <= 0) break;
+        tok = prof ? prof->start(s, GBEM_K_TRSM) : -1;
+        hipLaunchKernelGGL((panel_step_kernel<T, Q16T>), dim3((unsigned)(m / kNB)), dim3(256), smem, s, P, lda, j, ns,
+                           (const T *)(Winv + (P0 + (int64_t)kNB * j) * kNB), Winv + (P0 + (int64_t)kNB * (j + 1)) * kNB,
+                           info, (int)(P0 + kNB * (j + 1)), Q16);
         if (prof)
-            prof->stop(tok, GBEM_K_PANEL, 4.0 * m1 * kNB * kNB,
-                       5.0 * m1 * kNB * es + kNB * kNB * es + (Q16 ? 2.0 * m1 * kNB : 0.0), s);
+            prof->stop(tok, GBEM_K_TRSM,
+                       2.0 * m * kNB * kNB * (j + 1) + (j + 1 < ns ? 2.0 * kNB * kNB * kNB * (j + 1.0 + 1.0 / 3.0) : 0.0),
+                       (2.0 + j) * m * kNB * es + 3.0 * kNB * kNB * es + (Q16 ? 2.0 * m * kNB : 0.0), s);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t factor_panel(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
-                               int p, hipStream_t s, Prof *prof)
+static hipError_t factor_panel(int dtype, int64_t npad, int ow, T *A, int64_t lda, T *Winv, void *Q16,
+                               int32_t *info, int p, hipStream_t s, Prof *prof)
 {
-    const int64_t P0 = (int64_t)p * kOuter;
-    if (Q16 && dtype == GBEM_BF16) return launch_panel<T, 1>(npad, A, lda, Winv, Q16, info, P0, s, prof);
-    if (Q16 && dtype == GBEM_F16) return launch_panel<T, 2>(npad, A, lda, Winv, Q16, info, P0, s, prof);
-    return launch_panel<T, 0>(npad, A, lda, Winv, nullptr, info, P0, s, prof);
+    const int64_t P0 = (int64_t)p * ow;
+    if (Q16 && dtype == GBEM_BF16) return launch_panel<T, 1>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof);
+    if (Q16 && dtype == GBEM_F16) return launch_panel<T, 2>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof);
+    return launch_panel<T, 0>(npad, ow, A, lda, Winv, nullptr, info, P0, s, prof);
 }
 
 // Outer update of columns [c0, c0 + ncols) of the trailing matrix with the
-// outer panel whose rows below it start at `qrow`: C = A[c0.., c0..] (origin
-// on the diagonal), rows m = npad - c0.  TRI when the block is square.
+// outer panel at P0 (ow columns): C = A[c0.., c0..] (origin on the diagonal),
+// rows m = npad - c0.  TRI when the block is square.
 template <typename T>
-static hipError_t outer_update(int dtype, int64_t npad, T *A, int64_t lda, int64_t P0, const void *Q16,
+static hipError_t outer_update(int dtype, int64_t npad, int ow, T *A, int64_t lda, int64_t P0, const void *Q16,
                                int64_t c0, int64_t ncols, hipStream_t s, Prof *prof, int cls)
 {
     const int64_t m = npad - c0;
@@ -849,34 +850,34 @@ static hipError_t outer_update(int dtype, int64_t npad, T *A, int64_t lda, int64
     const int tok = prof ? prof->start(s, cls) : -1;
     hipError_t e;
     if (!b16) {
-        const T *Q = A + c0 + P0 * lda;   // L[c0:, P0:P0+256], column-major
-        e = tri ? launch_gemm<T, kTri, true, true>(tm, ntiles, kOuter, Q, lda, Q, lda, C, lda, s)
-                : launch_gemm<T, kRect, true, true>(tm, ntiles, kOuter, Q, lda, Q, lda, C, lda, s);
+        const T *Q = A + c0 + P0 * lda;   // L[c0:, P0:P0+ow], column-major
+        e = tri ? launch_gemm<T, kTri, true, true>(tm, ntiles, ow, Q, lda, Q, lda, C, lda, s)
+                : launch_gemm<T, kRect, true, true>(tm, ntiles, ow, Q, lda, Q, lda, C, lda, s);
     } else {
-        const int64_t q0 = c0 - (P0 + kOuter);   // first row of Q16 used
+        const int64_t q0 = c0 - (P0 + ow);   // first row of Q16 used
         if (dtype == GBEM_BF16) {
-            const __bf16 *Q = (const __bf16 *)Q16 + q0 * kOuter;
-            e = tri ? launch_syrk16<__bf16, kTri>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s)
-                    : launch_syrk16<__bf16, kRect>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s);
+            const __bf16 *Q = (const __bf16 *)Q16 + q0 * ow;
+            e = tri ? launch_syrk16<__bf16, kTri>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s)
+                    : launch_syrk16<__bf16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s);
         } else {
-            const _Float16 *Q = (const _Float16 *)Q16 + q0 * kOuter;
-            e = tri ? launch_syrk16<_Float16, kTri>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s)
-                    : launch_syrk16<_Float16, kRect>(tm, ntiles, kOuter, Q, Q, kOuter, (float *)C, lda, s);
+            const _Float16 *Q = (const _Float16 *)Q16 + q0 * ow;
+            e = tri ? launch_syrk16<_Float16, kTri>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s)
+                    : launch_syrk16<_Float16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s);
         }
     }
-    if (prof) prof->stop(tok, cls, 2.0 * tiles_el * kOuter, 2.0 * tiles_el * es + (double)m * kOuter * (b16 ? 2.0 : es), s);
+    if (prof) prof->stop(tok, cls, 2.0 * tiles_el * ow, 2.0 * tiles_el * es + (double)m * ow * (b16 ? 2.0 : es), s);
     return e;
 }
 
-// Right-looking Cholesky with 256-wide outer panels and one panel of
-// look-ahead: after the outer update of the next panel's columns (main
-// stream), the next panel is factored on the side stream while the main
-// stream applies the rest of the outer update.
+// Right-looking Cholesky with ow-wide outer panels and one panel of
+// look-ahead: the side stream updates the next panel's columns and factors
+// it while the main stream applies the rest of the outer update.
 template <typename T>
 static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
                            hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
 {
-    const int nbo = (int)(npad / kOuter);
+    const int ow = outer_width(npad);
+    const int nbo = (int)(npad / ow);
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_smem_bytes(sizeof(T)));
     if (e != hipSuccess) return e;
@@ -887,7 +888,7 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     }
     const bool b16 = dtype == GBEM_F16 || dtype == GBEM_BF16;
     auto q16 = [&](int p) -> void * {
-        return b16 ? (void *)((char *)Q16 + (size_t)(p & 1) * npad * kOuter * 2) : nullptr;
+        return b16 ? (void *)((char *)Q16 + (size_t)(p & 1) * npad * ow * 2) : nullptr;
     };
     // Side stream: the latency-critical chain (update of the next panel's
     // columns, then its factorisation).  Main stream: the rest of each outer
@@ -897,23 +898,23 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     hipEvent_t *evP = ev.data(), *evB = ev.data() + nbo + 1;
     if ((e = hipEventRecord(evB[nbo], s)) != hipSuccess) return e;   // inputs of this call are ready
     if ((e = hipStreamWaitEvent(side, evB[nbo], 0)) != hipSuccess) return e;
-    if ((e = factor_panel<T>(dtype, npad, A, lda, Winv, q16(0), info, 0, side, prof)) != hipSuccess) return e;
+    if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, q16(0), info, 0, side, prof)) != hipSuccess) return e;
     if ((e = hipEventRecord(evP[0], side)) != hipSuccess) return e;
     for (int K = 0; K + 1 < nbo; ++K) {
-        const int64_t P0 = (int64_t)K * kOuter;
+        const int64_t P0 = (int64_t)K * ow;
         // side: (a) panel K+1's columns with panel K, then factor panel K+1
         if (K > 0 && (e = hipStreamWaitEvent(side, evB[K - 1], 0)) != hipSuccess) return e;
-        if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), P0 + kOuter, kOuter, side, prof,
-                                 GBEM_K_PANEL)) != hipSuccess)
+        if ((e = outer_update<T>(dtype, npad, ow, A, lda, P0, q16(K), P0 + ow, ow, side, prof, GBEM_K_PANEL)) !=
+            hipSuccess)
             return e;
-        if ((e = factor_panel<T>(dtype, npad, A, lda, Winv, q16(K + 1), info, K + 1, side, prof)) != hipSuccess)
+        if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, q16(K + 1), info, K + 1, side, prof)) != hipSuccess)
             return e;
         if ((e = hipEventRecord(evP[K + 1], side)) != hipSuccess) return e;
         // main: (b) the columns beyond panel K+1 with panel K
-        const int64_t c0 = P0 + 2 * kOuter;
+        const int64_t c0 = P0 + 2 * ow;
         if (c0 < npad) {
             if ((e = hipStreamWaitEvent(s, evP[K], 0)) != hipSuccess) return e;
-            if ((e = outer_update<T>(dtype, npad, A, lda, P0, q16(K), c0, npad - c0, s, prof, GBEM_K_SYRK)) !=
+            if ((e = outer_update<T>(dtype, npad, ow, A, lda, P0, q16(K), c0, npad - c0, s, prof, GBEM_K_SYRK)) !=
                 hipSuccess)
                 return e;
         }
@@ -926,7 +927,7 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
 hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *, void *panel16,
                        int32_t *info, hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
 {
-    if (npad % kOuter) return hipErrorInvalidValue;
+    if (npad % outer_width(npad)) return hipErrorInvalidValue;
     if (dtype == GBEM_F64)
         return factor_t<double>(dtype, npad, (double *)A, lda, (double *)Winv, nullptr, info, s, side, ev, prof);
     return factor_t<float>(dtype, npad, (float *)A, lda, (float *)Winv, panel16, info, s, side, ev, prof);

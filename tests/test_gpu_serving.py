@@ -56,7 +56,7 @@ def test_mix_equals_alone(meshes, mode):
 
 def test_admission_under_small_budget(meshes):
     lay, lo, hi, cond = max(meshes, key=lambda m: m[1].shape[0])
-    npad = (lo.shape[0] + 255) // 256 * 256
+    npad = (lo.shape[0] + 511) // 512 * 512
     budget = int(2.5 * npad * npad * 8)          # about two jobs of this size at once
     with binding.Context(0, budget) as ctx:
         jobs = [ctx.submit(m[1], m[2], m[3], m[0].n_conductors, m[0].eps_r, m[0].length_unit_m)
