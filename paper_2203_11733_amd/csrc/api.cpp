@@ -110,23 +110,30 @@ struct Workspace {
 
     // flags of the persistent solves: zeroed once when (re)allocated; the
     // epoch restarts with them
+    // (published words are epoch-tagged: zero tags never match an epoch >= 1)
     hipError_t ensure_sync(int64_t npad, hipStream_t st)
     {
-        const size_t need = (size_t)2 * (npad / kNB) * 4 + 256;
-        if (sflags.cap < need) {
+        const size_t nflag = (((size_t)2 * (npad / kNB) * 4 + 256) + 255) / 256 * 256;
+        const size_t npub = (size_t)2 * npad * kMaxPub * 8, nsub = (size_t)2 * npad * kNB * 4;
+        const size_t need = nflag + npub + nsub;
+        if (sflags.cap < need || sync_npad != npad) {
             hipError_t e = sflags.ensure(need);
             if (e != hipSuccess) return e;
-            e = hipMemsetAsync(sflags.p, 0, sflags.cap, st);
+            e = hipMemsetAsync(sflags.p, 0, need, st);
             if (e != hipSuccess) return e;
             sync.epoch = 0;
             sync.base_f = sync.base_b = 0;
+            sync_npad = npad;
         }
         int32_t *f = sflags.as<int32_t>();
-        sync.err = f;                      // word 0: error flag
+        sync.err = f;                      // word 0: error flag, words 1, 2: ticket counters
         sync.flags_f = f + 64;
-        sync.flags_b = f + 64 + (sflags.cap / 4 - 64) / 2;
+        sync.flags_b = f + 64 + (nflag / 4 - 64) / 2;
+        sync.pub = reinterpret_cast<uint64_t *>(sflags.as<char>() + nflag);
+        sync.sub = reinterpret_cast<float *>(sflags.as<char>() + nflag + npub);
         return hipSuccess;
     }
+    int64_t sync_npad = -1;
 
     size_t bytes() const
     {
@@ -170,6 +177,7 @@ static size_t footprint(int64_t n, int m, int factor_dtype)
     if (factor_dtype != GBEM_F64) b += (size_t)npad * npad * 4;           // FP32 factor
     const size_t es = factor_dtype == GBEM_F64 ? 8 : 4;
     b += (size_t)npad * kNB * es + (size_t)npad * kPad * 2 * 2;          // W, 16-bit panels
+    b += (size_t)npad * (2 * kMaxPub * 8 + 2 * kNB * 4);                 // solve: published blocks, M_k, N_k
     b += 4 * (size_t)npad * m * 8 + (size_t)npad * 8;                    // B X R D, s
     b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 12;           // mesh, panels, near list + queue
     return b;
@@ -369,6 +377,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             dtype = (dtype == GBEM_F32) ? GBEM_F64 : GBEM_F32;   // BF16/F16 -> F32 -> F64
             continue;
         }
+        HIPCHK(chol_solve_prep(dtype, npad, Fm, lda, ws.Winv.p, ws.sync, st), "solve prep");
         HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
         HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
         if (dtype == GBEM_F64) {
@@ -1072,10 +1081,11 @@ static gbem_status chol_common(gbem_ctx *ctx, int32_t n, int32_t dtype, void *A,
         return GBEM_OK;
     }
     HIPCHK(chol_diag_inverses(dtype, npad, Ap.p, npad, ws.Winv.p, st), "diag inverses");
+    HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
+    HIPCHK(chol_solve_prep(dtype, npad, Ap.p, npad, ws.Winv.p, ws.sync, st), "solve prep");
     HIPCHK(ws.X.ensure((size_t)npad * nrhs * 8), "alloc");
     HIPCHK(hipMemsetAsync(ws.X.p, 0, (size_t)npad * nrhs * 8, st), "memset");
     HIPCHK(hipMemcpy2DAsync(ws.X.p, 8 * npad, Bm, 8 * ldb, 8 * n, nrhs, hipMemcpyDeviceToDevice, st), "copy B");
-    HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
     HIPCHK(hipMemsetAsync(ws.sync.err, 0, 4, st), "memset");
     HIPCHK(chol_solve(dtype, npad, Ap.p, npad, ws.Winv.p, nrhs, ws.X.as<double>(), npad, ws.sync, st), "solve");
     int32_t serr = 0;

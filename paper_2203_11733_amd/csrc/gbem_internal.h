@@ -162,11 +162,22 @@ struct SolveSync {
     int32_t *err = nullptr;
     int32_t epoch = 0;
     uint32_t base_f = 0, base_b = 0;   // host copies of the two ticket counters
+    // FP32 solves: published blocks (2 directions x npad x kMaxPub words) and
+    // the sub-diagonal products M_k, N_k (2 x npad x 128 floats) of the
+    // factor prepared last
+    uint64_t *pub = nullptr;
+    float *sub = nullptr;
+    const void *prep_of = nullptr;
+    int64_t prep_npad = 0;
 };
+constexpr int kMaxPub = 64;
 // solve.hip
 hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv,
                       int m, double *B, int64_t ldb, SolveSync &sync, hipStream_t s,
                       Prof *prof = nullptr);
+// M_k and N_k of a new FP32 factor (no-op for FP64); required before chol_solve
+hipError_t chol_solve_prep(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv,
+                           SolveSync &sync, hipStream_t s);
 constexpr int kResMaxSplit = 16;
 int residual_splits(int npad);
 size_t chol_winv_bytes(int dtype, int64_t npad);

@@ -210,30 +210,44 @@ __global__ __launch_bounds__(256) void bwd_solve_kernel(const T *__restrict__ L,
 // FP32 storage (the low-precision factors): the same persistent scheme with
 // the block products on MFMA (v_mfma_f32_16x16x4f32, FP32 accumulation; the
 // solve only has to match the precision of the factor, the FP64 refinement
-// supplies the rest).  Per workgroup:
-//   - 128 x 128 tiles of L (then W_k) stream through one LDS tile; the next
-//     tile is loaded into registers while the MFMAs work on the current one;
-//   - published blocks are read and written with agent-scope atomic loads and
-//     stores (they bypass the non-coherent per-XCD L2), so publishing needs
-//     only the completion of those stores before the flag, and consuming needs
-//     no cache invalidation;
-//   - a published block k implies that every block before it (in solve
-//     order) is published, so one observed flag covers all earlier blocks.
-// Waves split the 128-long inner dimension (and the rows when MC = 64); their
-// partial sums are added through LDS once per block row.
+// supplies the rest).  With D_k = L_kk and W_k = D_k^{-1}:
+//   forward   Y_k = W_k (B_k - sum_{j<k-1} L_kj Y_j) - M_k Y_{k-1},
+//             M_k = W_k L_{k,k-1};
+//   backward  X_k = W_k^T (Y_k - sum_{j>k+1} L_jk^T X_j) - N_k^T X_{k+1},
+//             N_k = L_{k+1,k} W_k.
+// M_k and N_k are formed once per factor (solve_prep), so after the block a
+// workgroup waits for last has arrived only one 128 x 128 product remains;
+// everything else overlaps the wait.  Right-hand sides are solved in
+// independent chains of 16 columns (the columns never mix), each block of
+// each chain by one workgroup.  Per workgroup:
+//   - W_k stays in LDS and M_k / N_k in registers from the start; the L
+//     blocks stream through a second LDS tile, the next one loaded into
+//     registers while the MFMAs work on the current one, so nothing on the
+//     path after a published block waits for HBM;
+//   - each wave owns 32 rows of the block, so the products need no
+//     cross-wave reduction;
+//   - a finished block is published as 64-bit words (value bits, epoch) with
+//     agent-scope atomic stores (they bypass the non-coherent per-XCD L2);
+//     consumers load the words with agent-scope atomic loads and re-load the
+//     ones whose epoch is stale.  Data and readiness travel together, so there
+//     is no separate flag and no store-completion wait before one.
+// Word layout of a published block (128 x 16 values): word w = R * 256 +
+// q * 64 + l holds row 16 R + 4 (l / 16) + q, column l % 16 (the MFMA output
+// layout of the producing wave, so each store instruction covers 512
+// contiguous bytes).
+// LDS: two 128-row tiles of stride TLD (FWD 144, BWD 132: conflict-free
+// fragment reads in either orientation) and two 128 x 16 right-operand
+// buffers; in FWD those sit in the last 16 floats of each tile row, which the
+// tiles leave free, so the layout fits the 160 KB of a CU.
 // ------------------------------------------------------------------------
-template <int MC, bool FWD> struct SolveCfg {
-    static constexpr int CB = MC / 16;                 // 16-column blocks of the RHS
-    static constexpr int NKG = MC <= 32 ? 4 : 2;      // wave groups over the inner dimension
-    static constexpr int NRG = 4 / NKG;               // wave groups over the rows
-    static constexpr int RB = 8 / NRG;                // 16-row blocks per wave
-    static constexpr int KW = kNB / NKG;              // inner range per wave
-    static constexpr int TLD = FWD ? 144 : 132;       // LDS tile stride (conflict-free fragment reads)
-    static constexpr int YLD = MC == 16 ? 16 : (MC == 32 ? 48 : 80);
-    static constexpr int RLD = MC + 4;                // partial-sum stride
-    static constexpr int EPT = kNB * MC / 256;        // (row, column) elements per thread
-    static constexpr size_t kTileBytes = (size_t)kNB * 144 * 4;
-    static constexpr size_t kSmem = kTileBytes + (size_t)2 * kNB * YLD * 4 + 64;
+constexpr int kChain = 16;   // right-hand sides per chain
+template <bool FWD> struct SolveCfg {
+    static constexpr int RB = 2;                      // 16-row blocks per wave
+    static constexpr int NW = 8;                      // published words per thread
+    static constexpr int TLD = FWD ? 144 : 132;       // LDS tile stride
+    static constexpr int YLD = FWD ? 144 : 16;        // right-operand stride
+    static constexpr size_t kTileBytes = (size_t)kNB * TLD * 4;
+    static constexpr size_t kSmem = 2 * kTileBytes + (FWD ? 0 : (size_t)2 * kNB * kChain * 4);
 };
 typedef float f4s_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u4s_t __attribute__((ext_vector_type(4)));
@@ -256,243 +270,287 @@ __device__ __forceinline__ void tile_store(float *tile, const u4s_t (&tr)[16])
     for (int q = 0; q < 16; ++q) dst[q] = tr[q];
 }
 
-// acc[rb][cb] += A(i, t) Y(t, n) over this wave's inner range; A(i, t) =
-// tile[t*TLD + i] (FWD: L_kj, W_k) or tile[i*TLD + t] (BWD: L_jk^T, W_k^T)
-template <int MC, bool FWD, int RB, int CB>
-__device__ __forceinline__ void tile_product(f4s_t (&acc)[RB][CB], const float *tile, const float *ys)
+// acc[rb] += A(i, t) Y(t, n) over t = 0..127 for the wave's rows
+// i = 32 w + 16 rb + ..; A(i, t) = tile[t*TLD + i] (FWD: L_kj, W_k, M_k) or
+// tile[i*TLD + t] (BWD: L_jk^T, W_k^T, N_k^T); Y(t, n) = ys[t*YLD + n]
+template <bool FWD>
+__device__ __forceinline__ void tile_product(f4s_t (&acc)[2], const float *tile, const float *ys)
 {
-    typedef SolveCfg<MC, FWD> C;
+    typedef SolveCfg<FWD> C;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rg = w % C::NRG, kg = w / C::NRG;
 #pragma unroll 4
-    for (int kk = 0; kk < C::KW; kk += 4) {
-        const int t = kg * C::KW + kk + (lane >> 4);
-        float b[C::CB];
-#pragma unroll
-        for (int cb = 0; cb < C::CB; ++cb) b[cb] = ys[t * C::YLD + cb * 16 + (lane & 15)];
+    for (int kk = 0; kk < kNB; kk += 4) {
+        const int t = kk + (lane >> 4);
+        const float b = ys[t * C::YLD + (lane & 15)];
 #pragma unroll
         for (int rb = 0; rb < C::RB; ++rb) {
-            const int i = (rg * C::RB + rb) * 16 + (lane & 15);
+            const int i = (w * C::RB + rb) * 16 + (lane & 15);
             const float a = FWD ? tile[t * C::TLD + i] : tile[i * C::TLD + t];
-#pragma unroll
-            for (int cb = 0; cb < C::CB; ++cb)
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[cb], acc[rb][cb], 0, 0, 0);
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[rb], 0, 0, 0);
         }
     }
 }
 
-// partial sums of all waves -> red (reusing the tile), then each thread adds
-// the groups for its elements e = tid + 256 u: row e % 128, column e / 128
-template <int MC, bool FWD, int EPT, int RB, int CB>
-__device__ __forceinline__ void reduce_partials(float (&out)[EPT], f4s_t (&acc)[RB][CB], float *red)
+// Issue the loads of this thread's words (w = tid + 256 u) of a published block.
+__device__ __forceinline__ void pub_issue(uint64_t (&wd)[8], const uint64_t *blk)
 {
-    typedef SolveCfg<MC, FWD> C;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rg = w % C::NRG, kg = w / C::NRG;
+    const uint64_t *p = blk + threadIdx.x;
 #pragma unroll
-    for (int rb = 0; rb < C::RB; ++rb)
+    for (int u = 0; u < 8; ++u) wd[u] = __hip_atomic_load(p + 256 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Complete the loads of a block: when some word is stale, one thread polls
+// word 0 until it carries `tag` (a waiting workgroup then adds one load per
+// poll to the memory system, not the whole block), after which the stale
+// words are re-loaded until all carry `tag`.  Bounded; returns the same value
+// in every thread (false after a timeout, with the error word set).
+__device__ __forceinline__ bool pub_complete(uint64_t (&wd)[8], const uint64_t *blk, uint32_t tag, int32_t *err,
+                                             int limit)
+{
+    const uint64_t *p = blk + threadIdx.x;
+    bool good = true;
 #pragma unroll
-        for (int cb = 0; cb < C::CB; ++cb)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = (rg * C::RB + rb) * 16 + 4 * (lane >> 4) + q, n = cb * 16 + (lane & 15);
-                red[(kg * kNB + row) * C::RLD + n] = acc[rb][cb][q];
-            }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < C::EPT; ++u) {
-        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
-        float s = 0.f;
-#pragma unroll
-        for (int g = 0; g < C::NKG; ++g) s += red[(g * kNB + row) * C::RLD + n];
-        out[u] = s;
+    for (int u = 0; u < 8; ++u) good = good && (uint32_t)(wd[u] >> 32) == tag;
+    if (!__syncthreads_or(!good)) return true;
+    if (threadIdx.x == 0) {
+        for (int n = 0; n < limit; ++n) {
+            if ((uint32_t)(__hip_atomic_load(blk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) == tag) break;
+            __builtin_amdgcn_s_sleep(2);
+        }
     }
+    __syncthreads();
+    for (int n = 0;; ++n) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if ((uint32_t)(wd[u] >> 32) != tag)
+                wd[u] = __hip_atomic_load(p + 256 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = true;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) good = good && (uint32_t)(wd[u] >> 32) == tag;
+        if (good || n >= limit) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if (!good) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return !__syncthreads_or(!good);
+}
+// words -> ys[row * YLD + col] (FP32)
+template <bool FWD>
+__device__ __forceinline__ void pub_to_lds(float *ys, const uint64_t (&wd)[8])
+{
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        ys[(u * 16 + 4 * (lane >> 4) + q) * SolveCfg<FWD>::YLD + (lane & 15)] = __uint_as_float((uint32_t)wd[u]);
 }
 
-template <int MC, bool FWD>
+// One workgroup per (block, chain).  Ticket t -> block t / nch in solve order,
+// chain t % nch (columns 16 c ..); Y holds the published words of chain c at
+// Y + c * npad * 16.
+template <bool FWD>
 __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__ L, int64_t lda,
-                                                       const float *__restrict__ W, double *B, int64_t ldb, int m,
-                                                       int nb, int32_t *flags, int32_t *__restrict__ counter,
-                                                       uint32_t base, int32_t epoch, int32_t *err, int limit)
+                                                       const float *__restrict__ W, const float *__restrict__ S,
+                                                       double *B, int64_t ldb, uint64_t *Y, int m, int nb, int nch,
+                                                       int32_t *__restrict__ counter, uint32_t base, uint32_t tag,
+                                                       int32_t *err, int limit)
 {
-    typedef SolveCfg<MC, FWD> C;
+    typedef SolveCfg<FWD> C;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    float *tile = reinterpret_cast<float *>(smem_raw);
-    float *ysb = reinterpret_cast<float *>(smem_raw + C::kTileBytes);   // two Y buffers
-    int *ready_s = reinterpret_cast<int *>(smem_raw + C::kTileBytes + (size_t)2 * kNB * C::YLD * 4);
-    const int tk = take_ticket(counter, base);
-    if (tk < 0 || tk >= nb) {
+    float *tile = reinterpret_cast<float *>(smem_raw);                  // streaming L blocks, then M_k / N_k
+    float *wtile = reinterpret_cast<float *>(smem_raw + C::kTileBytes);   // W_k
+    float *ys0 = FWD ? tile + kNB : reinterpret_cast<float *>(smem_raw + 2 * C::kTileBytes);
+    float *ys1 = FWD ? wtile + kNB : ys0 + kNB * kChain;
+    const int t = take_ticket(counter, base);
+    if (t < 0 || t >= nb * nch) {
         if (threadIdx.x == 0) __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
+    const int tk = t / nch, ch = t % nch;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // solve order: FWD blocks 0, 1, ..; BWD blocks nb-1, nb-2, ..
     const int k = FWD ? tk : nb - 1 - tk, k0 = k * kNB;
-    const int cnt = tk;                                  // blocks this one depends on
+    const int cnt = tk;                      // blocks this one depends on
+    const int nn = cnt > 0 ? cnt - 1 : 0;    // all but the last of them
+    const int mc = min(kChain, m - ch * kChain);   // columns of this chain
+    B += (int64_t)ch * kChain * ldb;
+    Y += (int64_t)ch * nb * kNB * kChain;
     auto jof = [&](int idx) { return FWD ? idx : nb - 1 - idx; };
-    // block of the matrix multiplying Y_j: FWD L[k, j] at (k0, j0); BWD L[j, k] at (j0, k0)
-    auto lblock = [&](int j) -> const float * {
+    auto pblk = [&](int idx) { return Y + (int64_t)jof(idx) * kNB * kChain; };
+    auto lsrc = [&](int idx) {   // L_kj (FWD) or L_jk (BWD) of the idx-th dependency
+        const int j = jof(idx);
         return FWD ? L + k0 + (int64_t)j * kNB * lda : L + (int64_t)j * kNB + (int64_t)k0 * lda;
     };
-    const float *Wk = W + (int64_t)k * kNB * kNB;
+    // element (rb, q) of this thread: row within the block; column lane % 16
+    auto erow = [&](int rb, int q) { return (wave * C::RB + rb) * 16 + 4 * (lane >> 4) + q; };
+    const int col = lane & 15;
 
-    // right-hand side of this block (read once, FP64)
-    double bk[C::EPT];
-#pragma unroll
-    for (int u = 0; u < C::EPT; ++u) {
-        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
-        bk[u] = n < m ? B[(k0 + row) + (int64_t)n * ldb] : 0.0;
-    }
-
-    // wait until the idx-th block in solve order is published (thread 0
-    // polls; the observed index is shared through LDS)
-    int ready = -1;
-    auto ensure_ready = [&](int idx) -> bool {
-        if (idx <= ready) return true;
-        if (threadIdx.x == 0) {
-            int got = -2;
-            if (wait_flag(flags + jof(idx), epoch, err, limit)) {
-                got = idx;
-                // blocks are published in solve order: probe further ahead
-                // (all loads in flight at once) and keep the newest published
-                int32_t f[8];
-#pragma unroll
-                for (int p = 0; p < 8; ++p) {
-                    const int q = min(cnt - 1, idx + (1 << (p + 1)) - 1);
-                    f[p] = __hip_atomic_load(flags + jof(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-#pragma unroll
-                for (int p = 0; p < 8; ++p)
-                    if (f[p] == epoch) got = max(got, min(cnt - 1, idx + (1 << (p + 1)) - 1));
-            }
-            *ready_s = got;
-        }
-        __syncthreads();
-        ready = *ready_s;
-        return ready >= idx;
-    };
-    // Y_j (FP64, published) -> registers
-    auto y_load = [&](double (&yr)[C::EPT], int j) {
-#pragma unroll
-        for (int u = 0; u < C::EPT; ++u) {
-            const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
-            yr[u] = n < m ? __hip_atomic_load(B + (j * kNB + row) + (int64_t)n * ldb, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)
-                          : 0.0;
-        }
-    };
-    auto y_store = [&](float *ys, const double (&yr)[C::EPT]) {
-#pragma unroll
-        for (int u = 0; u < C::EPT; ++u) {
-            const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
-            ys[row * C::YLD + n] = (float)yr[u];
-        }
-    };
-
-    f4s_t acc[C::RB][C::CB];
+    double bk[C::RB][4];
 #pragma unroll
     for (int rb = 0; rb < C::RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < C::CB; ++cb) acc[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 4; ++q) bk[rb][q] = col < mc ? B[(k0 + erow(rb, q)) + (int64_t)col * ldb] : 0.0;
 
-    u4s_t tr[16];
-    double yr[C::EPT];
-    bool ok = true;
-    if (cnt > 0) {
-        tile_load(tr, lblock(jof(0)), lda);
-        ok = ensure_ready(0);
-        if (ok) y_load(yr, jof(0));
+    u4s_t tr[16], sr[16];
+    tile_load(tr, W + (int64_t)k * kNB * kNB, kNB);
+    if (cnt > 0) tile_load(sr, S + (int64_t)k * kNB * kNB, kNB);
+    tile_store<C::TLD>(wtile, tr);
+    if (nn > 0) tile_load(tr, lsrc(0), lda);
+
+    f4s_t acc[2] = {f4s_t{0.f, 0.f, 0.f, 0.f}, f4s_t{0.f, 0.f, 0.f, 0.f}};
+    uint64_t wd[8];
+    if (nn > 0) {
+        pub_issue(wd, pblk(0));
+        if (!pub_complete(wd, pblk(0), tag, err, limit)) return;
+        pub_to_lds<FWD>(ys0, wd);
         tile_store<C::TLD>(tile, tr);
-        y_store(ysb, yr);
-        tile_load(tr, cnt > 1 ? lblock(jof(1)) : Wk, cnt > 1 ? lda : (int64_t)kNB);
+        if (nn > 1) tile_load(tr, lsrc(1), lda);
         __syncthreads();
-        for (int idx = 0; idx < cnt && ok; ++idx) {
-            const bool more = idx + 1 < cnt;
-            // the next Y block: loaded ahead of the product when already
-            // published, else waited for after it
-            const bool early = more && idx + 1 <= ready;
-            if (early) y_load(yr, jof(idx + 1));
-            tile_product<MC, FWD>(acc, tile, ysb + (idx & 1) * kNB * C::YLD);
-            if (more && !early) {
-                ok = ensure_ready(idx + 1);
-                if (ok) y_load(yr, jof(idx + 1));
-            }
+        for (int idx = 0; idx < nn; ++idx) {
+            const bool more = idx + 1 < nn;
+            if (more) pub_issue(wd, pblk(idx + 1));
+            tile_product<FWD>(acc, tile, (idx & 1) ? ys1 : ys0);
+            if (!more) break;
+            if (!pub_complete(wd, pblk(idx + 1), tag, err, limit)) return;
             __syncthreads();
             tile_store<C::TLD>(tile, tr);
-            if (more) {
-                y_store(ysb + ((idx + 1) & 1) * kNB * C::YLD, yr);
-                if (idx + 2 < cnt) tile_load(tr, lblock(jof(idx + 2)), lda);
-                else tile_load(tr, Wk, kNB);
-            }
+            pub_to_lds<FWD>(((idx + 1) & 1) ? ys1 : ys0, wd);
+            if (idx + 2 < nn) tile_load(tr, lsrc(idx + 2), lda);
             __syncthreads();
         }
-        if (!ok) return;   // error word set; the host reports it
-        // tile holds L of the last block or W_k: W_k is in tr when cnt > 0
-    } else {
-        tile_load(tr, Wk, kNB);
     }
-    // r = B_k - sum_j (...) Y_j  -> ys[0]
-    float part[C::EPT];
-    __syncthreads();
-    reduce_partials<MC, FWD>(part, acc, tile);
-    float *ys = ysb;
-    __syncthreads();
+    __syncthreads();   // the last product is done with tile, ys0 and ys1
+    // Z = W_k (B_k - acc): the difference goes through LDS as the right operand
 #pragma unroll
-    for (int u = 0; u < C::EPT; ++u) {
-        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
-        ys[row * C::YLD + n] = (float)(bk[u] - (double)part[u]);
+    for (int rb = 0; rb < C::RB; ++rb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ys0[erow(rb, q) * C::YLD + col] = (float)(bk[rb][q] - (double)acc[rb][q]);
+        acc[rb] = f4s_t{0.f, 0.f, 0.f, 0.f};
     }
-    tile_store<C::TLD>(tile, tr);   // W_k
+    if (cnt > 0) {
+        tile_store<C::TLD>(tile, sr);   // M_k / N_k
+        pub_issue(wd, pblk(cnt - 1));   // the last dependency, completed after the product
+    }
     __syncthreads();
+    tile_product<FWD>(acc, wtile, ys0);
+    if (cnt > 0) {
+        // Y_k = Z - M_k Y_{k-1} (FWD) or X_k = Z - N_k^T X_{k+1} (BWD)
+        if (!pub_complete(wd, pblk(cnt - 1), tag, err, limit)) return;
+        pub_to_lds<FWD>(ys1, wd);
+        __syncthreads();
+        f4s_t acc2[2] = {f4s_t{0.f, 0.f, 0.f, 0.f}, f4s_t{0.f, 0.f, 0.f, 0.f}};
+        tile_product<FWD>(acc2, tile, ys1);
+        acc[0] -= acc2[0];
+        acc[1] -= acc2[1];
+    }
+    // publish, then the FP64 result
+    uint64_t *yk = Y + (int64_t)k * kNB * kChain;
 #pragma unroll
     for (int rb = 0; rb < C::RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < C::CB; ++cb) acc[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
-    tile_product<MC, FWD>(acc, tile, ys);
-    __syncthreads();
-    reduce_partials<MC, FWD>(part, acc, tile);
-#pragma unroll
-    for (int u = 0; u < C::EPT; ++u) {
-        const int e = threadIdx.x + 256 * u, row = e % kNB, n = e / kNB;
-        if (n < m)
-            __hip_atomic_store(B + (k0 + row) + (int64_t)n * ldb, (double)part[u], __ATOMIC_RELAXED,
+        for (int q = 0; q < 4; ++q)
+            __hip_atomic_store(yk + (wave * C::RB + rb) * 256 + q * 64 + lane,
+                               ((uint64_t)tag << 32) | __float_as_uint(acc[rb][q]), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-    }
-    // the stores above complete before the flag is raised
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + k, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (col < mc) B[(k0 + erow(rb, q)) + (int64_t)col * ldb] = (double)acc[rb][q];
 }
 
-template <int MC>
-static hipError_t solve32_mc(int64_t npad, const float *L, int64_t lda, const float *W, int m, double *B,
-                             int64_t ldb, SolveSync &sync, hipStream_t s, Prof *prof)
+// M_k = W_k L_{k,k-1} (k = 1 .. nb-1, slot k of S) and N_k = L_{k+1,k} W_k
+// (k = 0 .. nb-2, slot k of S + npad * 128).  One workgroup per product,
+// both operands in LDS, 8 x 8 outputs per thread on FP32 FMAs.
+constexpr int kPLd = kNB + 4;
+__global__ __launch_bounds__(256) void solve_prep_kernel(const float *__restrict__ L, int64_t lda,
+                                                         const float *__restrict__ W, float *__restrict__ S,
+                                                         int64_t npad)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    float *As = reinterpret_cast<float *>(smem_raw);   // As[t * kPLd + i] = A(i, t)
+    float *Bs = As + kNB * kPLd;                       // Bs[t * kPLd + c] = B(t, c)
+    const bool second = blockIdx.y == 1;
+    const int k = second ? blockIdx.x : blockIdx.x + 1;
+    const int64_t k0 = (int64_t)k * kNB;
+    const float *Wk = W + k0 * kNB;
+    const float *A = second ? L + (k0 + kNB) + k0 * lda : Wk;
+    const int64_t ldA = second ? lda : kNB;
+    const float *Bm = second ? Wk : L + k0 + (k0 - kNB) * lda;
+    const int64_t ldB = second ? kNB : lda;
+    float *out = S + (second ? npad * kNB : 0) + k0 * kNB;
+    const int tid = threadIdx.x;
+    {
+        const int c = tid >> 1, h = tid & 1;
+        for (int r = h * 64; r < h * 64 + 64; r += 4) {
+            const f4s_t a = *reinterpret_cast<const f4s_t *>(A + r + (int64_t)c * ldA);
+            *reinterpret_cast<f4s_t *>(As + c * kPLd + r) = a;
+            const f4s_t b = *reinterpret_cast<const f4s_t *>(Bm + r + (int64_t)c * ldB);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[(r + e) * kPLd + c] = b[e];
+        }
+    }
+    __syncthreads();
+    const int ti = (tid & 15) * 8, tc = (tid >> 4) * 8;
+    float acc[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = 0.f;
+    for (int t = 0; t < kNB; ++t) {
+        const f4s_t a0 = *reinterpret_cast<const f4s_t *>(As + t * kPLd + ti);
+        const f4s_t a1 = *reinterpret_cast<const f4s_t *>(As + t * kPLd + ti + 4);
+        const f4s_t b0 = *reinterpret_cast<const f4s_t *>(Bs + t * kPLd + tc);
+        const f4s_t b1 = *reinterpret_cast<const f4s_t *>(Bs + t * kPLd + tc + 4);
+        const float a[8] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        const float b[8] = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        f4s_t o0, o1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o0[i] = acc[i][j];
+            o1[i] = acc[i + 4][j];
+        }
+        *reinterpret_cast<f4s_t *>(out + (int64_t)(tc + j) * kNB + ti) = o0;
+        *reinterpret_cast<f4s_t *>(out + (int64_t)(tc + j) * kNB + ti + 4) = o1;
+    }
+}
+
+static hipError_t solve32(int64_t npad, const float *L, int64_t lda, const float *W, int m, double *B, int64_t ldb,
+                          SolveSync &sync, hipStream_t s, Prof *prof)
 {
     const int nb = (int)(npad / kNB);
-    const size_t smem = SolveCfg<MC, true>::kSmem;
+    const int nch = (m + kChain - 1) / kChain;
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)tsolve32_kernel<MC, true>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)) != hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)tsolve32_kernel<MC, false>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)SolveCfg<MC, false>::kSmem)) !=
-            hipSuccess)
+    if ((e = hipFuncSetAttribute((const void *)tsolve32_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)SolveCfg<true>::kSmem)) != hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)tsolve32_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)SolveCfg<false>::kSmem)) != hipSuccess)
         return e;
-    const int limit = 1 << 26;
-    const size_t smem_b = SolveCfg<MC, false>::kSmem;
+    const int limit = 1 << 22;
     ++sync.epoch;
+    const uint32_t tag = (uint32_t)sync.epoch;
+    uint64_t *Yf = sync.pub, *Yb = sync.pub + (size_t)npad * kMaxPub;
+    const unsigned grid = (unsigned)(nb * nch);
     const int tok = prof ? prof->start(s, GBEM_K_SOLVE) : -1;
-    hipLaunchKernelGGL((tsolve32_kernel<MC, true>), dim3(nb), dim3(256), smem, s, L, lda, W, B, ldb, m, nb,
-                       sync.flags_f, sync.err + 1, sync.base_f, sync.epoch, sync.err, limit);
-    hipLaunchKernelGGL((tsolve32_kernel<MC, false>), dim3(nb), dim3(256), smem_b, s, L, lda, W, B, ldb, m, nb,
-                       sync.flags_b, sync.err + 2, sync.base_b, sync.epoch, sync.err, limit);
+    hipLaunchKernelGGL(tsolve32_kernel<true>, dim3(grid), dim3(256), SolveCfg<true>::kSmem, s, L, lda, W,
+                       (const float *)sync.sub, B, ldb, Yf, m, nb, nch, sync.err + 1, sync.base_f, tag, sync.err,
+                       limit);
+    hipLaunchKernelGGL(tsolve32_kernel<false>, dim3(grid), dim3(256), SolveCfg<false>::kSmem, s, L, lda, W,
+                       (const float *)sync.sub + npad * kNB, B, ldb, Yb, m, nb, nch, sync.err + 2, sync.base_b, tag,
+                       sync.err, limit);
     if (prof) {
         const double lbytes = (double)npad * (npad + kNB) / 2.0 * 4.0;
         prof->stop(tok, GBEM_K_SOLVE, 2.0 * 2.0 * (double)npad * npad / 2.0 * m,
-                   2.0 * lbytes + 2.0 * npad * kNB * 4.0 + 4.0 * npad * m * 8.0, s, 2);
+                   2.0 * nch * lbytes + 4.0 * nch * npad * kNB * 4.0 + 4.0 * npad * m * 8.0, s, 2);
     }
     e = hipGetLastError();
-    if (e == hipSuccess) {
-        sync.base_f += (uint32_t)nb;
-        sync.base_b += (uint32_t)nb;
+    if (e == hipSuccess) {   // each launch consumes exactly grid tickets
+        sync.base_f += grid;
+        sync.base_b += grid;
     }
     return e;
 }
@@ -547,9 +605,29 @@ hipError_t chol_solve(int dtype, int64_t npad, const void *L, int64_t lda, const
     if (dtype == GBEM_F64)
         return solve_t<double>(npad, (const double *)L, lda, (const double *)Winv, m, B, ldb, sync, s, prof);
     const float *Lf = (const float *)L, *Wf = (const float *)Winv;
-    if (m <= 16) return solve32_mc<16>(npad, Lf, lda, Wf, m, B, ldb, sync, s, prof);
-    if (m <= 32) return solve32_mc<32>(npad, Lf, lda, Wf, m, B, ldb, sync, s, prof);
-    return solve32_mc<64>(npad, Lf, lda, Wf, m, B, ldb, sync, s, prof);
+    if (sync.prep_of != L || sync.prep_npad != npad) return hipErrorInvalidValue;   // solve_prep first
+    return solve32(npad, Lf, lda, Wf, m, B, ldb, sync, s, prof);
+}
+
+hipError_t chol_solve_prep(int dtype, int64_t npad, const void *L, int64_t lda, const void *Winv,
+                           SolveSync &sync, hipStream_t s)
+{
+    if (npad % kNB) return hipErrorInvalidValue;
+    sync.prep_of = nullptr;
+    if (dtype == GBEM_F64) return hipSuccess;
+    const int nb = (int)(npad / kNB);
+    if (nb > 1) {
+        const size_t smem = (size_t)2 * kNB * kPLd * 4;
+        hipError_t e = hipFuncSetAttribute((const void *)solve_prep_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(solve_prep_kernel, dim3(nb - 1, 2), dim3(256), smem, s, (const float *)L, lda,
+                           (const float *)Winv, sync.sub, npad);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    sync.prep_of = L;
+    sync.prep_npad = npad;
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------------------
