@@ -120,8 +120,14 @@ __device__ __forceinline__ void leaf16(T *Lb, T *Wb, int32_t *info, int grow)
             T piv = rowbc(v[j], j);
             firstbad = (firstbad < 0 && !(piv > T(0))) ? j : firstbad;
             piv = (piv > T(0)) ? piv : T(1);
-            const T d = sqrt(piv);
-            rd[j] = T(1) / d;
+            T d;
+            if constexpr (sizeof(T) == 4) {   // FP32 factors are refined in FP64: hardware rsq (~1 ulp)
+                rd[j] = __builtin_amdgcn_rsqf(piv);
+                d = piv * rd[j];
+            } else {
+                d = sqrt(piv);
+                rd[j] = T(1) / d;
+            }
             const T lj = (r == j) ? d : v[j] * rd[j];   // rows above j: unused
             v[j] = lj;
 #pragma clang loop unroll(full)
@@ -130,7 +136,10 @@ __device__ __forceinline__ void leaf16(T *Lb, T *Wb, int32_t *info, int grow)
         if (firstbad >= 0 && lane == 0 && *info == 0) *info = grow + firstbad + 1;
     } else {
 #pragma clang loop unroll(full)
-        for (int j = 0; j < kLB; ++j) rd[j] = T(1) / rowbc(v[j], j);
+        for (int j = 0; j < kLB; ++j) {
+            if constexpr (sizeof(T) == 4) rd[j] = __builtin_amdgcn_rcpf(rowbc(v[j], j));
+            else rd[j] = T(1) / rowbc(v[j], j);
+        }
     }
     // W = L^{-1}: row j of W is (raw row j) / L_jj; rows below subtract
     // L_rj / L_jj times the raw row j.
