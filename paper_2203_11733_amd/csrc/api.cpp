@@ -92,10 +92,22 @@ struct DevBuf {
     template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// Small results the host reads during an extraction, in pinned memory so a
+// read is one DMA (no staging copy), gathered so that each host wait covers
+// all of them.
+struct Readback {
+    int64_t nnz;
+    int32_t bad, info, serr, pad;
+    double bn[kMaxRhs], rn[kMaxRhs];
+    double C[kMaxRhs * kMaxRhs];
+};
+
 struct Workspace {
     DevBuf lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, D, s, partial, C,
         flags, norms, sflags, rpart, semi;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t evrb = nullptr;          // readback point
+    Readback *rb = nullptr;             // pinned host memory
     bool events_ok = false;
     SolveSync sync;
     Prof prof;
@@ -156,14 +168,22 @@ struct Workspace {
             hipError_t r = hipEventCreate(&e);
             if (r != hipSuccess) return r;
         }
+        hipError_t r = hipEventCreateWithFlags(&evrb, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+        void *h = nullptr;
+        if ((r = hipHostMalloc(&h, sizeof(Readback), hipHostMallocDefault)) != hipSuccess) return r;
+        rb = static_cast<Readback *>(h);
         events_ok = true;
         return hipSuccess;
     }
     ~Workspace()
     {
         release_all();
-        if (events_ok)
+        if (events_ok) {
             for (auto &e : ev) (void)hipEventDestroy(e);
+            (void)hipEventDestroy(evrb);
+            (void)hipHostFree(rb);
+        }
         for (auto &e : fev) (void)hipEventDestroy(e);
         if (side) (void)hipStreamDestroy(side);
     }
@@ -245,9 +265,11 @@ enum class Stop { kAssembled, kFull };
 
 // The extraction pipeline on one stream and workspace.  Mesh arrays and C
 // are device pointers.
+// hC (optional): host copy of C, fetched with the final wait.
 static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, const double *dlo,
                                 const double *dhi, const int32_t *dcond, double eps_r, double lu,
-                                const gbem_opts &o, double *dC, gbem_report *rep, Stop stop)
+                                const gbem_opts &o, double *dC, gbem_report *rep, Stop stop,
+                                double *hC = nullptr)
 {
     const int64_t npad = round_up(n, kPad);
     HIPCHK(ws.init_events(), "hipEventCreate");
@@ -287,32 +309,14 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     double *bnorm = ws.norms.as<double>() + kMaxRhs;
     HIPCHK(launch_col_norms(B, npad, (int)npad, m, bnorm, st), "col_norms");
 
-    // one host sync: near-list size, validation flag, panels per conductor
-    int64_t nnz = 0;
-    int32_t bad = 0;
-    double bn[kMaxRhs];
-    HIPCHK(hipMemcpyAsync(&nnz, ws.rowptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st), "D2H nnz");
-    HIPCHK(hipMemcpyAsync(&bad, flags, 4, hipMemcpyDeviceToHost, st), "D2H flag");
-    HIPCHK(hipMemcpyAsync(bn, bnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
-    HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
-    if (bad) {
-        set_error("panel " + std::to_string(bad - 1) +
-                  " is not an axis-aligned rectangle with exactly one zero extent, or its conductor id is out of range");
-        return GBEM_EINVAL;
-    }
-    for (int k = 0; k < m; ++k)
-        if (bn[k] == 0.0) {
-            set_error("conductor " + std::to_string(k) + " has no panels");
-            return GBEM_EINVAL;
-        }
-
-    HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near rows");
-    HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
-    HIPCHK(ws.semi.ensure(near_semi_bytes(nnz)), "alloc near queue");
-    tok = pf.start(st, GBEM_K_NEAR_LIST);
-    HIPCHK(launch_near_fill(dlo, dhi, n, eta2, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
-                            ws.ncol.as<int32_t>(), st), "near_fill");
-    pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8) + (double)nnz * 8, st);
+    // one host wait: near-list size, validation flag, panels per conductor;
+    // the far field (which needs none of them) is queued first and runs
+    // while the host waits
+    Readback *rbk = ws.rb;
+    HIPCHK(hipMemcpyAsync(&rbk->nnz, ws.rowptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st), "D2H nnz");
+    HIPCHK(hipMemcpyAsync(&rbk->bad, flags, 4, hipMemcpyDeviceToHost, st), "D2H flag");
+    HIPCHK(hipMemcpyAsync(rbk->bn, bnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
+    HIPCHK(hipEventRecord(ws.evrb, st), "hipEventRecord");
     GaussRule rule;
     gauss_legendre_rule(o.far_order, &rule);
     tok = pf.start(st, GBEM_K_FAR);
@@ -324,6 +328,31 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         pf.stop(tok, GBEM_K_FAR, 11.0 * p2 * p2 * (double)n * (n + 1) / 2.0,
                 (double)npad * npad * 8.0 + (double)n * sizeof(Panel), st);
     }
+    HIPCHK(hipEventSynchronize(ws.evrb), "hipEventSynchronize");
+    const int64_t nnz = rbk->nnz;
+    const int32_t bad = rbk->bad;
+    double bn[kMaxRhs];
+    for (int k = 0; k < m; ++k) bn[k] = rbk->bn[k];
+    if (bad) {
+        HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");   // the far kernel is done with the panels
+        set_error("panel " + std::to_string(bad - 1) +
+                  " is not an axis-aligned rectangle with exactly one zero extent, or its conductor id is out of range");
+        return GBEM_EINVAL;
+    }
+    for (int k = 0; k < m; ++k)
+        if (bn[k] == 0.0) {
+            HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+            set_error("conductor " + std::to_string(k) + " has no panels");
+            return GBEM_EINVAL;
+        }
+
+    HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near rows");
+    HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
+    HIPCHK(ws.semi.ensure(near_semi_bytes(nnz)), "alloc near queue");
+    tok = pf.start(st, GBEM_K_NEAR_LIST);
+    HIPCHK(launch_near_fill(dlo, dhi, n, eta2, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
+                            ws.ncol.as<int32_t>(), st), "near_fill");
+    pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8) + (double)nnz * 8, st);
     tok = pf.start(st, GBEM_K_NEAR_EVAL);
     HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
                             A, lda, ws.semi.as<int32_t>(), st), "near_eval");
@@ -366,17 +395,10 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(ws.ensure_side(), "side stream");
         HIPCHK(chol_factor(dtype, npad, Fm, lda, ws.Winv.p, ws.Pw.p, ws.P16.p, flags + 1, st, ws.side, ws.fev, &pf),
                "cholesky");
-        int32_t info = 0;
-        HIPCHK(hipMemcpyAsync(&info, flags + 1, 4, hipMemcpyDeviceToHost, st), "D2H info");
-        HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
-        if (info != 0) {
-            if (dtype == GBEM_F64) {
-                set_error("Cholesky: non-positive pivot at row " + std::to_string(info - 1));
-                return GBEM_ENOTPD;
-            }
-            dtype = (dtype == GBEM_F32) ? GBEM_F64 : GBEM_F32;   // BF16/F16 -> F32 -> F64
-            continue;
-        }
+        // The pivot status is read with the next host wait; the solves are
+        // queued behind it regardless (on a failed factor they are discarded:
+        // their termination does not depend on the values).
+        HIPCHK(hipMemcpyAsync(&rbk->info, flags + 1, 4, hipMemcpyDeviceToHost, st), "D2H info");
         HIPCHK(chol_solve_prep(dtype, npad, Fm, lda, ws.Winv.p, ws.sync, st), "solve prep");
         HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
         HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
@@ -393,7 +415,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(ws.rpart.ensure((size_t)residual_splits((int)npad) * m * npad * 8), "alloc residual partials");
         double *R = ws.R.as<double>();
         double *rnorm = ws.norms.as<double>();
-        bool converged = false;
+        bool converged = false, retry = false;
         for (iters = 0;; ++iters) {
             tok = pf.start(st, GBEM_K_RESIDUAL);
             HIPCHK(launch_residual(A, lda, (int)npad, X, npad, B, npad, m, R, npad, ws.rpart.as<double>(), st),
@@ -401,12 +423,16 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             pf.stop(tok, GBEM_K_RESIDUAL, 2.0 * (double)npad * npad * m,
                     (double)npad * npad * 8.0 + 3.0 * (double)npad * m * 8.0, st, 2);
             HIPCHK(launch_col_norms(R, npad, (int)npad, m, rnorm, st), "col_norms");
-            double rn[kMaxRhs];
-            int32_t serr = 0;
-            HIPCHK(hipMemcpyAsync(rn, rnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
-            HIPCHK(hipMemcpyAsync(&serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
-            HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
-            if (serr) {
+            HIPCHK(hipMemcpyAsync(rbk->rn, rnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
+            HIPCHK(hipMemcpyAsync(&rbk->serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
+            HIPCHK(hipEventRecord(ws.evrb, st), "hipEventRecord");
+            HIPCHK(hipEventSynchronize(ws.evrb), "hipEventSynchronize");
+            if (iters == 0 && rbk->info != 0) {   // the low-precision factor failed
+                retry = true;
+                break;
+            }
+            const double *rn = rbk->rn;
+            if (rbk->serr) {
                 set_error("triangular solve: a block wait exceeded its poll limit");
                 return GBEM_EDEVICE;
             }
@@ -422,6 +448,10 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, R, npad, ws.sync, st, &pf), "solve");
             HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
             HIPCHK(launch_axpy_cols(X, npad, R, npad, (int)npad, m, st), "update");
+        }
+        if (retry) {
+            dtype = (dtype == GBEM_F32) ? GBEM_F64 : GBEM_F32;   // BF16/F16 -> F32 -> F64
+            continue;
         }
         if (!converged) {
             if (rep) {
@@ -440,14 +470,18 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     const double eps0 = 8.8541878128e-12;
     HIPCHK(launch_charge_finish(ws.partial.as<double>(), nchunks, m, eps_r * eps0 * lu, dC, st), "charges");
     HIPCHK(hipEventRecord(ws.ev[3], st), "hipEventRecord");
-    int32_t serr = 0;
-    HIPCHK(hipMemcpyAsync(&serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
-    HIPCHK(hipEventSynchronize(ws.ev[3]), "hipEventSynchronize");
+    HIPCHK(hipMemcpyAsync(&rbk->serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
+    if (hC) HIPCHK(hipMemcpyAsync(rbk->C, dC, sizeof(double) * m * m, hipMemcpyDeviceToHost, st), "D2H C");
     HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
-    if (serr) {
+    if (dtype == GBEM_F64 && rbk->info != 0) {
+        set_error("Cholesky: non-positive pivot at row " + std::to_string(rbk->info - 1));
+        return GBEM_ENOTPD;
+    }
+    if (rbk->serr) {
         set_error("triangular solve: a block wait exceeded its poll limit");
         return GBEM_EDEVICE;
     }
+    if (hC) memcpy(hC, rbk->C, sizeof(double) * m * m);
     if (rep) {
         float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
         (void)hipEventElapsedTime(&t01, ws.ev[0], ws.ev[1]);
@@ -560,12 +594,8 @@ static void worker_main(gbem_ctx *ctx, Worker *w)
             } else {
                 dC = w->ws.C.as<double>();
                 st = run_pipeline(w->ws, w->stream, j->n, j->m, w->ws.lo.as<double>(), w->ws.hi.as<double>(),
-                                  w->ws.cond.as<int32_t>(), j->eps_r, j->lu, j->opts, dC, &rep, Stop::kFull);
-                if (st == GBEM_OK) {
-                    e = hipMemcpyAsync(C.data(), dC, sizeof(double) * j->m * j->m, hipMemcpyDeviceToHost, w->stream);
-                    if (e == hipSuccess) e = hipStreamSynchronize(w->stream);
-                    if (e != hipSuccess) st = dev_fail(e, "serving: download");
-                }
+                                  w->ws.cond.as<int32_t>(), j->eps_r, j->lu, j->opts, dC, &rep, Stop::kFull,
+                                  C.data());
             }
         }
         if (st == GBEM_OK) rep.asym = asym_of(C.data(), j->m);
@@ -808,16 +838,14 @@ extern "C" gbem_status gbem_extract(gbem_ctx *ctx, const gbem_mesh *mesh, const 
     const int m = mesh->n_conductors;
     HIPCHK(ctx->ws.C.ensure(sizeof(double) * m * m), "alloc C");
     gbem_report r{};
+    std::vector<double> C(m * m);
     s = run_pipeline(ctx->ws, ctx->stream, mesh->n_panels, m, ctx->ws.lo.as<double>(), ctx->ws.hi.as<double>(),
                      ctx->ws.cond.as<int32_t>(), mesh->eps_r, mesh->length_unit_m, o, ctx->ws.C.as<double>(),
-                     &r, Stop::kFull);
+                     &r, Stop::kFull, C.data());
     if (s != GBEM_OK) {
         if (rep) *rep = r;
         return s;
     }
-    std::vector<double> C(m * m);
-    HIPCHK(hipMemcpyAsync(C.data(), ctx->ws.C.p, sizeof(double) * m * m, hipMemcpyDeviceToHost, ctx->stream), "D2H");
-    HIPCHK(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     memcpy(C_out, C.data(), sizeof(double) * m * m);
     r.asym = asym_of(C.data(), m);
     if (rep) *rep = r;
@@ -838,15 +866,11 @@ extern "C" gbem_status gbem_extract_device(gbem_ctx *ctx, const gbem_mesh *mesh,
     HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
     gbem_report r{};
-    s = run_pipeline(ctx->ws, st, mesh->n_panels, mesh->n_conductors, mesh->lo, mesh->hi, mesh->conductor,
-                     mesh->eps_r, mesh->length_unit_m, o, C_out_device, &r, Stop::kFull);
-    if (s == GBEM_OK && rep) {
-        const int m = mesh->n_conductors;
-        std::vector<double> C(m * m);
-        HIPCHK(hipMemcpyAsync(C.data(), C_out_device, sizeof(double) * m * m, hipMemcpyDeviceToHost, st), "D2H");
-        HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
-        r.asym = asym_of(C.data(), m);
-    }
+    const int m = mesh->n_conductors;
+    std::vector<double> C(rep ? m * m : 0);   // host copy only for the report's asymmetry
+    s = run_pipeline(ctx->ws, st, mesh->n_panels, m, mesh->lo, mesh->hi, mesh->conductor, mesh->eps_r,
+                     mesh->length_unit_m, o, C_out_device, &r, Stop::kFull, rep ? C.data() : nullptr);
+    if (s == GBEM_OK && rep) r.asym = asym_of(C.data(), m);
     if (rep) *rep = r;
     return s;
 }

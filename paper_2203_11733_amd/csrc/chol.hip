@@ -892,7 +892,7 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     if (e != hipSuccess) return e;
     while ((int)ev.size() < 2 * nbo + 2) {   // evP[0..nbo), evB[0..nbo]
         hipEvent_t x;
-        if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming | hipEventDisableSystemFence)) != hipSuccess) return e;
         ev.push_back(x);
     }
     const bool b16 = dtype == GBEM_F16 || dtype == GBEM_BF16;
