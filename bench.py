@@ -107,7 +107,7 @@ def log(msg):
 def layout_of(name):
     import gbem_inputs as gi
     return {"crossing_bus": gi.crossing_bus, "three_layer_bus": gi.three_layer_bus,
-            "two_plates": gi.two_plates}[name]()
+            "two_plates": gi.two_plates, "crossing_bars_in_box": gi.crossing_bars_in_box}[name]()
 
 
 def cpu_baseline(lo, hi, cond, layout, p, eta):
@@ -264,6 +264,60 @@ def sweep(args, binding, np):
             "reference": "FP64 path, p=8, eta=4", "rows": rows}
 
 
+PARTITION_SETS = {
+    # section 3.3 rule (p1, p2, p3, p5); lengths in the layout's unit (um)
+    "crossing_bars_in_box": [(1.0, 4.0, 1.0, 1.0), (0.5, 4.0, 0.25, 2.0), (0.1, 4.0, 1.0, 1.0)],
+    "crossing_bus": [(0.01, 4.0, 1.0, 0.2), (0.005, 4.0, 1.0, 0.2), (0.0025, 4.0, 1.0, 0.2), (0.001, 4.0, 1.0, 0.2)],
+}
+
+
+def partitioned(args, binding, np):
+    """Per-main-net meshes (section 3.3 partition rule, one mesh and one column
+    of C per conductor) against the layout's own mesh in FP64, and for the
+    paper's bars in a box against section 5, Table 2."""
+    import torch
+    lay = layout_of(args.layout)
+    blo, bhi, bc = lay.arrays()
+    m = lay.n_conductors
+    ctx = binding.Context(0)
+    lo, hi, cond = binding.mesh_layout(lay)
+    C_ref, rep_ref = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, binding.make_opts(args.p, args.eta))
+    t0 = time.perf_counter()
+    for _ in range(2):
+        ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, binding.make_opts(args.p, args.eta))
+    ref_ms = (time.perf_counter() - t0) / 2 * 1e3
+    log(f"partition: {lay.name} own mesh N={lo.shape[0]} FP64 {ref_ms:.1f} ms")
+    rows = []
+    for prm in PARTITION_SETS.get(lay.name, PARTITION_SETS["crossing_bus"]):
+        for mode in ("f64", "mixed"):
+            o = binding.make_opts(args.p, args.eta, **MODES[mode])
+            C, panels, rep = ctx.extract_partitioned(blo, bhi, bc, m, lay.eps_r, lay.length_unit_m, *prm, opts=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = max(1, args.steps)
+            for _ in range(reps):
+                C, panels, rep = ctx.extract_partitioned(blo, bhi, bc, m, lay.eps_r, lay.length_unit_m, *prm, opts=o)
+            ms = (time.perf_counter() - t0) / reps * 1e3
+            row = {"p1_p2_p3_p5": list(prm), "mode": mode, "panels_per_mesh": panels.tolist(),
+                   "panels_total": int(panels.sum()), "ms_per_extraction": ms,
+                   "C_rel_err_vs_own_mesh_f64": float(np.abs(C - C_ref).max() / np.abs(C_ref).max()),
+                   "asym": rep["asym"]}
+            if lay.name == "crossing_bars_in_box":
+                row["C_aF"] = np.round(C * 1e18, 2).tolist()
+            rows.append(row)
+            log(f"partition: {row}")
+    out = {"metric": "partitioned extraction (per-main-net meshes)", "unit": "ms per extraction",
+           "config": {"workload": f"{lay.name}: own mesh N={lo.shape[0]}, M={m}"},
+           "own_mesh_f64_ms": ref_ms, "own_mesh_C": (np.round(C_ref * 1e18, 2).tolist()
+                                                    if lay.name == "crossing_bars_in_box" else None),
+           "rows": rows}
+    if lay.name == "crossing_bars_in_box":
+        out["paper_table2_aF"] = {"74 panels": [222, -58.6, -58.6, 178], "183 panels": [225, -58.3, -58.3, 179],
+                                  "594 panels": [226, -58.7, -58.7, 179], "comparator": [230, -61, -61, 180.6]}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +335,9 @@ def main():
                     help="time without the library's per-launch HIP events (no roofline)")
     ap.add_argument("--sweep", action="store_true",
                     help="precision sweep p x eta x factor dtype on --layout (default three_layer_bus)")
+    ap.add_argument("--partition", action="store_true",
+                    help="per-main-net meshes by the section 3.3 rule on --layout (crossing_bus or "
+                         "crossing_bars_in_box) against the layout's own mesh")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference for HBM byte counters)")
     args = ap.parse_args()
@@ -295,6 +352,9 @@ def main():
 
     if args.serving:
         print(json.dumps(serving(args, binding, np)))
+        return
+    if args.partition:
+        print(json.dumps(partitioned(args, binding, np)))
         return
     if args.sweep:
         if args.layout == "crossing_bus":

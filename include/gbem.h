@@ -180,8 +180,57 @@ typedef struct {
 } gbem_mesh_buf;
 gbem_status gbem_mesh_boxes(const double *box_lo, const double *box_hi, const int32_t *box_cond,
                             int32_t n_boxes, const gbem_mesh_rule *rule, gbem_mesh_buf *out);
-/* Free the arrays of a gbem_mesh_buf filled by gbem_mesh_boxes. */
+/* Free the arrays of a gbem_mesh_buf filled by gbem_mesh_boxes or
+ * gbem_mesh_partition. */
 void gbem_mesh_buf_free(gbem_mesh_buf *buf);
+
+/* Partition rule of section 3.3 (error estimate of Proposition 2: element
+ * area times the field derivative, the derivative taken as falling with the
+ * cube of the distance to the main net, eq. "electric_derivative").  For one
+ * main net, every box face is split into rectangles I with
+ *   |I| <= p4                       where the distance d(I, main net) <= p5,
+ *   |I| <= p4 * p3 * (d / p5)^3     beyond,
+ * p4 = p1 on faces that face the main net and p1 * p2 on faces turned away
+ * from it (field shielding, p2 usually > 1).  Readings where the paper is
+ * silent: d is the Euclidean distance from I to the nearest box of the main
+ * net; the faces of the main net and of any box enclosing it face it, any
+ * other face faces it when some box of the main net reaches beyond the face's
+ * plane on its outer side; a rectangle over its bound is halved across its
+ * longer side (lower in-plane axis on a tie) at lo + (hi - lo) * 0.5, depth
+ * first, lower half first, all in plain FP64.  Output order: boxes as given,
+ * faces -x, +x, -y, +y, -z, +z.  Boxes with conductor -1 (a grounded
+ * enclosure) are meshed like conductors. */
+typedef struct {
+    double p1;   /* area bound (length unit^2) near the main net, facing side */
+    double p2;   /* >= 1: factor of p1 on faces turned away from the main net */
+    double p3;   /* > 0: factor of the far bound */
+    double p5;   /* > 0: distance (length unit) where the far bound starts */
+} gbem_partition;
+/* Mesh for main net main_net (a conductor id of box_cond); arrays as for
+ * gbem_mesh_boxes (library-allocated, free with gbem_mesh_buf_free).
+ * GBEM_EINVAL: invalid rule, no box on main_net, intersecting boxes, or a
+ * rule that asks for more than 2^29 panels or pieces below 1e-12 of a face. */
+gbem_status gbem_mesh_partition(const double *box_lo, const double *box_hi, const int32_t *box_cond,
+                                int32_t n_boxes, int32_t main_net, const gbem_partition *rule,
+                                gbem_mesh_buf *out);
+/* The paper's extraction with per-main-net meshes (section 3.2: the main net
+ * at potential 1, all other boundaries at 0, C_1 = Q_1 and C_n = Q_n): for
+ * each conductor k = 0 .. n_conductors-1, mesh with gbem_mesh_partition(k),
+ * extract, and keep column k of that extraction's Maxwell matrix (the charges
+ * on every net with net k at potential 1).  The n_conductors extractions are
+ * independent and run through the serving loop (several at once on their own
+ * streams, queued behind jobs already submitted); the same HBM budget
+ * applies.  C_out: host, n_conductors^2,
+ * row-major, C_out[n * n_conductors + k] = charge on net n per volt on net k.
+ * panels_out (optional, host, n_conductors): panel count of mesh k.  rep
+ * (optional): GPU times and panel counts summed over the meshes, largest
+ * residual and refinement count, asym of the assembled C (it measures how
+ * much the per-net meshes disagree). */
+gbem_status gbem_extract_partitioned(gbem_ctx *ctx, const double *box_lo, const double *box_hi,
+                                     const int32_t *box_cond, int32_t n_boxes, int32_t n_conductors,
+                                     double eps_r, double length_unit_m, const gbem_partition *rule,
+                                     const gbem_opts *opts, double *C_out, int32_t *panels_out,
+                                     gbem_report *rep);
 
 /* ---- stage entry points (same kernels as gbem_extract; for parity tests) ---- */
 

@@ -26,6 +26,7 @@ EXPORTS = [
     "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit", "gbem_poll", "gbem_wait",
     "gbem_job_free", "gbem_server_stats", "gbem_mesh_boxes", "gbem_mesh_buf_free", "gbem_near_list",
     "gbem_assemble", "gbem_assemble_sample", "gbem_cholesky_device", "gbem_cholesky_solve_device",
+    "gbem_mesh_partition", "gbem_extract_partitioned",
 ]
 
 
@@ -75,6 +76,12 @@ class MeshRule(ctypes.Structure):
                 ("growth", ctypes.c_double), ("h_max", ctypes.c_double)]
 
 
+class Partition(ctypes.Structure):
+    """Partition rule of section 3.3 (gbem_partition)."""
+    _fields_ = [("p1", ctypes.c_double), ("p2", ctypes.c_double), ("p3", ctypes.c_double),
+                ("p5", ctypes.c_double)]
+
+
 class MeshBuf(ctypes.Structure):
     _fields_ = [("n_panels", ctypes.c_int32), ("lo", ctypes.POINTER(ctypes.c_double)),
                 ("hi", ctypes.POINTER(ctypes.c_double)), ("conductor", ctypes.POINTER(ctypes.c_int32))]
@@ -110,6 +117,11 @@ def load():
     lib.gbem_server_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]
     lib.gbem_mesh_boxes.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(MeshRule),
                                     ctypes.POINTER(MeshBuf)]
+    lib.gbem_mesh_partition.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Partition),
+                                        ctypes.POINTER(MeshBuf)]
+    lib.gbem_extract_partitioned.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double, ctypes.POINTER(Partition), ctypes.POINTER(Opts),
+                                             _vp, _vp, ctypes.POINTER(Report)]
     lib.gbem_mesh_buf_free.argtypes = [ctypes.POINTER(MeshBuf)]
     lib.gbem_mesh_buf_free.restype = None
     lib.gbem_near_list.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.c_double, _vp, _vp, ctypes.c_int64,
@@ -124,7 +136,7 @@ def load():
     for name in ("gbem_create", "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit",
                  "gbem_poll", "gbem_wait", "gbem_server_stats", "gbem_mesh_boxes", "gbem_near_list",
                  "gbem_assemble", "gbem_assemble_sample", "gbem_cholesky_device",
-                 "gbem_cholesky_solve_device"):
+                 "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -184,6 +196,30 @@ def mesh_layout(layout):
     return mesh_boxes(blo, bhi, bcond, layout.rule)
 
 
+def _take_buf(lib, buf):
+    try:
+        n = buf.n_panels
+        lo = np.ctypeslib.as_array(buf.lo, shape=(n * 3,)).reshape(n, 3).copy()
+        hi = np.ctypeslib.as_array(buf.hi, shape=(n * 3,)).reshape(n, 3).copy()
+        cond = np.ctypeslib.as_array(buf.conductor, shape=(n,)).copy()
+    finally:
+        lib.gbem_mesh_buf_free(ctypes.byref(buf))
+    return lo, hi, cond
+
+
+def mesh_partition(box_lo, box_hi, box_cond, main_net, p1, p2, p3, p5):
+    """Library mesher, partition rule of section 3.3 for one main net: (lo, hi, cond)."""
+    lib = load()
+    blo = np.ascontiguousarray(box_lo, dtype=np.float64).reshape(-1, 3)
+    bhi = np.ascontiguousarray(box_hi, dtype=np.float64).reshape(-1, 3)
+    bc = np.ascontiguousarray(box_cond, dtype=np.int32).reshape(-1)
+    r = Partition(p1, p2, p3, p5)
+    buf = MeshBuf()
+    _check(lib.gbem_mesh_partition(_ptr(blo), _ptr(bhi), _ptr(bc), blo.shape[0], main_net, ctypes.byref(r),
+                                   ctypes.byref(buf)))
+    return _take_buf(lib, buf)
+
+
 class Context:
     """A device context: synchronous extraction, serving loop and stage calls."""
 
@@ -225,6 +261,23 @@ class Context:
         o = opts or make_opts()
         _check(self.lib.gbem_extract(self.h, ctypes.byref(m), ctypes.byref(o), _ptr(C), ctypes.byref(rep)))
         return C, rep.as_dict()
+
+    def extract_partitioned(self, box_lo, box_hi, box_cond, n_conductors, eps_r, length_unit_m,
+                            p1, p2, p3, p5, opts: Opts | None = None):
+        """Per-main-net meshes (section 3.3 rule), column k of C from mesh k.
+        Returns (C, panels per mesh, report)."""
+        blo = np.ascontiguousarray(box_lo, dtype=np.float64).reshape(-1, 3)
+        bhi = np.ascontiguousarray(box_hi, dtype=np.float64).reshape(-1, 3)
+        bc = np.ascontiguousarray(box_cond, dtype=np.int32).reshape(-1)
+        C = np.zeros((n_conductors, n_conductors))
+        panels = np.zeros(n_conductors, dtype=np.int32)
+        rep = Report()
+        o = opts or make_opts()
+        r = Partition(p1, p2, p3, p5)
+        _check(self.lib.gbem_extract_partitioned(self.h, _ptr(blo), _ptr(bhi), _ptr(bc), blo.shape[0], n_conductors,
+                                                 eps_r, length_unit_m, ctypes.byref(r), ctypes.byref(o), _ptr(C),
+                                                 _ptr(panels), ctypes.byref(rep)))
+        return C, panels, rep.as_dict()
 
     def extract_layout(self, layout, opts: Opts | None = None):
         lo, hi, cond = mesh_layout(layout)

@@ -1135,3 +1135,83 @@ extern "C" gbem_status gbem_cholesky_solve_device(gbem_ctx *ctx, int32_t n, int3
 {
     return chol_common(ctx, n, dtype, const_cast<void *>(L), lda, nullptr, stream, nrhs, B, ldb, true);
 }
+
+extern "C" gbem_status gbem_extract_partitioned(gbem_ctx *ctx, const double *box_lo, const double *box_hi,
+                                                const int32_t *box_cond, int32_t n_boxes, int32_t n_conductors,
+                                                double eps_r, double length_unit_m, const gbem_partition *rule,
+                                                const gbem_opts *opts, double *C_out, int32_t *panels_out,
+                                                gbem_report *rep)
+{
+    if (!ctx || !box_lo || !box_hi || !box_cond || !rule || !C_out || n_boxes <= 0) {
+        set_error("gbem_extract_partitioned: null argument or no boxes");
+        return GBEM_EINVAL;
+    }
+    if (n_conductors <= 0 || n_conductors > kMaxRhs) {
+        set_error("gbem_extract_partitioned: n_conductors must be 1.." + std::to_string(kMaxRhs));
+        return GBEM_EINVAL;
+    }
+    const int m = n_conductors;
+    std::vector<double> C(m * m), Ck(m * m);
+    gbem_report tot{};
+    // the meshes are independent: they go through the serving loop, which
+    // runs up to kWorkers of them at once on streams of their own
+    std::vector<gbem_job *> jobs(m, nullptr);
+    auto drop = [&](int upto) {
+        for (int k = 0; k < upto; ++k)
+            if (jobs[k]) gbem_job_free(jobs[k]);
+    };
+    for (int k = 0; k < m; ++k) {
+        gbem_mesh_buf buf{};
+        gbem_status s = gbem_mesh_partition(box_lo, box_hi, box_cond, n_boxes, k, rule, &buf);
+        if (s != GBEM_OK) {
+            drop(k);
+            return s;
+        }
+        const gbem_mesh mesh{buf.n_panels, m, buf.lo, buf.hi, buf.conductor, eps_r, length_unit_m};
+        if (panels_out) panels_out[k] = mesh.n_panels;
+        s = gbem_submit(ctx, &mesh, opts, &jobs[k]);   // copies the mesh
+        gbem_mesh_buf_free(&buf);
+        if (s != GBEM_OK) {
+            drop(k);
+            return s;
+        }
+    }
+    gbem_status first_err = GBEM_OK;
+    std::string err_msg;
+    for (int k = 0; k < m; ++k) {
+        gbem_report r{};
+        const gbem_status s = gbem_wait(jobs[k], -1.0, Ck.data(), &r);
+        if (s != GBEM_OK) {
+            if (first_err == GBEM_OK) {
+                first_err = s;
+                err_msg = gbem_last_error();
+            }
+            continue;
+        }
+        for (int n = 0; n < m; ++n) C[n * m + k] = Ck[n * m + k];   // column k: charges with net k at 1 V
+        tot.t_assemble_ms += r.t_assemble_ms;
+        tot.t_factor_ms += r.t_factor_ms;
+        tot.t_solve_ms += r.t_solve_ms;
+        tot.t_total_ms += r.t_total_ms;
+        tot.residual = std::max(tot.residual, r.residual);
+        tot.refine_iters = std::max(tot.refine_iters, r.refine_iters);
+        tot.factor_used = r.factor_used;
+        tot.n_near += r.n_near;
+        tot.n_panels += r.n_panels;
+        for (int c = 0; c < GBEM_K_COUNT; ++c) {
+            tot.prof_ms[c] += r.prof_ms[c];
+            tot.prof_launches[c] += r.prof_launches[c];
+            tot.prof_flops[c] += r.prof_flops[c];
+            tot.prof_bytes[c] += r.prof_bytes[c];
+        }
+    }
+    drop(m);
+    if (first_err != GBEM_OK) {
+        set_error("gbem_extract_partitioned: " + err_msg);
+        return first_err;
+    }
+    memcpy(C_out, C.data(), sizeof(double) * m * m);
+    tot.asym = asym_of(C.data(), m);
+    if (rep) *rep = tot;
+    return GBEM_OK;
+}

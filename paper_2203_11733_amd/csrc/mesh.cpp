@@ -10,6 +10,22 @@
 // Order: boxes as given; faces -x, +x, -y, +y, -z, +z; within a face the lower
 // in-plane axis is the outer loop.  All arithmetic is plain FP64 without
 // contraction (this file is compiled with -ffp-contract=off).
+//
+// Partition rule of section 3.3 (gbem_mesh_partition), for one main net k:
+// every face is split into rectangles I with |I| <= p4 where the distance d
+// from I to the main net is <= p5, and |I| <= p4 p3 (d/p5)^3 beyond; p4 = p1
+// on faces that face the main net and p1 p2 on faces turned away from it.
+// Readings (the paper fixes only the bounds):
+//   d      Euclidean distance between I and the nearest box of net k:
+//          d^2 = min over those boxes of gx*gx + gy*gy + gz*gz, g the gap
+//          per axis (0 where the extents overlap), d = sqrt(d^2);
+//   bound  d <= p5: p4; else r = d / p5, p4 * p3 * (r * r * r);
+//   facing the faces of net k itself and the faces of a box that contains
+//          net k face it; any other face faces it when some box of net k
+//          reaches beyond the face's plane on its outer side;
+//   split  a rectangle whose area (h1 - l1) * (h2 - l2) exceeds its bound is
+//          halved across its longer side (the lower in-plane axis on a tie)
+//          at lo + (hi - lo) * 0.5; depth first, lower half first.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -86,6 +102,76 @@ static bool boxes_ok(const double *blo, const double *bhi, int nb, std::string &
                 return false;
             }
         }
+    return true;
+}
+
+// Partition of one face (in-plane axes t1 < t2, normal axis nrm at plane)
+// by bisection; appends to lo/hi/cond.  false when the rule asks for more
+// than max_total panels or for pieces below 1e-12 of the face.
+struct NetBoxes {
+    std::vector<double> lo, hi;   // 3 per box of the main net
+};
+static double net_dist2(const NetBoxes &net, const double *l, const double *h)
+{
+    double best = INFINITY;
+    for (size_t b = 0; b < net.lo.size() / 3; ++b) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double g = 0.0;
+            if (net.lo[3 * b + k] > h[k]) g = net.lo[3 * b + k] - h[k];
+            else if (l[k] > net.hi[3 * b + k]) g = l[k] - net.hi[3 * b + k];
+            d2 = d2 + g * g;
+        }
+        if (d2 < best) best = d2;
+    }
+    return best;
+}
+static bool partition_face(const NetBoxes &net, double p4, const gbem_partition &r, int nrm, double plane,
+                           double a0, double a1, double b0, double b1, int32_t c, std::vector<double> &lo,
+                           std::vector<double> &hi, std::vector<int32_t> &cond, size_t max_total)
+{
+    const int t1 = nrm == 0 ? 1 : 0, t2 = nrm == 2 ? 1 : 2;
+    const double min1 = (a1 - a0) * 1e-12, min2 = (b1 - b0) * 1e-12;
+    struct Rect { double a0, a1, b0, b1; };
+    std::vector<Rect> stack{{a0, a1, b0, b1}};
+    while (!stack.empty()) {
+        const Rect q = stack.back();
+        stack.pop_back();
+        double l[3], h[3];
+        l[nrm] = plane;
+        h[nrm] = plane;
+        l[t1] = q.a0;
+        h[t1] = q.a1;
+        l[t2] = q.b0;
+        h[t2] = q.b1;
+        const double d = sqrt(net_dist2(net, l, h));
+        double bound = p4;
+        if (d > r.p5) {
+            const double x = d / r.p5;
+            bound = p4 * r.p3 * (x * x * x);
+        }
+        const double w1 = q.a1 - q.a0, w2 = q.b1 - q.b0;
+        if (w1 * w2 <= bound) {
+            if (cond.size() >= max_total) return false;
+            for (int k = 0; k < 3; ++k) {
+                lo.push_back(l[k]);
+                hi.push_back(h[k]);
+            }
+            cond.push_back(c);
+            continue;
+        }
+        if (w1 < min1 || w2 < min2) return false;
+        // halves pushed upper first, so the lower half is emitted first
+        if (w1 >= w2) {
+            const double m = q.a0 + (q.a1 - q.a0) * 0.5;
+            stack.push_back({m, q.a1, q.b0, q.b1});
+            stack.push_back({q.a0, m, q.b0, q.b1});
+        } else {
+            const double m = q.b0 + (q.b1 - q.b0) * 0.5;
+            stack.push_back({q.a0, q.a1, m, q.b1});
+            stack.push_back({q.a0, q.a1, q.b0, m});
+        }
+    }
     return true;
 }
 
@@ -177,4 +263,83 @@ extern "C" void gbem_mesh_buf_free(gbem_mesh_buf *buf)
     buf->lo = buf->hi = nullptr;
     buf->conductor = nullptr;
     buf->n_panels = 0;
+}
+
+extern "C" gbem_status gbem_mesh_partition(const double *box_lo, const double *box_hi,
+                                           const int32_t *box_cond, int32_t n_boxes, int32_t main_net,
+                                           const gbem_partition *rule, gbem_mesh_buf *out)
+{
+    if (!box_lo || !box_hi || !box_cond || !rule || !out || n_boxes <= 0) {
+        set_error("gbem_mesh_partition: null argument or no boxes");
+        return GBEM_EINVAL;
+    }
+    if (!(rule->p1 > 0.0) || !(rule->p2 >= 1.0) || !(rule->p3 > 0.0) || !(rule->p5 > 0.0) ||
+        !isfinite(rule->p1) || !isfinite(rule->p2) || !isfinite(rule->p3) || !isfinite(rule->p5)) {
+        set_error("gbem_mesh_partition: need p1 > 0, p2 >= 1, p3 > 0, p5 > 0 (finite)");
+        return GBEM_EINVAL;
+    }
+    std::string why;
+    if (!boxes_ok(box_lo, box_hi, n_boxes, why)) {
+        set_error("gbem_mesh_partition: " + why);
+        return GBEM_EINVAL;
+    }
+    NetBoxes net;
+    double nlo[3] = {INFINITY, INFINITY, INFINITY}, nhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < n_boxes; ++b)
+        if (box_cond[b] == main_net)
+            for (int k = 0; k < 3; ++k) {
+                net.lo.push_back(box_lo[3 * b + k]);
+                net.hi.push_back(box_hi[3 * b + k]);
+                nlo[k] = fmin(nlo[k], box_lo[3 * b + k]);
+                nhi[k] = fmax(nhi[k], box_hi[3 * b + k]);
+            }
+    if (net.lo.empty()) {
+        set_error("gbem_mesh_partition: no box belongs to the main net");
+        return GBEM_EINVAL;
+    }
+    const size_t max_total = (size_t)INT32_MAX / 4;
+    std::vector<double> lo, hi;
+    std::vector<int32_t> cond;
+    for (int b = 0; b < n_boxes; ++b) {
+        const double *bl = box_lo + 3 * b, *bh = box_hi + 3 * b;
+        bool contains = true;   // box b strictly contains the main net's bounding box
+        for (int k = 0; k < 3; ++k)
+            if (!(bl[k] < nlo[k] && nhi[k] < bh[k])) contains = false;
+        for (int f = 0; f < 6; ++f) {
+            const int nrm = f / 2;
+            const bool upper = f & 1;
+            const double plane = upper ? bh[nrm] : bl[nrm];
+            bool facing = box_cond[b] == main_net || contains;
+            if (!facing) {
+                for (size_t q = 0; q < net.lo.size() / 3 && !facing; ++q)
+                    facing = upper ? net.hi[3 * q + nrm] > plane : net.lo[3 * q + nrm] < plane;
+            }
+            const double p4 = facing ? rule->p1 : rule->p1 * rule->p2;
+            const int t1 = nrm == 0 ? 1 : 0, t2 = nrm == 2 ? 1 : 2;
+            if (!partition_face(net, p4, *rule, nrm, plane, bl[t1], bh[t1], bl[t2], bh[t2], box_cond[b], lo, hi,
+                                cond, max_total)) {
+                set_error("gbem_mesh_partition: the rule asks for too many or too small panels");
+                return GBEM_EINVAL;
+            }
+        }
+    }
+    const size_t n = cond.size();
+    double *plo = (double *)malloc(sizeof(double) * 3 * n);
+    double *phi = (double *)malloc(sizeof(double) * 3 * n);
+    int32_t *pc = (int32_t *)malloc(sizeof(int32_t) * n);
+    if (!plo || !phi || !pc) {
+        free(plo);
+        free(phi);
+        free(pc);
+        set_error("gbem_mesh_partition: host allocation failed");
+        return GBEM_ENOMEM;
+    }
+    memcpy(plo, lo.data(), sizeof(double) * 3 * n);
+    memcpy(phi, hi.data(), sizeof(double) * 3 * n);
+    memcpy(pc, cond.data(), sizeof(int32_t) * n);
+    out->n_panels = (int32_t)n;
+    out->lo = plo;
+    out->hi = phi;
+    out->conductor = pc;
+    return GBEM_OK;
 }

@@ -1,0 +1,250 @@
+"""Partition rule of section 3.3 and the per-main-net extraction.
+
+CPU part: the oracle's partition mesher against closed forms (bisection
+counts on a lone cube, facing vs turned-away faces), against the properties
+the rule fixes (each face tiled exactly, every piece within its area bound,
+no piece split needlessly), and against the paper's section 5 numbers
+(Table 2); then the library mesher bit for bit against the oracle's.
+GPU part (marked gpu): the per-main-net extraction through the C ABI against
+the oracle, FP64 1e-10 relative, mixed 1e-3.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gbem_inputs as gi
+from oracle import partition as op
+from paper_2203_11733_amd import binding
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+BARS = gi.crossing_bars_in_box()
+PARAMS = [(1.0, 4.0, 1.0, 1.0), (0.5, 4.0, 0.25, 2.0), (0.25, 2.0, 1.0, 1.0)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _face_key(lo, hi, blo, bhi):
+    """(box, face) a panel lies on: the first box face containing it."""
+    nrm = int(np.nonzero(lo == hi)[0][0])
+    for b in range(blo.shape[0]):
+        for upper in (0, 1):
+            plane = bhi[b][nrm] if upper else blo[b][nrm]
+            if lo[nrm] != plane:
+                continue
+            t = [k for k in range(3) if k != nrm]
+            if all(blo[b][k] <= lo[k] and hi[k] <= bhi[b][k] for k in t):
+                return b, 2 * nrm + upper
+    raise AssertionError("panel on no box face")
+
+
+def _area(lo, hi):
+    d = hi - lo
+    d = d[d > 0]
+    return float(d[0] * d[1])
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("p1,per_face", [(0.1, 16), (0.3, 4), (1.0, 1), (0.5, 2), (0.06, 32)])
+def test_lone_cube_bisection_count(p1, per_face):
+    """Only the main net: every face has d = 0 and bound p1, so a unit face is
+    halved k times with k the least integer with 2^-k <= p1 (alternating
+    axes: squares, or 1:2 strips when k is odd)."""
+    lo, hi, c = op.mesh_partition([[0, 0, 0]], [[1, 1, 1]], [0], 0, p1, 4.0, 1.0, 1.0)
+    k = math.ceil(math.log2(1.0 / p1) - 1e-12)
+    assert per_face == 2 ** k
+    assert lo.shape[0] == 6 * per_face
+    areas = np.array([_area(a, b) for a, b in zip(lo, hi)])
+    assert np.all(areas == 2.0 ** -k)
+
+
+def test_turned_away_faces_are_coarser():
+    """Net 0 = unit cube at the origin, box 1 = unit cube at x in [3, 4]; p5
+    large, so every bound is p4.  Box 1's -x face faces the net (p4 = p1,
+    16 pieces at p1 = 0.1); its +x face and its four side faces do not (no
+    part of the net lies beyond those planes): p4 = 4 p1 = 0.4, 4 pieces."""
+    lo, hi, c = op.mesh_partition([[0, 0, 0], [3, 0, 0]], [[1, 1, 1], [4, 1, 1]], [0, 1], 0, 0.1, 4.0, 1.0, 100.0)
+    per = [0] * 6
+    for a, b, cc in zip(lo, hi, c):
+        if cc == 1:
+            nrm = int(np.nonzero(a == b)[0][0])
+            per[2 * nrm + (1 if a[nrm] == 4.0 or (nrm > 0 and a[nrm] == 1.0) else 0)] += 1
+    assert per == [16, 4, 4, 4, 4, 4]
+    assert int((c == 0).sum()) == 96
+    # an enclosure faces the net on every face
+    lo, hi, c = op.mesh_partition([[0, 0, 0], [-2, -2, -2]], [[1, 1, 1], [3, 3, 3]], [0, -1], 0, 1.0, 4.0, 1.0,
+                                  100.0)
+    assert int((c == -1).sum()) == 6 * 32   # 25 = face area / p1 -> 2^5 pieces per face
+
+
+def test_far_bound_grows_with_cube_of_distance():
+    """d > p5: bound p4 p3 (d/p5)^3 (eq. electric_derivative)."""
+    net = [((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))]
+    # rectangle at distance 3 along x from the net, p5 = 1.5, p3 = 0.5, p4 = 0.2
+    b = op.area_bound(net, [4.0, 0.0, 0.0], [4.0, 1.0, 1.0], 0.2, 0.5, 1.5)
+    assert b == 0.2 * 0.5 * 8.0
+    assert op.area_bound(net, [2.0, 0.0, 0.0], [2.0, 1.0, 1.0], 0.2, 0.5, 1.5) == 0.2   # d = 1 <= p5
+    # distance to the nearest of several boxes; corner gaps combine as a Euclidean norm
+    net2 = net + [((10.0, 0.0, 0.0), (11.0, 1.0, 1.0))]
+    b2 = op.area_bound(net2, [4.0, 4.0, 0.0], [4.0, 5.0, 1.0], 1.0, 1.0, 1.0)
+    assert b2 == pytest.approx(math.sqrt(9.0 + 9.0) ** 3, rel=1e-15)
+
+
+# ---------------------------------------------------------------- properties
+@pytest.mark.parametrize("prm", PARAMS)
+@pytest.mark.parametrize("layout", [BARS, gi.random_small_layout(4)], ids=["bars_in_box", "random4"])
+def test_partition_tiles_faces_within_bounds(layout, prm):
+    blo, bhi, bc = layout.arrays()
+    for k in range(layout.n_conductors):
+        lo, hi, c = op.mesh_partition(blo, bhi, bc, k, *prm)
+        net = [(tuple(blo[b]), tuple(bhi[b])) for b in range(blo.shape[0]) if bc[b] == k]
+        faces = {}
+        for i in range(lo.shape[0]):
+            faces.setdefault(_face_key(lo[i], hi[i], blo, bhi), []).append(i)
+        assert len(faces) == 6 * blo.shape[0]
+        for (b, f), idx in faces.items():
+            nrm, upper = f // 2, f & 1
+            t = [q for q in range(3) if q != nrm]
+            face_area = (bhi[b][t[0]] - blo[b][t[0]]) * (bhi[b][t[1]] - blo[b][t[1]])
+            areas = [_area(lo[i], hi[i]) for i in idx]
+            assert math.fsum(areas) == pytest.approx(face_area, rel=1e-13)
+            # pairwise disjoint interiors
+            L = lo[idx][:, t]
+            H = hi[idx][:, t]
+            ov = (np.minimum(H[:, None, :], H[None, :, :]) - np.maximum(L[:, None, :], L[None, :, :])).clip(0)
+            inter = ov[..., 0] * ov[..., 1]
+            np.fill_diagonal(inter, 0.0)
+            assert inter.max() == 0.0
+            facing = op.faces_main_net(blo[b], bhi[b], bc[b] == k, net, nrm, bool(upper))
+            p4 = prm[0] if facing else prm[0] * prm[1]
+            for i in idx:
+                a = _area(lo[i], hi[i])
+                assert a <= op.area_bound(net, lo[i], hi[i], p4, prm[2], prm[3])
+                if len(idx) == 1:
+                    continue
+                # not split needlessly: the piece's parent is the piece doubled
+                # across the axis it was halved on (the parent's longer side, the
+                # lower axis on a tie), on one side or the other, inside the face;
+                # one such candidate must break its bound
+                broke = False
+                for s_ax in (0, 1):
+                    o_ax = 1 - s_ax
+                    ws = hi[i][t[s_ax]] - lo[i][t[s_ax]]
+                    wo = hi[i][t[o_ax]] - lo[i][t[o_ax]]
+                    longer = 2 * ws >= wo if s_ax == 0 else 2 * ws > wo
+                    if not longer:
+                        continue
+                    for side in (-1, 1):
+                        pl, ph = lo[i].copy(), hi[i].copy()
+                        if side < 0:
+                            pl[t[s_ax]] -= ws
+                        else:
+                            ph[t[s_ax]] += ws
+                        tol = 1e-12 * (bhi[b][t[s_ax]] - blo[b][t[s_ax]])
+                        if pl[t[s_ax]] < blo[b][t[s_ax]] - tol or ph[t[s_ax]] > bhi[b][t[s_ax]] + tol:
+                            continue
+                        if 2 * a > op.area_bound(net, pl, ph, p4, prm[2], prm[3]):
+                            broke = True
+                assert broke, (b, f, lo[i], hi[i])
+
+
+def test_partition_pieces_are_not_split_needlessly():
+    """A face whose whole area already meets its bound stays one piece; the
+    halving stops as soon as a piece meets its bound (lone cube: all pieces
+    have the largest admissible dyadic area)."""
+    lo, hi, c = op.mesh_partition([[0, 0, 0], [-30, -30, -30]], [[1, 1, 1], [31, 31, 31]], [0, -1], 0,
+                                  0.05, 2.0, 1.0, 0.5)
+    # enclosure faces: distance >= 30, bound 0.05 * (30/0.5)^3 = 10800 > face area 3721: one piece each
+    assert int((c == -1).sum()) == 6
+    assert int((c == 0).sum()) == 6 * 32
+
+
+def test_table2_partitioned_extraction():
+    """Section 5, Table 2: with per-main-net meshes of about 100 pieces the
+    capacitances are within 3 % of the paper's finest GBEM row and the two
+    columns agree (C12 = C21) within 1 %."""
+    with open(os.path.join(GOLDEN, "table2_crossing_bars.json")) as f:
+        g = json.load(f)
+    blo, bhi, bc = BARS.arrays()
+    C, panels = op.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, *PARAMS[0])
+    C = C * 1e18
+    say(f"  partitioned C (aF) {np.round(C, 2).tolist()} panels {panels}")
+    assert max(panels) < 150
+    row = g["gbem"][-1]
+    for key, val in (("C11", C[0, 0]), ("C12", C[0, 1]), ("C21", C[1, 0]), ("C22", C[1, 1])):
+        assert abs(val - row[key]) <= 0.03 * abs(row[key]), (key, val)
+    assert abs(C[0, 1] - C[1, 0]) <= 0.01 * abs(C[0, 1])
+
+
+# ---------------------------------------------------------------- library vs oracle
+@pytest.mark.parametrize("prm", PARAMS)
+@pytest.mark.parametrize("layout", [BARS, gi.random_small_layout(4), gi.crossing_bus()],
+                         ids=["bars_in_box", "random4", "crossing_bus"])
+def test_library_partition_bit_exact(layout, prm):
+    blo, bhi, bc = layout.arrays()
+    for k in range(min(layout.n_conductors, 3)):
+        a = binding.mesh_partition(blo, bhi, bc, k, *prm)
+        b = op.mesh_partition(blo, bhi, bc, k, *prm)
+        for x, y in zip(a, b):
+            assert x.dtype == y.dtype and x.shape == y.shape
+            assert x.tobytes() == y.tobytes()
+
+
+def test_library_partition_rejects_bad_rules():
+    blo, bhi, bc = BARS.arrays()
+    for prm in [(0.0, 4.0, 1.0, 1.0), (1.0, 0.5, 1.0, 1.0), (1.0, 4.0, 0.0, 1.0), (1.0, 4.0, 1.0, -1.0),
+                (math.inf, 4.0, 1.0, 1.0)]:
+        with pytest.raises(binding.GbemError) as e:
+            binding.mesh_partition(blo, bhi, bc, 0, *prm)
+        assert e.value.status == binding.EINVAL
+    with pytest.raises(binding.GbemError):
+        binding.mesh_partition(blo, bhi, bc, 5, *PARAMS[0])   # no box on net 5
+    with pytest.raises(binding.GbemError):
+        binding.mesh_partition(blo, bhi, bc, 0, 1e-30, 4.0, 1.0, 1.0)   # far too fine
+
+
+# ---------------------------------------------------------------- GPU
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prm", PARAMS[:2])
+def test_gpu_partitioned_extraction_vs_oracle(ctx, prm):
+    blo, bhi, bc = BARS.arrays()
+    say(f"partitioned extraction bars_in_box {prm}")
+    C, panels, rep = ctx.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, *prm)
+    Co, po = op.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, *prm)
+    say(f"  C(aF) {np.round(C * 1e18, 3).tolist()} panels {panels.tolist()} rel {_rel(C, Co):.2e} asym {rep['asym']:.2e}")
+    assert panels.tolist() == po
+    assert rep["n_panels"] == sum(po)
+    assert _rel(C, Co) < 1e-10
+    # mixed precision path on the same meshes
+    o = binding.make_opts(3, 2.0, "f32", "f16", 1e-8, 40)
+    Cm, _, repm = ctx.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, *prm, opts=o)
+    assert _rel(Cm, Co) < 1e-3
+
+
+@pytest.mark.gpu
+def test_gpu_partitioned_extraction_three_nets(ctx):
+    lay = gi.random_small_layout(4)
+    blo, bhi, bc = lay.arrays()
+    prm = (0.1, 3.0, 1.0, 0.5)
+    C, panels, rep = ctx.extract_partitioned(blo, bhi, bc, lay.n_conductors, lay.eps_r, lay.length_unit_m, *prm)
+    Co, po = op.extract_partitioned(blo, bhi, bc, lay.n_conductors, lay.eps_r, lay.length_unit_m, *prm)
+    say(f"  random4 panels {panels.tolist()} rel {_rel(C, Co):.2e}")
+    assert panels.tolist() == po
+    assert _rel(C, Co) < 1e-10
