@@ -266,7 +266,9 @@ def sweep(args, binding, np):
 
 PARTITION_SETS = {
     # section 3.3 rule (p1, p2, p3, p5); lengths in the layout's unit (um)
-    "crossing_bars_in_box": [(1.0, 4.0, 1.0, 1.0), (0.5, 4.0, 0.25, 2.0), (0.1, 4.0, 1.0, 1.0)],
+    # the last three land near Table 2's sizes (about 74, 183 and 594 pieces per mesh)
+    "crossing_bars_in_box": [(1.0, 4.0, 1.0, 1.0), (0.5, 4.0, 0.25, 2.0), (0.1, 4.0, 1.0, 1.0),
+                             (0.5, 4.0, 2.0, 0.5), (0.2, 4.0, 4.0, 0.5), (1.5, 4.0, 0.5, 4.0)],
     "crossing_bus": [(0.01, 4.0, 1.0, 0.2), (0.005, 4.0, 1.0, 0.2), (0.0025, 4.0, 1.0, 0.2), (0.001, 4.0, 1.0, 0.2)],
 }
 
@@ -342,7 +344,7 @@ def main():
                     help="also run a plain 256 MiB device copy (the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the extraction runs on a single GPU; multi-GPU runs are not supported, use --gpus 1"}))
         sys.exit(2)
 
     import numpy as np

@@ -13,8 +13,11 @@ outer boundary, section 2.1 / 3.1).
 Mesh rules (numbers are in the box's length unit):
   ("uniform", h)                  every box edge of length L is split into
                                   n = max(1, ceil(L/h - 1e-9)) equal cells
-  ("graded", h_min, growth, h_max) edge-graded split, cells grow geometrically
-                                  from both ends (see the design doc for the rule)
+  ("graded", h_min, growth, h_max) edge-graded split: cells h_min, h_min*growth,
+                                  ... from both ends while a cell is <= h_max and
+                                  the run from one end stays <= L/2; the middle
+                                  is split uniformly into
+                                  max(1, ceil(rem/h_max - 1e-9)) cells
 """
 from __future__ import annotations
 

@@ -92,12 +92,12 @@ _vp = ctypes.c_void_p
 
 
 def load():
-    """Load libgbem.so (built by ``__graft_entry__.build()``); raises if missing."""
+    """Load libgbem.so (built by ``python -m paper_2203_11733_amd.build``); raises if missing."""
     global _LIB
     if _LIB is not None:
         return _LIB
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2203_11733_amd.build")
     lib = ctypes.CDLL(LIB_PATH)
     lib.gbem_version.restype = ctypes.c_char_p
     lib.gbem_status_str.restype = ctypes.c_char_p

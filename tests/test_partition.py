@@ -182,6 +182,22 @@ def test_table2_partitioned_extraction():
     assert abs(C[0, 1] - C[1, 0]) <= 0.01 * abs(C[0, 1])
 
 
+def test_table2_size_594():
+    """Section 5, Table 2, 594-panel row: a rule that yields about 594 pieces
+    per main-net mesh (p1 = 1.5, p2 = 4, p3 = 0.5, p5 = 4) reproduces the
+    paper's capacitances within 2 %."""
+    with open(os.path.join(GOLDEN, "table2_crossing_bars.json")) as f:
+        g = json.load(f)
+    row = [r for r in g["gbem"] if r["panels"] == 594][0]
+    blo, bhi, bc = BARS.arrays()
+    C, panels = op.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, 1.5, 4.0, 0.5, 4.0)
+    C = C * 1e18
+    say(f"  594-size partition C (aF) {np.round(C, 2).tolist()} panels {panels}")
+    assert all(abs(n - 594) <= 0.02 * 594 for n in panels)
+    for key, val in (("C11", C[0, 0]), ("C12", C[0, 1]), ("C21", C[1, 0]), ("C22", C[1, 1])):
+        assert abs(val - row[key]) <= 0.02 * abs(row[key]), (key, val)
+
+
 # ---------------------------------------------------------------- library vs oracle
 @pytest.mark.parametrize("prm", PARAMS)
 @pytest.mark.parametrize("layout", [BARS, gi.random_small_layout(4), gi.crossing_bus()],
