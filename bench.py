@@ -320,6 +320,29 @@ def partitioned(args, binding, np):
     return out
 
 
+def exact_mode(args, binding, np):
+    """Exact reference mode (every pair through the exact integral) against the
+    default far-field rule and the p = 8, eta = 4 setting, FP64 throughout."""
+    lay = layout_of(args.layout)
+    lo, hi, cond = binding.mesh_layout(lay)
+    n, m = lo.shape[0], lay.n_conductors
+    ctx = binding.Context(0)
+    res = {}
+    for name, (p, eta) in (("exact", (3, 1e6)), ("p8_eta4", (8, 4.0)), ("p3_eta2", (3, 2.0))):
+        o = binding.make_opts(p, eta)
+        ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, o)
+        t0 = time.perf_counter()
+        C, rep = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, o)
+        res[name] = (C, (time.perf_counter() - t0) * 1e3, rep)
+        log(f"exact: {name} {res[name][1]:.1f} ms, near pairs {rep['n_near']}")
+    Ce = res["exact"][0]
+    rows = [{"setting": k, "ms": v[1], "assemble_ms": v[2]["t_assemble_ms"], "near_pairs": v[2]["n_near"],
+             "C_rel_dev_from_exact": float(np.abs(v[0] - Ce).max() / np.abs(Ce).max())} for k, v in res.items()]
+    ctx.close()
+    return {"metric": "exact reference mode", "unit": "ms per extraction (FP64)",
+            "config": {"workload": f"{lay.name}: N={n}, M={m}"}, "pairs": n * (n + 1) // 2, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,6 +363,8 @@ def main():
     ap.add_argument("--partition", action="store_true",
                     help="per-main-net meshes by the section 3.3 rule on --layout (crossing_bus or "
                          "crossing_bars_in_box) against the layout's own mesh")
+    ap.add_argument("--exact", action="store_true",
+                    help="exact reference mode (every pair exact) on --layout vs the far-field settings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference for HBM byte counters)")
     args = ap.parse_args()
@@ -357,6 +382,9 @@ def main():
         return
     if args.partition:
         print(json.dumps(partitioned(args, binding, np)))
+        return
+    if args.exact:
+        print(json.dumps(exact_mode(args, binding, np)))
         return
     if args.sweep:
         if args.layout == "crossing_bus":
