@@ -97,7 +97,7 @@ struct DevBuf {
 // all of them.
 struct Readback {
     int64_t nnz;
-    int32_t bad, info, serr, pad;
+    int32_t bad, info, perr, serr;   // info, perr: flags[1], flags[2] (pivot status, panel wait error)
     double bn[kMaxRhs], rn[kMaxRhs];
     double C[kMaxRhs * kMaxRhs];
 };
@@ -398,7 +398,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         // The pivot status is read with the next host wait; the solves are
         // queued behind it regardless (on a failed factor they are discarded:
         // their termination does not depend on the values).
-        HIPCHK(hipMemcpyAsync(&rbk->info, flags + 1, 4, hipMemcpyDeviceToHost, st), "D2H info");
+        HIPCHK(hipMemcpyAsync(&rbk->info, flags + 1, 8, hipMemcpyDeviceToHost, st), "D2H info");
         HIPCHK(chol_solve_prep(dtype, npad, Fm, lda, ws.Winv.p, ws.sync, st), "solve prep");
         HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
         HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
@@ -427,6 +427,10 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             HIPCHK(hipMemcpyAsync(&rbk->serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
             HIPCHK(hipEventRecord(ws.evrb, st), "hipEventRecord");
             HIPCHK(hipEventSynchronize(ws.evrb), "hipEventSynchronize");
+            if (rbk->perr) {
+                set_error("Cholesky: a panel wait exceeded its poll limit");
+                return GBEM_EDEVICE;
+            }
             if (iters == 0 && rbk->info != 0) {   // the low-precision factor failed
                 retry = true;
                 break;
@@ -473,6 +477,10 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(hipMemcpyAsync(&rbk->serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
     if (hC) HIPCHK(hipMemcpyAsync(rbk->C, dC, sizeof(double) * m * m, hipMemcpyDeviceToHost, st), "D2H C");
     HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (rbk->perr) {
+        set_error("Cholesky: a panel wait exceeded its poll limit");
+        return GBEM_EDEVICE;
+    }
     if (dtype == GBEM_F64 && rbk->info != 0) {
         set_error("Cholesky: non-positive pivot at row " + std::to_string(rbk->info - 1));
         return GBEM_ENOTPD;
@@ -1091,9 +1099,14 @@ static gbem_status chol_common(gbem_ctx *ctx, int32_t n, int32_t dtype, void *A,
         HIPCHK(chol_factor(dtype, npad, Ap.p, npad, ws.Winv.p, ws.Pw.p, ws.P16.p, ws.flags.as<int32_t>() + 1, st,
                            ws.side, ws.fev),
                "cholesky");
-        int32_t inf = 0;
-        HIPCHK(hipMemcpyAsync(&inf, ws.flags.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost, st), "D2H");
+        int32_t ie[2] = {0, 0};   // pivot status, panel wait error
+        HIPCHK(hipMemcpyAsync(ie, ws.flags.as<int32_t>() + 1, 8, hipMemcpyDeviceToHost, st), "D2H");
         HIPCHK(hipStreamSynchronize(st), "sync");
+        if (ie[1]) {
+            set_error("Cholesky: a panel wait exceeded its poll limit");
+            return GBEM_EDEVICE;
+        }
+        int32_t inf = ie[0];
         if (info) *info = inf;
         if (inf > n) inf = 0;   // a pivot in the identity padding cannot fail
         if (inf != 0) {

@@ -20,6 +20,7 @@
 // 16-bit row-major copy of the panel.
 #include "gbem_internal.h"
 
+#include <atomic>
 #include <type_traits>
 
 namespace gbem {
@@ -582,39 +583,91 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int tm, int K, const T *A,
 }
 
 // ------------------------------------------------------------------------
-// Factorisation of one outer panel (ow columns from P0, ns = ow/128
-// column blocks) after its diagonal block 0 is factored.  Step j (one
-// launch, j = 0 .. ns-1), P = the panel's top-left corner, tile I covering
-// the rows 128 (j + 1 + I) .. of the panel:
-//   - column block j of those rows receives the updates of blocks 0..j-1,
-//     A[R, j] -= X[R, 0..j-1] X[j, 0..j-1]^T          (K = 128 j)
-//   - panel solve in place, X[R, j] = A[R, j] W_j^T   (W_j = L_jj^{-1})
-//   - tile 0 (the rows of diagonal block j+1) then updates that block with
-//     blocks 0..j and factors it (L, W_{j+1}).
-// For 16-bit trailing updates the solve also writes the 16-bit copy of the
-// rows below the panel (row-major Q, columns 128 j ..).
+// Factorisation of one outer panel (ow columns from P0, ns = ow/128 column
+// blocks) after its diagonal block 0 is factored, in one launch.  P = the
+// panel's top-left corner; workgroup I owns row block q = I + 1 (rows
+// 128 q ..) and walks the panel's columns j = 0 .. min(q, ns) - 1:
+//   - j > 0: A[q, j] -= X[q, 0..j-1] X[j, 0..j-1]^T     (K = 128 j), once row
+//     block j has published its columns 0..j-1;
+//   - panel solve in place, X[q, j] = A[q, j] W_j^T    (W_j = L_jj^{-1}), once
+//     W_j is published (W_0 comes from the launch before);
+//   - q < ns (a diagonal block of the panel): after its columns it publishes
+//     them, updates A[q, q] with them and factors it (L_qq, W_q), then
+//     publishes W_q.
+// So while one workgroup factors diagonal block q, the others already apply
+// column q's update.  Row blocks are handed out by an atomic ticket in
+// execution order, so a workgroup only ever waits for lower row blocks whose
+// workgroups already run: every wait ends (also beside other kernels that
+// hold CUs); each is bounded and sets the error word pf[0] instead of
+// spinning on.  pf[2 ns + 1] is the ticket counter; the workgroup with the
+// last ticket resets it for the next launch on the stream.  pf[1 + q] / pf[1 + ns + q]: "columns of
+// row block q" / "W_q" flags, holding the launch's epoch when published
+// (release after the stores, acquire after the flag: agent scope, since the
+// workgroups sit on different XCDs).  For 16-bit trailing updates the solve
+// also writes the 16-bit copy of the rows below the panel (row-major Q,
+// columns 128 j ..).
 // ------------------------------------------------------------------------
+__device__ __forceinline__ bool panel_wait(const int32_t *flag, int32_t epoch, int32_t *err, int limit)
+{
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        int n = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++n > limit) break;
+        }
+        ok = n <= limit;
+        if (!ok) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+__device__ __forceinline__ void panel_publish(int32_t *flag, int32_t epoch)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename T, int Q16>
-__global__ __launch_bounds__(256) void panel_step_kernel(T *P, int64_t lda, int j, int ns, const T *Wj, T *Wn,
-                                                         int32_t *info, int kn, void *Q)   // ns = ow / 128
+__global__ __launch_bounds__(256) void panel_kernel(T *P, int64_t lda, int ns, T *W, int32_t *info, int kn0, void *Q,
+                                                    int32_t *pf, int32_t epoch, int limit)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    const int I = blockIdx.x;
-    const int64_t r0 = (int64_t)kNB * (j + 1 + I);   // first row of the tile within the panel
-    T *C = P + r0 + (int64_t)kNB * j * lda;
-    if (j > 0) {
-        gemm_tile<T, false, true, 0>(0, 0, kNB * j, P + r0, lda, P + (int64_t)kNB * j, lda, C, lda, nullptr, 0, 0,
-                                     smem_raw);
-        __syncthreads();   // this workgroup's updated tile is complete and visible to it
+    __shared__ int ticket;
+    if (threadIdx.x == 0) {
+        ticket = atomicAdd(pf + 2 * ns + 1, 1);
+        if (ticket == (int)gridDim.x - 1) __hip_atomic_store(pf + 2 * ns + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    gemm_tile<T, false, false, Q16>(0, 0, kNB, C, lda, Wj, kNB, C, lda, Q, (int)(r0 - kNB * ns), kNB * j, smem_raw,
-                                    kNB * ns);
-    if (I != 0 || j + 1 >= ns) return;
     __syncthreads();
-    T *D = P + r0 + r0 * lda;   // diagonal block j + 1
-    gemm_tile<T, true, true, 0>(0, 0, kNB * (j + 1), P + r0, lda, P + r0, lda, D, lda, nullptr, 0, 0, smem_raw);
+    if (ticket < 0 || ticket >= (int)gridDim.x) {   // counter not reset: report, do nothing
+        if (threadIdx.x == 0) __hip_atomic_store(pf, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const int q = ticket + 1;
+    const int64_t r0 = (int64_t)kNB * q;   // first row of the block within the panel
+    const int nc = min(q, ns);
+    for (int j = 0; j < nc; ++j) {
+        T *C = P + r0 + (int64_t)kNB * j * lda;
+        if (j > 0) {
+            if (!panel_wait(pf + 1 + j, epoch, pf, limit)) return;
+            gemm_tile<T, false, true, 0>(0, 0, kNB * j, P + r0, lda, P + (int64_t)kNB * j, lda, C, lda, nullptr, 0, 0,
+                                         smem_raw);
+            __syncthreads();   // this workgroup's updated block is complete and visible to it
+            if (!panel_wait(pf + 1 + ns + j, epoch, pf, limit)) return;
+        }
+        gemm_tile<T, false, false, Q16>(0, 0, kNB, C, lda, W + (int64_t)kNB * j * kNB, kNB, C, lda, Q,
+                                        (int)(r0 - kNB * ns), kNB * j, smem_raw, kNB * ns);
+        __syncthreads();
+    }
+    if (q >= ns) return;
+    panel_publish(pf + 1 + q, epoch);   // columns 0..q-1 of row block q
+    T *D = P + r0 + r0 * lda;            // diagonal block q
+    gemm_tile<T, true, true, 0>(0, 0, kNB * q, P + r0, lda, P + r0, lda, D, lda, nullptr, 0, 0, smem_raw);
     __syncthreads();
-    diag_block<T, true>(D, lda, Wn, info, kn, smem_raw);
+    diag_block<T, true>(D, lda, W + (int64_t)kNB * q * kNB, info, kn0 + kNB * q, smem_raw);
+    panel_publish(pf + 1 + ns + q, epoch);   // W_q and L_qq
 }
 
 // ------------------------------------------------------------------------
@@ -799,34 +852,39 @@ static hipError_t launch_syrk16(int tm, int ntiles, int K, const H *QA, const H 
     return hipGetLastError();
 }
 
-// Factor the outer panel at P0 (ow columns, rows P0 .. npad):
-// diagonal block 0, then one panel_step launch per column block.
+// Factor the outer panel at P0 (ow columns, rows P0 .. npad): diagonal
+// block 0, then the rest of the panel in one launch.  info[1 .. 1 + 2 ns]:
+// error word and flags of panel_kernel.
+static std::atomic<int32_t> g_panel_epoch{0};
 template <typename T, int Q16T>
 static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
                                int64_t P0, hipStream_t s, Prof *prof)
 {
     const double es = (double)sizeof(T);
     const int ns = ow / kNB;
+    if (ns > kMaxPanelBlocks) return hipErrorInvalidValue;
     const size_t smem = std::max(gemm_smem_bytes<T>(), diag_smem_bytes(sizeof(T)));
-    hipError_t e = hipFuncSetAttribute((const void *)panel_step_kernel<T, Q16T>,
+    hipError_t e = hipFuncSetAttribute((const void *)panel_kernel<T, Q16T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     int tok = prof ? prof->start(s, GBEM_K_DIAG) : -1;
     hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
                        A + P0 + P0 * lda, lda, Winv + P0 * kNB, info, (int)P0);
     if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
-    T *P = A + P0 + P0 * lda;
-    for (int j = 0; j < ns; ++j) {
-        const int64_t m = npad - P0 - (int64_t)kNB * (j + 1);   // rows below diagonal block j
-        if (m <= 0) break;
-        tok = prof ? prof->start(s, GBEM_K_TRSM) : -1;
-        hipLaunchKernelGGL((panel_step_kernel<T, Q16T>), dim3((unsigned)(m / kNB)), dim3(256), smem, s, P, lda, j, ns,
-                           (const T *)(Winv + (P0 + (int64_t)kNB * j) * kNB), Winv + (P0 + (int64_t)kNB * (j + 1)) * kNB,
-                           info, (int)(P0 + kNB * (j + 1)), Q16);
-        if (prof)
-            prof->stop(tok, GBEM_K_TRSM,
-                       2.0 * m * kNB * kNB * (j + 1) + (j + 1 < ns ? 2.0 * kNB * kNB * kNB * (j + 1.0 + 1.0 / 3.0) : 0.0),
-                       (2.0 + j) * m * kNB * es + 3.0 * kNB * kNB * es + (Q16 ? 2.0 * m * kNB : 0.0), s);
+    const int64_t m = npad - P0 - kNB;   // rows below diagonal block 0
+    if (m <= 0) return hipGetLastError();
+    const int32_t epoch = ++g_panel_epoch;
+    tok = prof ? prof->start(s, GBEM_K_TRSM) : -1;
+    hipLaunchKernelGGL((panel_kernel<T, Q16T>), dim3((unsigned)(m / kNB)), dim3(256), smem, s, A + P0 + P0 * lda,
+                       lda, ns, Winv + P0 * kNB, info, (int)P0, Q16, info + 1, epoch, 1 << 22);
+    if (prof) {
+        double fl = 0.0, by = 0.0;
+        for (int j = 0; j < ns; ++j) {
+            const double mj = (double)(m - (int64_t)kNB * j);
+            fl += 2.0 * mj * kNB * kNB * (j + 1) + (j + 1 < ns ? 2.0 * kNB * kNB * kNB * (j + 1.0 + 1.0 / 3.0) : 0.0);
+            by += (2.0 + j) * mj * kNB * es + 3.0 * kNB * kNB * es + (Q16 ? 2.0 * mj * kNB : 0.0);
+        }
+        prof->stop(tok, GBEM_K_TRSM, fl, by, s);
     }
     return hipGetLastError();
 }

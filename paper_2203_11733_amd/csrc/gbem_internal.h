@@ -16,6 +16,9 @@ namespace gbem {
 // identity block, so the factorisation and solves need no edge cases.
 constexpr int kFarTile = 64;
 constexpr int kNB = 128;          // Cholesky block (diagonal block lives in LDS)
+constexpr int kMaxPanelBlocks = 4;   // widest outer panel / kNB; chol_factor's info points at
+                                     // 3 + 2 * kMaxPanelBlocks zeroed ints (pivot info, error word,
+                                     // flags, ticket counter)
 constexpr int kPad = 512;         // padding of the matrix order (one outer Cholesky panel)
 constexpr int kMaxOrder = 8;      // largest Gauss order of the far rule
 constexpr int kMaxRhs = 64;       // right-hand sides handled per solve pass
