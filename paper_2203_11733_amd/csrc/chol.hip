@@ -358,7 +358,9 @@ __global__ __launch_bounds__(256) void diag_kernel(T *__restrict__ A, int64_t ld
 // ------------------------------------------------------------------------
 constexpr int kBM = 128, kBK = 16;
 // outer panel width for a matrix of order npad
-static int outer_width(int64_t npad) { return npad >= 32768 ? 512 : 256; }
+// (measured on the MI355X in mixed mode: 512 wins from order ~16k up, e.g.
+// 26.7 vs 28.2 ms at 20k panels; 256 below, where the panel chain dominates)
+static int outer_width(int64_t npad) { return npad >= 16384 ? 512 : 256; }
 constexpr int kLdsLd = kBM + 16;   // LDS row stride: the four k-rows of a fragment load hit distinct banks
 constexpr int kRect = 0, kTri = 1;
 
