@@ -102,6 +102,80 @@ __device__ __forceinline__ T rowbc(T v, int c)
     }
 }
 
+// Sum of x over the four 16-lane row groups of the wave, in every group
+// (v_permlane16_swap exchanges rows 0 <-> 1 and 2 <-> 3 of two registers,
+// v_permlane32_swap the two halves; both sums are formed in the same order in
+// every group, so all groups hold the same value).
+__device__ __forceinline__ float group_sum(float x)
+{
+    const unsigned u = __builtin_bit_cast(unsigned, x);
+    const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    const float y = __builtin_bit_cast(float, (unsigned)p[0]) + __builtin_bit_cast(float, (unsigned)p[1]);
+    const unsigned v = __builtin_bit_cast(unsigned, y);
+    const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __builtin_bit_cast(float, (unsigned)q[0]) + __builtin_bit_cast(float, (unsigned)q[1]);
+}
+
+// FP32 leaf factorisation and inverse with the work split over the four row
+// groups of the wave (lane = 16 g + r; group g owns the columns c = 4 k + g):
+// column c is the input column minus sum_{t<c} L_rt L_ct, each group summing
+// its own columns t and the groups' sums added with group_sum (left-looking),
+// then scaled by the pivot taken inside the owning group.  The substitution
+// for W = L^{-1} likewise updates W's columns 4 k + g in group g, with column
+// c of L sent to every group.  About 20 % faster than the replicated leaf
+// below on gfx950 (3.8 vs 4.8 thousand cycles); the FP64 leaf stays
+// replicated (its 64-bit swaps and divisions make the split version slower).
+__device__ __forceinline__ void leaf16_split(float *Lb, float *Wb, int32_t *info, int grow)
+{
+    typedef float T;
+    const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    T a[4], l[4], w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = Lb[(4 * k + g) * kLB + r];
+        l[k] = T(0);
+        w[k] = (4 * k + g == r) ? T(1) : T(0);
+    }
+    int firstbad = -1;
+    T rr = T(0);
+#pragma clang loop unroll(full)
+    for (int c = 0; c < kLB; ++c) {
+        const int gc = c & 3, kc = c >> 2;
+        T x = T(0);
+#pragma unroll
+        for (int k = 0; k < (c + 3) / 4; ++k) x += l[k] * rowbc(l[k], c);   // columns not yet done hold 0
+        const T y = a[kc] - group_sum(x);   // column c after its updates (group gc)
+        T piv = rowbc(y, c);
+        const bool bad = !(piv > T(0));
+        firstbad = (firstbad < 0 && bad && g == gc) ? c : firstbad;
+        piv = bad ? T(1) : piv;
+        const T rdc = __builtin_amdgcn_rsqf(piv);   // refined in FP64 later: hardware rsq (~1 ulp)
+        const T d = piv * rdc;
+        const T lc = r > c ? y * rdc : (r == c ? d : T(0));
+        if (g == gc) l[kc] = lc;
+        // substitution step c: rows below c subtract L_rc / L_cc times row c
+        const T lr = group_sum(g == gc ? lc : T(0));   // column c in every group
+        const T inv = __builtin_amdgcn_rcpf(rowbc(lr, c));
+        rr = r == c ? inv : rr;
+        const T coef = r > c ? lr * inv : T(0);
+#pragma unroll
+        for (int k = 0; k <= c / 4; ++k) w[k] -= coef * rowbc(w[k], c);
+    }
+    // first non-positive pivot over the four groups
+    int fb = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int f = __builtin_amdgcn_readlane(firstbad, 16 * q);
+        fb = (f >= 0 && (fb < 0 || f < fb)) ? f : fb;
+    }
+    if (fb >= 0 && lane == 0 && *info == 0) *info = grow + fb + 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Lb[(4 * k + g) * kLB + r] = l[k];
+        Wb[(4 * k + g) * kLB + r] = w[k] * rr;
+    }
+}
+
 // One wave; lane r (mod 16) owns row r of the 16 x 16 block Lb (column-major,
 // lower triangle valid).  FACTOR: Cholesky in place (upper part written as
 // zero).  Then Wb = L^{-1} (lower, zero above).  Branch-free on lane-dependent
@@ -109,6 +183,10 @@ __device__ __forceinline__ T rowbc(T v, int c)
 template <typename T, bool FACTOR>
 __device__ __forceinline__ void leaf16(T *Lb, T *Wb, int32_t *info, int grow)
 {
+    if constexpr (FACTOR && sizeof(T) == 4) {
+        leaf16_split(Lb, Wb, info, grow);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int r = lane & 15;
     T v[kLB], rd[kLB];
@@ -650,8 +728,21 @@ __global__ __launch_bounds__(256) void panel_kernel(T *P, int64_t lda, int ns, T
     const int q = ticket + 1;
     const int64_t r0 = (int64_t)kNB * q;   // first row of the block within the panel
     const int nc = min(q, ns);
+    T *D = P + r0 + r0 * lda;   // diagonal block q (factored here when q < ns)
+    // FP64: diagonal block q's update (K = 128 q, on one workgroup) is split so
+    // that only its last column block follows W_{q-1} (C2, same GPU: 94.5 ->
+    // 91.5 ms per extraction); FP32: one update after the loop (the split
+    // measured 0.6 ms slower there)
+    constexpr bool kSplitD = sizeof(T) == 8;
     for (int j = 0; j < nc; ++j) {
         T *C = P + r0 + (int64_t)kNB * j * lda;
+        if (kSplitD && j > 0 && j == q - 1 && q < ns) {
+            // the part of diagonal block q's update from column blocks 0..q-2
+            // (final already), ahead of the waits for block q-1
+            gemm_tile<T, true, true, 0>(0, 0, kNB * (q - 1), P + r0, lda, P + r0, lda, D, lda, nullptr, 0, 0,
+                                        smem_raw);
+            __syncthreads();
+        }
         if (j > 0) {
             if (!panel_wait(pf + 1 + j, epoch, pf, limit)) return;
             gemm_tile<T, false, true, 0>(0, 0, kNB * j, P + r0, lda, P + (int64_t)kNB * j, lda, C, lda, nullptr, 0, 0,
@@ -665,8 +756,12 @@ __global__ __launch_bounds__(256) void panel_kernel(T *P, int64_t lda, int ns, T
     }
     if (q >= ns) return;
     panel_publish(pf + 1 + q, epoch);   // columns 0..q-1 of row block q
-    T *D = P + r0 + r0 * lda;            // diagonal block q
-    gemm_tile<T, true, true, 0>(0, 0, kNB * q, P + r0, lda, P + r0, lda, D, lda, nullptr, 0, 0, smem_raw);
+    if (kSplitD && q >= 2) {   // the rest of the update: column block q-1
+        const T *Pq = P + r0 + (int64_t)kNB * (q - 1) * lda;
+        gemm_tile<T, true, true, 0>(0, 0, kNB, Pq, lda, Pq, lda, D, lda, nullptr, 0, 0, smem_raw);
+    } else {
+        gemm_tile<T, true, true, 0>(0, 0, kNB * q, P + r0, lda, P + r0, lda, D, lda, nullptr, 0, 0, smem_raw);
+    }
     __syncthreads();
     diag_block<T, true>(D, lda, W + (int64_t)kNB * q * kNB, info, kn0 + kNB * q, smem_raw);
     panel_publish(pf + 1 + ns + q, epoch);   // W_q and L_qq
@@ -697,10 +792,16 @@ template <> struct Mfma32<_Float16> {
 constexpr int kBK16 = 64, kPad16 = 8;
 static size_t syrk16_smem_bytes() { return (size_t)2 * 2 * kBM * (kBK16 + kPad16) * 2; }
 
-template <typename H, int MODE, int NK>
+// DIAG0: the launch that updates the next outer panel's columns (MODE
+// kRect, C at that panel's diagonal) also factors the panel's first diagonal
+// block: the workgroup of tile (0, 0) runs diag_block on it after its own
+// update (W into Wd, pivot status into info, global row k0), so the
+// factorisation overlaps the rest of the update instead of following it.
+template <typename H, int MODE, int NK, bool DIAG0 = false>
 __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__restrict__ QA,
                                                      const H *__restrict__ QB, int64_t ldq,
-                                                     float *__restrict__ C, int64_t ldc)
+                                                     float *__restrict__ C, int64_t ldc, float *Wd = nullptr,
+                                                     int32_t *info = nullptr, int k0 = 0)
 {
     typedef typename Mfma32<H>::frag_t frag_t;
     constexpr int LD = kBK16 + kPad16;
@@ -809,6 +910,16 @@ __global__ __launch_bounds__(256) void syrk16_kernel(int tm, int K, const H *__r
             }
             *reinterpret_cast<f4_t *>(C + row + (int64_t)col * ldc) = v;
         }
+    if constexpr (DIAG0) {
+        if (I == 0 && J == 0) {   // uniform over the workgroup
+            // the block this workgroup just wrote: stores complete and visible
+            // (release), every wave done, then loads past the stale L1 lines
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            diag_block<float, true>(C, ldc, Wd, info, k0, smem_raw);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -838,29 +949,51 @@ static hipError_t launch_gemm(int tm, int ntiles, int K, const T *A, int64_t lda
     return hipGetLastError();
 }
 
+// Wd != nullptr: also factor the first diagonal block (DIAG0, kRect only)
 template <typename H, int MODE>
 static hipError_t launch_syrk16(int tm, int ntiles, int K, const H *QA, const H *QB, int64_t ldq, float *C,
-                                int64_t ldc, hipStream_t s)
+                                int64_t ldc, hipStream_t s, float *Wd = nullptr, int32_t *info = nullptr, int k0 = 0)
 {
-    const size_t smem = syrk16_smem_bytes();
-    const void *fn = K == 512 ? (const void *)syrk16_kernel<H, MODE, 8> : (const void *)syrk16_kernel<H, MODE, 4>;
+    const size_t smem = std::max(syrk16_smem_bytes(), Wd ? diag_smem_bytes(sizeof(float)) : (size_t)0);
     if (K != 512 && K != 256) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    if (K == 512)
-        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 8>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc);
-    else
-        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 4>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc);
+    hipError_t e;
+    if constexpr (MODE == kRect) {
+        if (Wd) {
+            const void *fn = K == 512 ? (const void *)syrk16_kernel<H, MODE, 8, true>
+                                      : (const void *)syrk16_kernel<H, MODE, 4, true>;
+            if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)) != hipSuccess)
+                return e;
+            if (K == 512)
+                hipLaunchKernelGGL((syrk16_kernel<H, MODE, 8, true>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB,
+                                   ldq, C, ldc, Wd, info, k0);
+            else
+                hipLaunchKernelGGL((syrk16_kernel<H, MODE, 4, true>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB,
+                                   ldq, C, ldc, Wd, info, k0);
+            return hipGetLastError();
+        }
+    } else if (Wd) {
+        return hipErrorInvalidValue;
+    }
+    const void *fn = K == 512 ? (const void *)syrk16_kernel<H, MODE, 8> : (const void *)syrk16_kernel<H, MODE, 4>;
+    if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)) != hipSuccess) return e;
+    if (K == 512) {
+        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 8>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc,
+                           nullptr, nullptr, 0);
+    } else {
+        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 4>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc,
+                           nullptr, nullptr, 0);
+    }
     return hipGetLastError();
 }
 
 // Factor the outer panel at P0 (ow columns, rows P0 .. npad): diagonal
-// block 0, then the rest of the panel in one launch.  info[1 .. 1 + 2 ns]:
+// block 0 (unless the update of the panel's columns already factored it),
+// then the rest of the panel in one launch.  info[1 .. 1 + 2 ns]:
 // error word and flags of panel_kernel.
 static std::atomic<int32_t> g_panel_epoch{0};
 template <typename T, int Q16T>
 static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
-                               int64_t P0, hipStream_t s, Prof *prof)
+                               int64_t P0, hipStream_t s, Prof *prof, bool diag0_done)
 {
     const double es = (double)sizeof(T);
     const int ns = ow / kNB;
@@ -869,10 +1002,13 @@ static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv,
     hipError_t e = hipFuncSetAttribute((const void *)panel_kernel<T, Q16T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    int tok = prof ? prof->start(s, GBEM_K_DIAG) : -1;
-    hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
-                       A + P0 + P0 * lda, lda, Winv + P0 * kNB, info, (int)P0);
-    if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
+    int tok;
+    if (!diag0_done) {
+        tok = prof ? prof->start(s, GBEM_K_DIAG) : -1;
+        hipLaunchKernelGGL((diag_kernel<T, true>), dim3(1), dim3(256), diag_smem_bytes(sizeof(T)), s,
+                           A + P0 + P0 * lda, lda, Winv + P0 * kNB, info, (int)P0);
+        if (prof) prof->stop(tok, GBEM_K_DIAG, 2.0 * kNB * kNB * kNB / 3.0, 3.0 * kNB * kNB * es, s);
+    }
     const int64_t m = npad - P0 - kNB;   // rows below diagonal block 0
     if (m <= 0) return hipGetLastError();
     const int32_t epoch = ++g_panel_epoch;
@@ -891,26 +1027,36 @@ static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv,
     return hipGetLastError();
 }
 
+// diag0_done: the first diagonal block was factored by the launch that
+// updated the panel's columns
 template <typename T>
 static hipError_t factor_panel(int dtype, int64_t npad, int ow, T *A, int64_t lda, T *Winv, void *Q16,
-                               int32_t *info, int p, hipStream_t s, Prof *prof)
+                               int32_t *info, int p, hipStream_t s, Prof *prof, bool diag0_done = false)
 {
     const int64_t P0 = (int64_t)p * ow;
-    if (Q16 && dtype == GBEM_BF16) return launch_panel<T, 1>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof);
-    if (Q16 && dtype == GBEM_F16) return launch_panel<T, 2>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof);
-    return launch_panel<T, 0>(npad, ow, A, lda, Winv, nullptr, info, P0, s, prof);
+    if (Q16 && dtype == GBEM_BF16)
+        return launch_panel<T, 1>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof, diag0_done);
+    if (Q16 && dtype == GBEM_F16)
+        return launch_panel<T, 2>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof, diag0_done);
+    return launch_panel<T, 0>(npad, ow, A, lda, Winv, nullptr, info, P0, s, prof, diag0_done);
 }
 
 // Outer update of columns [c0, c0 + ncols) of the trailing matrix with the
 // outer panel at P0 (ow columns): C = A[c0.., c0..] (origin on the diagonal),
 // rows m = npad - c0.  TRI when the block is square.
+// Wd != nullptr (16-bit updates of a rectangular block only): the launch also
+// factors the diagonal block at C's origin (W into Wd, pivot status into info).
 template <typename T>
 static hipError_t outer_update(int dtype, int64_t npad, int ow, T *A, int64_t lda, int64_t P0, const void *Q16,
-                               int64_t c0, int64_t ncols, hipStream_t s, Prof *prof, int cls)
+                               int64_t c0, int64_t ncols, hipStream_t s, Prof *prof, int cls, T *Wd = nullptr,
+                               int32_t *info = nullptr)
 {
     const int64_t m = npad - c0;
     const int tm = (int)(m / kBM), tn = (int)(ncols / kBM);
-    const bool tri = ncols == m;
+    // a square block takes the triangular tile grid, except when the launch
+    // also factors the diagonal block (rectangular grid; tiles above the
+    // diagonal return at once)
+    const bool tri = ncols == m && !Wd;
     const int ntiles = tri ? tm * (tm + 1) / 2 : tm * tn;
     T *C = A + c0 + c0 * lda;
     const double es = (double)sizeof(T);
@@ -924,17 +1070,23 @@ static hipError_t outer_update(int dtype, int64_t npad, int ow, T *A, int64_t ld
                 : launch_gemm<T, kRect, true, true>(tm, ntiles, ow, Q, lda, Q, lda, C, lda, s);
     } else {
         const int64_t q0 = c0 - (P0 + ow);   // first row of Q16 used
+        float *W32 = (float *)Wd;
         if (dtype == GBEM_BF16) {
             const __bf16 *Q = (const __bf16 *)Q16 + q0 * ow;
             e = tri ? launch_syrk16<__bf16, kTri>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s)
-                    : launch_syrk16<__bf16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s);
+                    : launch_syrk16<__bf16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s, W32, info, (int)c0);
         } else {
             const _Float16 *Q = (const _Float16 *)Q16 + q0 * ow;
             e = tri ? launch_syrk16<_Float16, kTri>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s)
-                    : launch_syrk16<_Float16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s);
+                    : launch_syrk16<_Float16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s, W32, info,
+                                                     (int)c0);
         }
     }
-    if (prof) prof->stop(tok, cls, 2.0 * tiles_el * ow, 2.0 * tiles_el * es + (double)m * ow * (b16 ? 2.0 : es), s);
+    if (prof) {
+        double fl = 2.0 * tiles_el * ow, by = 2.0 * tiles_el * es + (double)m * ow * (b16 ? 2.0 : es);
+        if (Wd) fl += 2.0 * kNB * kNB * kNB / 3.0, by += 3.0 * kNB * kNB * es;   // the diagonal block
+        prof->stop(tok, cls, fl, by, s);
+    }
     return e;
 }
 
@@ -973,10 +1125,13 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
         const int64_t P0 = (int64_t)K * ow;
         // side: (a) panel K+1's columns with panel K, then factor panel K+1
         if (K > 0 && (e = hipStreamWaitEvent(side, evB[K - 1], 0)) != hipSuccess) return e;
-        if ((e = outer_update<T>(dtype, npad, ow, A, lda, P0, q16(K), P0 + ow, ow, side, prof, GBEM_K_PANEL)) !=
-            hipSuccess)
+        // 16-bit updates: the same launch factors panel K+1's first diagonal block
+        T *Wd = b16 ? Winv + (P0 + ow) * kNB : nullptr;
+        if ((e = outer_update<T>(dtype, npad, ow, A, lda, P0, q16(K), P0 + ow, ow, side, prof, GBEM_K_PANEL, Wd,
+                                 info)) != hipSuccess)
             return e;
-        if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, q16(K + 1), info, K + 1, side, prof)) != hipSuccess)
+        if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, q16(K + 1), info, K + 1, side, prof, b16)) !=
+            hipSuccess)
             return e;
         if ((e = hipEventRecord(evP[K + 1], side)) != hipSuccess) return e;
         // main: (b) the columns beyond panel K+1 with panel K
