@@ -104,7 +104,7 @@ struct Readback {
 
 struct Workspace {
     DevBuf lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, D, s, partial, C,
-        flags, norms, sflags, rpart, semi;
+        flags, norms, sflags, rpart, semi, nmask;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t evrb = nullptr;          // readback point
     Readback *rb = nullptr;             // pinned host memory
@@ -150,7 +150,7 @@ struct Workspace {
     size_t bytes() const
     {
         const DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
-                               &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi};
+                               &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi, &nmask};
         size_t t = 0;
         for (auto *b : all) t += b->cap;
         return t;
@@ -158,7 +158,7 @@ struct Workspace {
     void release_all()
     {
         DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
-                         &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi};
+                         &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi, &nmask};
         for (auto *b : all) b->release();
     }
     hipError_t init_events()
@@ -200,6 +200,7 @@ static size_t footprint(int64_t n, int m, int factor_dtype)
     b += (size_t)npad * (2 * kMaxPub * 8 + 2 * kNB * 4);                 // solve: published blocks, M_k, N_k
     b += 4 * (size_t)npad * m * 8 + (size_t)npad * 8;                    // B X R D, s
     b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 12;           // mesh, panels, near list + queue
+    b += (size_t)n * near_mask_words(n) * 8;                              // near-test bit masks
     return b;
 }
 
@@ -276,6 +277,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(ws.pan.ensure(sizeof(Panel) * n), "alloc panels");
     HIPCHK(ws.cnt.ensure(sizeof(int64_t) * n), "alloc near counts");
     HIPCHK(ws.rowptr.ensure(sizeof(int64_t) * (n + 1)), "alloc row_ptr");
+    HIPCHK(ws.nmask.ensure(sizeof(uint64_t) * (size_t)n * near_mask_words(n)), "alloc near masks");
     HIPCHK(ws.flags.ensure(64), "alloc flags");
     HIPCHK(ws.A.ensure((size_t)npad * npad * 8), "alloc A");
     HIPCHK(ws.B.ensure((size_t)npad * m * 8), "alloc B");
@@ -301,7 +303,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     pf.stop(tok, GBEM_K_OTHER, 0.0, (double)n * (48 + 4 + 64), st);
     const double eta2 = o.near_eta * o.near_eta;
     const int tok_near = pf.start(st, GBEM_K_NEAR_LIST);
-    HIPCHK(launch_near_count(dlo, dhi, n, eta2, ws.cnt.as<int64_t>(), st), "near_count");
+    HIPCHK(launch_near_count(dlo, dhi, n, eta2, ws.cnt.as<int64_t>(), ws.nmask.as<uint64_t>(), st), "near_count");
     HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), st), "scan");
     pf.stop(tok_near, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8 + 8), st, 2);
     double *B = ws.B.as<double>();
@@ -350,9 +352,9 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
     HIPCHK(ws.semi.ensure(near_semi_bytes(nnz)), "alloc near queue");
     tok = pf.start(st, GBEM_K_NEAR_LIST);
-    HIPCHK(launch_near_fill(dlo, dhi, n, eta2, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
+    HIPCHK(launch_near_fill(ws.nmask.as<uint64_t>(), n, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
                             ws.ncol.as<int32_t>(), st), "near_fill");
-    pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (48 + 8) + (double)nnz * 8, st);
+    pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (n + 64) / 16.0 + (double)nnz * 8, st);
     tok = pf.start(st, GBEM_K_NEAR_EVAL);
     HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
                             A, lda, ws.semi.as<int32_t>(), st), "near_eval");
@@ -985,8 +987,10 @@ extern "C" gbem_status gbem_near_list(gbem_ctx *ctx, const gbem_mesh *mesh, doub
     const int n = mesh->n_panels;
     HIPCHK(ws.cnt.ensure(sizeof(int64_t) * n), "alloc");
     HIPCHK(ws.rowptr.ensure(sizeof(int64_t) * (n + 1)), "alloc");
+    HIPCHK(ws.nmask.ensure(sizeof(uint64_t) * (size_t)n * near_mask_words(n)), "alloc");
     const double eta2 = near_eta * near_eta;
-    HIPCHK(launch_near_count(ws.lo.as<double>(), ws.hi.as<double>(), n, eta2, ws.cnt.as<int64_t>(), ctx->stream), "near_count");
+    HIPCHK(launch_near_count(ws.lo.as<double>(), ws.hi.as<double>(), n, eta2, ws.cnt.as<int64_t>(),
+                             ws.nmask.as<uint64_t>(), ctx->stream), "near_count");
     HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), ctx->stream), "scan");
     HIPCHK(hipMemcpyAsync(row_ptr, ws.rowptr.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, ctx->stream), "D2H");
     HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
@@ -998,8 +1002,8 @@ extern "C" gbem_status gbem_near_list(gbem_ctx *ctx, const gbem_mesh *mesh, doub
     }
     HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(*nnz, 1)), "alloc");
     HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(*nnz, 1)), "alloc");
-    HIPCHK(launch_near_fill(ws.lo.as<double>(), ws.hi.as<double>(), n, eta2, ws.rowptr.as<int64_t>(),
-                            ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), ctx->stream), "near_fill");
+    HIPCHK(launch_near_fill(ws.nmask.as<uint64_t>(), n, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
+                            ws.ncol.as<int32_t>(), ctx->stream), "near_fill");
     HIPCHK(hipMemcpyAsync(col, ws.ncol.p, sizeof(int32_t) * *nnz, hipMemcpyDeviceToHost, ctx->stream), "D2H");
     HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
     return GBEM_OK;

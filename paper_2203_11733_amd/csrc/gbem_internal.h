@@ -133,11 +133,13 @@ hipError_t launch_gather(const double *A, int64_t lda, const int32_t *ii, const 
 hipError_t launch_identity_pad(void *A, int64_t lda, int n, int npad, bool f64, hipStream_t s);
 
 // near.hip (compiled with -ffp-contract=off: the near/far test is bit-exact)
+// mask: n * near_mask_words(n) words, written by near_count, read by near_fill
+inline int64_t near_mask_words(int64_t n) { return (n + 63) / 64; }
 hipError_t launch_near_count(const double *lo, const double *hi, int n, double eta2,
-                             int64_t *cnt, hipStream_t s);
+                             int64_t *cnt, uint64_t *mask, hipStream_t s);
 hipError_t launch_exclusive_scan(const int64_t *cnt, int n, int64_t *row_ptr, hipStream_t s);
-hipError_t launch_near_fill(const double *lo, const double *hi, int n, double eta2,
-                            const int64_t *row_ptr, int32_t *row, int32_t *col, hipStream_t s);
+hipError_t launch_near_fill(const uint64_t *mask, int n, const int64_t *row_ptr, int32_t *row, int32_t *col,
+                            hipStream_t s);
 
 // near_eval.hip: closed-form Galerkin integrals of the near pairs.
 // semi_buf: near_semi_bytes(nnz) bytes of scratch (queue of semi-analytic pairs)

@@ -33,10 +33,13 @@ __device__ __forceinline__ bool is_near(const double *li, const double *hi_, dou
     return sep2 < eta2 * dm;
 }
 
-// One workgroup per row i; counts near j in [0, i].
+// One workgroup per row i; counts near j in [0, i] and keeps the test
+// results as bit masks: mask[i * nw + c] bit b <=> column 64 c + b is near
+// (nw = ceil(n / 64) words per row; words past i / 64 are not written).
 __global__ __launch_bounds__(256) void near_count_kernel(const double *__restrict__ lo,
                                                          const double *__restrict__ hi, int n,
-                                                         double eta2, int64_t *__restrict__ cnt)
+                                                         double eta2, int64_t *__restrict__ cnt,
+                                                         uint64_t *__restrict__ mask)
 {
     __shared__ int64_t red[4];
     const int i = blockIdx.x;
@@ -46,14 +49,24 @@ __global__ __launch_bounds__(256) void near_count_kernel(const double *__restric
         hi_[k] = hi[3 * i + k];
     }
     const double di = diam2_of(li, hi_);
+    const int64_t nw = (n + 63) / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t c = 0;
-    for (int j = threadIdx.x; j <= i; j += 256) {
-        double lj[3], hj[3];
-        for (int k = 0; k < 3; ++k) {
-            lj[k] = lo[3 * j + k];
-            hj[k] = hi[3 * j + k];
+    for (int base = 0; base <= i; base += 256) {   // uniform trip count: every lane reaches the ballot
+        const int j = base + threadIdx.x;
+        bool nr = false;
+        if (j <= i) {
+            double lj[3], hj[3];
+            for (int k = 0; k < 3; ++k) {
+                lj[k] = lo[3 * j + k];
+                hj[k] = hi[3 * j + k];
+            }
+            nr = is_near(li, hi_, di, lj, hj, diam2_of(lj, hj), eta2);
         }
-        c += is_near(li, hi_, di, lj, hj, diam2_of(lj, hj), eta2) ? 1 : 0;
+        c += nr ? 1 : 0;
+        const uint64_t bits = __ballot(nr);
+        const int w0 = base + 64 * wave;   // first column of this wave's word
+        if (lane == 0 && w0 <= i) mask[(int64_t)i * nw + w0 / 64] = bits;
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
@@ -62,10 +75,10 @@ __global__ __launch_bounds__(256) void near_count_kernel(const double *__restric
 }
 
 hipError_t launch_near_count(const double *lo, const double *hi, int n, double eta2, int64_t *cnt,
-                             hipStream_t s)
+                             uint64_t *mask, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(near_count_kernel, dim3(n), dim3(256), 0, s, lo, hi, n, eta2, cnt);
+    hipLaunchKernelGGL(near_count_kernel, dim3(n), dim3(256), 0, s, lo, hi, n, eta2, cnt, mask);
     return hipGetLastError();
 }
 
@@ -103,58 +116,45 @@ hipError_t launch_exclusive_scan(const int64_t *cnt, int n, int64_t *row_ptr, hi
     return hipGetLastError();
 }
 
-// One workgroup per row; writes the near columns of row i in ascending order
-// (ballot + prefix count within each 256-wide chunk), and the row index.
-__global__ __launch_bounds__(256) void near_fill_kernel(const double *__restrict__ lo,
-                                                        const double *__restrict__ hi, int n,
-                                                        double eta2,
+// One wave per row: the columns of row i in ascending order, read from the
+// masks of near_count (popcounts, a prefix sum over the wave's 64 words,
+// then each lane writes the set bits of its word), and the row index.
+__global__ __launch_bounds__(256) void near_fill_kernel(const uint64_t *__restrict__ mask, int n,
                                                         const int64_t *__restrict__ row_ptr,
-                                                        int32_t *__restrict__ row,
-                                                        int32_t *__restrict__ col)
+                                                        int32_t *__restrict__ row, int32_t *__restrict__ col)
 {
-    __shared__ int wave_cnt[4];
-    const int i = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double li[3], hi_[3];
-    for (int k = 0; k < 3; ++k) {
-        li[k] = lo[3 * i + k];
-        hi_[k] = hi[3 * i + k];
-    }
-    const double di = diam2_of(li, hi_);
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;   // whole wave
+    const int64_t nw = (n + 63) / 64;
+    const int words = i / 64 + 1;
     int64_t out = row_ptr[i];
-    for (int base = 0; base <= i; base += 256) {
-        int j = base + threadIdx.x;
-        bool nr = false;
-        if (j <= i) {
-            double lj[3], hj[3];
-            for (int k = 0; k < 3; ++k) {
-                lj[k] = lo[3 * j + k];
-                hj[k] = hi[3 * j + k];
-            }
-            nr = is_near(li, hi_, di, lj, hj, diam2_of(lj, hj), eta2);
+    for (int g = 0; g < words; g += 64) {
+        const int w = g + lane;
+        uint64_t bits = w < words ? mask[(int64_t)i * nw + w] : 0ull;
+        const int pc = __popcll(bits);
+        int incl = pc;   // inclusive prefix over the lanes
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += t;
         }
-        uint64_t mask = __ballot(nr);
-        int before = __popcll(mask & ((1ull << lane) - 1ull));
-        if (lane == 0) wave_cnt[wave] = __popcll(mask);
-        __syncthreads();
-        int off = 0;
-        for (int w = 0; w < wave; ++w) off += wave_cnt[w];
-        if (nr) {
-            col[out + off + before] = j;
-            row[out + off + before] = i;
+        int64_t o = out + incl - pc;
+        while (bits) {
+            const int b = __ffsll((long long)bits) - 1;
+            bits &= bits - 1;
+            col[o] = 64 * w + b;
+            row[o] = i;
+            ++o;
         }
-        int tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
-        __syncthreads();
-        out += tot;
+        out += __shfl(incl, 63, 64);
     }
 }
-
-hipError_t launch_near_fill(const double *lo, const double *hi, int n, double eta2,
-                            const int64_t *row_ptr, int32_t *row, int32_t *col, hipStream_t s)
+hipError_t launch_near_fill(const uint64_t *mask, int n, const int64_t *row_ptr, int32_t *row, int32_t *col,
+                            hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(near_fill_kernel, dim3(n), dim3(256), 0, s, lo, hi, n, eta2, row_ptr, row, col);
+    hipLaunchKernelGGL(near_fill_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, mask, n, row_ptr, row, col);
     return hipGetLastError();
 }
-
 }  // namespace gbem

@@ -21,21 +21,46 @@ hipError_t launch_jacobi_scale(const double *A, int64_t lda, int npad, double *s
 }
 
 // F = S A S in FP32, lower triangle (column j = blockIdx.x, rows i >= j).
-__global__ void scale_convert_kernel(const double *__restrict__ A, int64_t lda,
-                                     const double *__restrict__ s, int npad, float *__restrict__ F,
-                                     int64_t ldf)
+// F = S A S (lower triangle) in FP32.  Workgroup: 1024 rows x 8 columns;
+// thread: 4 consecutive rows (one 32-byte load and one 16-byte store per
+// column).  npad is a multiple of 512 and lda, ldf multiples of 4, so every
+// access is aligned; threads whose rows all lie above the diagonal return.
+__global__ __launch_bounds__(256) void scale_convert_kernel(const double *__restrict__ A, int64_t lda,
+                                                            const double *__restrict__ s, int npad,
+                                                            float *__restrict__ F, int64_t ldf)
 {
-    const int j = blockIdx.x;
-    const int i = blockIdx.y * blockDim.x + threadIdx.x;
-    if (i >= npad || i < j) return;
-    F[i + (int64_t)j * ldf] = (float)(s[i] * A[i + (int64_t)j * lda] * s[j]);
+    typedef double d4_t __attribute__((ext_vector_type(4)));
+    typedef float f4_t __attribute__((ext_vector_type(4)));
+    const int j0 = blockIdx.x * 8;
+    const int i = blockIdx.y * 1024 + threadIdx.x * 4;
+    if (i >= npad || i + 3 < j0) return;   // rows past the matrix (npad need not divide by 1024) or above
+    const d4_t si = *reinterpret_cast<const d4_t *>(s + i);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int j = j0 + c;
+        if (i + 3 < j) break;   // the rest of this thread's rows lie above the diagonal
+        const d4_t a = *reinterpret_cast<const d4_t *>(A + i + (int64_t)j * lda);
+        const double sj = s[j];
+        f4_t f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) f[e] = (float)(si[e] * a[e] * sj);
+        float *dst = F + i + (int64_t)j * ldf;
+        if (i >= j) {
+            *reinterpret_cast<f4_t *>(dst) = f;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i + e >= j) dst[e] = f[e];
+        }
+    }
 }
 
 hipError_t launch_scale_convert(const double *A, int64_t lda, const double *s, int npad, float *F,
                                 int64_t ldf, hipStream_t st)
 {
-    hipLaunchKernelGGL(scale_convert_kernel, dim3(npad, (npad + 255) / 256), dim3(256), 0, st, A, lda,
-                       s, npad, F, ldf);
+    if (npad % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(scale_convert_kernel, dim3(npad / 8, (npad + 1023) / 1024), dim3(256), 0, st, A, lda, s, npad,
+                       F, ldf);
     return hipGetLastError();
 }
 
