@@ -49,11 +49,14 @@ struct GaussRule {
     float wwf[kMaxOrder * kMaxOrder];
 };
 
-// Gauss rule of the semi-analytic near-pair route (halved weights).
-constexpr int kNearOrder = 10;
+// Gauss rules of the semi-analytic near-pair route (halved weights): 10
+// points per axis, 8 for pairs at least two sides apart.
+constexpr int kNearOrder = 10, kNearOrderWide = 8;
 struct NearRule {
     double x[kNearOrder];
     double w[kNearOrder];
+    double x8[kNearOrderWide];
+    double w8[kNearOrderWide];
 };
 
 // Event-based per-class kernel timing (opts.profile).  start() records an

@@ -33,55 +33,67 @@ __device__ __forceinline__ bool is_near(const double *li, const double *hi_, dou
     return sep2 < eta2 * dm;
 }
 
-// One workgroup per row i; counts near j in [0, i] and keeps the test
-// results as bit masks: mask[i * nw + c] bit b <=> column 64 c + b is near
-// (nw = ceil(n / 64) words per row; words past i / 64 are not written).
+// Counts near j in [0, i] for every row i and keeps the test results as bit
+// masks: mask[i * nw + c] bit b <=> column 64 c + b is near (nw = ceil(n /
+// 64) words per row; words past i / 64 are not written).  Workgroup: 64 rows
+// x 256 columns of the lower triangle (grid: column blocks x row blocks;
+// blocks wholly above the diagonal return); a thread keeps its column's box
+// and diameter, the rows' come from LDS; each wave's ballot is one mask word,
+// its popcount goes to cnt[i] by an integer atomic (cnt zeroed first).
 __global__ __launch_bounds__(256) void near_count_kernel(const double *__restrict__ lo,
                                                          const double *__restrict__ hi, int n,
                                                          double eta2, int64_t *__restrict__ cnt,
                                                          uint64_t *__restrict__ mask)
 {
-    __shared__ int64_t red[4];
-    const int i = blockIdx.x;
-    double li[3], hi_[3];
-    for (int k = 0; k < 3; ++k) {
-        li[k] = lo[3 * i + k];
-        hi_[k] = hi[3 * i + k];
-    }
-    const double di = diam2_of(li, hi_);
-    const int64_t nw = (n + 63) / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t c = 0;
-    for (int base = 0; base <= i; base += 256) {   // uniform trip count: every lane reaches the ballot
-        const int j = base + threadIdx.x;
-        bool nr = false;
-        if (j <= i) {
-            double lj[3], hj[3];
-            for (int k = 0; k < 3; ++k) {
-                lj[k] = lo[3 * j + k];
-                hj[k] = hi[3 * j + k];
-            }
-            nr = is_near(li, hi_, di, lj, hj, diam2_of(lj, hj), eta2);
+    __shared__ double rl[64][3], rh[64][3], rd[64];
+    const int c0 = blockIdx.x * 256, i0 = blockIdx.y * 64;
+    if (c0 > i0 + 63) return;   // uniform
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rows = min(64, n - i0);
+    if (tid < rows) {
+        double l[3], h[3];
+        for (int k = 0; k < 3; ++k) {
+            l[k] = lo[3 * (i0 + tid) + k];
+            h[k] = hi[3 * (i0 + tid) + k];
+            rl[tid][k] = l[k];
+            rh[tid][k] = h[k];
         }
-        c += nr ? 1 : 0;
-        const uint64_t bits = __ballot(nr);
-        const int w0 = base + 64 * wave;   // first column of this wave's word
-        if (lane == 0 && w0 <= i) mask[(int64_t)i * nw + w0 / 64] = bits;
+        rd[tid] = diam2_of(l, h);
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    const int j = c0 + tid;
+    const bool colok = j < n;
+    double lj[3] = {0.0, 0.0, 0.0}, hj[3] = {0.0, 0.0, 0.0}, dj = 0.0;
+    if (colok) {
+        for (int k = 0; k < 3; ++k) {
+            lj[k] = lo[3 * j + k];
+            hj[k] = hi[3 * j + k];
+        }
+        dj = diam2_of(lj, hj);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) cnt[i] = red[0] + red[1] + red[2] + red[3];
+    const int64_t nw = (n + 63) / 64;
+    const int w0 = c0 + 64 * wave;   // first column of this wave's word
+    for (int r = 0; r < rows; ++r) {
+        const int i = i0 + r;
+        const double li[3] = {rl[r][0], rl[r][1], rl[r][2]}, hi_[3] = {rh[r][0], rh[r][1], rh[r][2]};
+        const bool nr = colok && j <= i && is_near(li, hi_, rd[r], lj, hj, dj, eta2);
+        const uint64_t bits = __ballot(nr);
+        if (lane == 0 && w0 <= i) {
+            mask[(int64_t)i * nw + w0 / 64] = bits;
+            if (bits) atomicAdd((unsigned long long *)(cnt + i), (unsigned long long)__popcll(bits));
+        }
+    }
 }
-
 hipError_t launch_near_count(const double *lo, const double *hi, int n, double eta2, int64_t *cnt,
                              uint64_t *mask, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(near_count_kernel, dim3(n), dim3(256), 0, s, lo, hi, n, eta2, cnt, mask);
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int64_t) * n, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(near_count_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)((n + 63) / 64)), dim3(256), 0,
+                       s, lo, hi, n, eta2, cnt, mask);
     return hipGetLastError();
 }
-
 // Exclusive scan of n counts into row_ptr[0..n] (single workgroup, in order).
 __global__ __launch_bounds__(1024) void scan_kernel(const int64_t *__restrict__ cnt, int n,
                                                     int64_t *__restrict__ row_ptr)
