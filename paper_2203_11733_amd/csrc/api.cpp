@@ -321,8 +321,21 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(hipEventRecord(ws.evrb, st), "hipEventRecord");
     GaussRule rule;
     gauss_legendre_rule(o.far_order, &rule);
+    // a low-precision factor works on F = S A S in FP32 (S = diag(A)^(-1/2)):
+    // S comes from the panels' self integrals up front, and the far and near
+    // passes write F beside A, so no pass over the finished A is needed
+    float *Fasm = nullptr;
+    const double *sasm = nullptr;
+    if (stop == Stop::kFull && o.factor_dtype != GBEM_F64) {
+        HIPCHK(ws.F.ensure((size_t)npad * npad * 4), "alloc F");
+        HIPCHK(ws.s.ensure((size_t)npad * 8), "alloc s");
+        HIPCHK(launch_self_scale(dlo, dhi, ws.pan.as<Panel>(), n, (int)npad, ws.s.as<double>(), st), "self scale");
+        Fasm = ws.F.as<float>();
+        sasm = ws.s.as<double>();
+    }
     tok = pf.start(st, GBEM_K_FAR);
-    HIPCHK(launch_far(ws.pan.as<Panel>(), n, (int)npad, o.far_order, rule, o.far_dtype, A, lda, st), "far");
+    HIPCHK(launch_far(ws.pan.as<Panel>(), n, (int)npad, o.far_order, rule, o.far_dtype, A, lda, st, Fasm, npad, sasm),
+           "far");
     {
         const double p2 = (double)o.far_order * o.far_order;
         // 11 flops per evaluation of w_a w_b / |x_a - y_b|: 3 differences, 5 for the
@@ -357,7 +370,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (n + 64) / 16.0 + (double)nnz * 8, st);
     tok = pf.start(st, GBEM_K_NEAR_EVAL);
     HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
-                            A, lda, ws.semi.as<int32_t>(), st), "near_eval");
+                            A, lda, ws.semi.as<int32_t>(), st, Fasm, npad, sasm), "near_eval");
     pf.stop(tok, GBEM_K_NEAR_EVAL, 0.0, (double)nnz * (2 * 8 + 2 * 4 + 2 * 48), st);
     HIPCHK(hipEventRecord(ws.ev[1], st), "hipEventRecord");
     if (rep) {
@@ -375,6 +388,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(hipMemsetAsync(ws.sync.err, 0, 4, st), "hipMemsetAsync");
     double *X = ws.X.as<double>();
     int dtype = o.factor_dtype;
+    bool f_ready = Fasm != nullptr;   // F = S A S written by the assembly (consumed by the first factor)
     int iters = 0;
     double resid = 0.0;
     for (;;) {   // fallback loop: a failed low-precision factor retries one level up
@@ -385,13 +399,17 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(hipMemsetAsync(flags + 1, 0, 4, st), "hipMemsetAsync");
         void *Fm = A;
         if (dtype != GBEM_F64) {
-            HIPCHK(ws.F.ensure((size_t)npad * npad * es), "alloc F");
-            HIPCHK(ws.s.ensure((size_t)npad * 8), "alloc s");
-            tok = pf.start(st, GBEM_K_OTHER);
-            HIPCHK(launch_jacobi_scale(A, lda, (int)npad, ws.s.as<double>(), st), "jacobi");
-            HIPCHK(launch_scale_convert(A, lda, ws.s.as<double>(), (int)npad, ws.F.as<float>(), npad, st),
-                   "scale_convert");
-            pf.stop(tok, GBEM_K_OTHER, 2.0 * (double)npad * npad / 2.0, (double)npad * npad / 2.0 * 12.0, st, 2);
+            if (!f_ready) {   // a retry: the failed factor overwrote F
+                HIPCHK(ws.F.ensure((size_t)npad * npad * es), "alloc F");
+                HIPCHK(ws.s.ensure((size_t)npad * 8), "alloc s");
+                tok = pf.start(st, GBEM_K_OTHER);
+                HIPCHK(launch_jacobi_scale(A, lda, (int)npad, ws.s.as<double>(), st), "jacobi");
+                HIPCHK(launch_scale_convert(A, lda, ws.s.as<double>(), (int)npad, ws.F.as<float>(), npad, st),
+                       "scale_convert");
+                pf.stop(tok, GBEM_K_OTHER, 2.0 * (double)npad * npad / 2.0, (double)npad * npad / 2.0 * 12.0, st,
+                        2);
+            }
+            f_ready = false;
             Fm = ws.F.p;
         }
         HIPCHK(ws.ensure_side(), "side stream");

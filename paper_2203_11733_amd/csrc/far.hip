@@ -119,13 +119,17 @@ __device__ __forceinline__ T far_pair(const Panel &pi, const Panel &pj, const Ga
     return acc;
 }
 
+// F != nullptr: also F[i + j ldf] = (float)(sc_i a_ij sc_j) for the lower tile
 template <int P, typename T>
 __global__ __launch_bounds__(256) void far_tile_kernel(const Panel *__restrict__ pan, int n,
                                                        int ntile, GaussRule g,
-                                                       double *__restrict__ A, int64_t lda)
+                                                       double *__restrict__ A, int64_t lda,
+                                                       float *__restrict__ F, int64_t ldf,
+                                                       const double *__restrict__ sc)
 {
     __shared__ Panel pj_s[kFarTile];
     __shared__ double tile[kFarTile][kFarTile + 1];
+    __shared__ double scj[kFarTile];   // column scales of F
 
     // lower-triangle tile (I, J), I >= J, from the linear block index
     const int64_t t = blockIdx.x;
@@ -142,6 +146,7 @@ __global__ __launch_bounds__(256) void far_tile_kernel(const Panel *__restrict__
     if (tid < kFarTile) {
         int j = j0 + tid;
         if (j < n) pj_s[tid] = pan[j];
+        if (F) scj[tid] = sc[j];   // j < npad
     }
     Panel pi;
     if (i < n) pi = pan[i];
@@ -163,10 +168,12 @@ __global__ __launch_bounds__(256) void far_tile_kernel(const Panel *__restrict__
     }
     __syncthreads();
     // lower tile (rows i, columns j)
+    const double si = F ? sc[i] : 0.0;
     for (int m = 0; m < kFarTile / 4; ++m) {
         const int jl = jg + 4 * m;
         double v = (I == J && jl > il) ? tile[jl][il] : tile[il][jl];
         A[(int64_t)(I * kFarTile + il) + (int64_t)(j0 + jl) * lda] = v;
+        if (F && (I != J || jl <= il)) F[(int64_t)i + (int64_t)(j0 + jl) * ldf] = (float)(si * v * scj[jl]);
     }
     // mirrored tile (rows j, columns i); the diagonal tile is already complete
     if (I != J) {
@@ -179,30 +186,37 @@ __global__ __launch_bounds__(256) void far_tile_kernel(const Panel *__restrict__
 
 template <typename T>
 static hipError_t launch_far_t(const Panel *pan, int n, int npad, int p, const GaussRule &g,
-                               double *A, int64_t lda, hipStream_t s)
+                               double *A, int64_t lda, hipStream_t s, float *F, int64_t ldf, const double *sc)
 {
     const int ntile = npad / kFarTile;
     const int64_t nblk = (int64_t)ntile * (ntile + 1) / 2;
     dim3 grid((unsigned)nblk), block(256);
+#define FAR_CASE(PP)                                                                                           \
+    case PP:                                                                                                   \
+        hipLaunchKernelGGL((far_tile_kernel<PP, T>), grid, block, 0, s, pan, n, ntile, g, A, lda, F, ldf, sc); \
+        break;
     switch (p) {
-    case 1: hipLaunchKernelGGL((far_tile_kernel<1, T>), grid, block, 0, s, pan, n, ntile, g, A, lda); break;
-    case 2: hipLaunchKernelGGL((far_tile_kernel<2, T>), grid, block, 0, s, pan, n, ntile, g, A, lda); break;
-    case 3: hipLaunchKernelGGL((far_tile_kernel<3, T>), grid, block, 0, s, pan, n, ntile, g, A, lda); break;
-    case 4: hipLaunchKernelGGL((far_tile_kernel<4, T>), grid, block, 0, s, pan, n, ntile, g, A, lda); break;
-    case 5: hipLaunchKernelGGL((far_tile_kernel<5, T>), grid, block, 0, s, pan, n, ntile, g, A, lda); break;
-    case 6: hipLaunchKernelGGL((far_tile_kernel<6, T>), grid, block, 0, s, pan, n, ntile, g, A, lda); break;
-    case 8: hipLaunchKernelGGL((far_tile_kernel<8, T>), grid, block, 0, s, pan, n, ntile, g, A, lda); break;
+    FAR_CASE(1)
+    FAR_CASE(2)
+    FAR_CASE(3)
+    FAR_CASE(4)
+    FAR_CASE(5)
+    FAR_CASE(6)
+    FAR_CASE(8)
     default: return hipErrorInvalidValue;
     }
+#undef FAR_CASE
     return hipGetLastError();
 }
 
 hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule &rule,
-                      int far_dtype, double *A, int64_t lda, hipStream_t s)
+                      int far_dtype, double *A, int64_t lda, hipStream_t s, float *F, int64_t ldf,
+                      const double *sc)
 {
     if (npad % kFarTile) return hipErrorInvalidValue;
-    if (far_dtype == GBEM_F32) return launch_far_t<float>(pan, n, npad, p, rule, A, lda, s);
-    return launch_far_t<double>(pan, n, npad, p, rule, A, lda, s);
+    if ((F == nullptr) != (sc == nullptr)) return hipErrorInvalidValue;
+    if (far_dtype == GBEM_F32) return launch_far_t<float>(pan, n, npad, p, rule, A, lda, s, F, ldf, sc);
+    return launch_far_t<double>(pan, n, npad, p, rule, A, lda, s, F, ldf, sc);
 }
 
 }  // namespace gbem

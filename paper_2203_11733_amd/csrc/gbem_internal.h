@@ -146,14 +146,24 @@ hipError_t launch_near_fill(const uint64_t *mask, int n, const int64_t *row_ptr,
 
 // near_eval.hip: closed-form Galerkin integrals of the near pairs.
 // semi_buf: near_semi_bytes(nnz) bytes of scratch (queue of semi-analytic pairs)
+// F, sc (optional, together): also F[i + j ldf] = (float)(sc_i a_ij sc_j) for
+// the near pairs (j <= i), the scaled FP32 copy the mixed-precision factor uses
 hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
                             const int32_t *row, const int32_t *col, int64_t nnz, double *A,
-                            int64_t lda, int32_t *semi_buf, hipStream_t s);
+                            int64_t lda, int32_t *semi_buf, hipStream_t s, float *F = nullptr,
+                            int64_t ldf = 0, const double *sc = nullptr);
+// sc[i] = a_ii^(-1/2) from the self integrals of the panels (the values the
+// near pass writes on the diagonal), 1 for the padding rows [n, npad)
+hipError_t launch_self_scale(const double *lo, const double *hi, const Panel *pan, int n, int npad, double *sc,
+                             hipStream_t s);
 inline size_t near_semi_bytes(int64_t nnz) { return (size_t)(64 + nnz) * sizeof(int32_t); }
 
 // far.hip
+// F, sc (optional, together): also the scaled FP32 lower triangle (see
+// launch_near_eval); near entries are overwritten by the near pass
 hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule &rule,
-                      int far_dtype, double *A, int64_t lda, hipStream_t s);
+                      int far_dtype, double *A, int64_t lda, hipStream_t s, float *F = nullptr,
+                      int64_t ldf = 0, const double *sc = nullptr);
 
 // chol.hip
 // side: second stream for the look-ahead panel factorisation; ev: event pool

@@ -191,7 +191,8 @@ __global__ __launch_bounds__(256) void near_eval_kernel(const double *__restrict
                                                         const int32_t *__restrict__ col,
                                                         int64_t nnz, double *__restrict__ A,
                                                         int64_t lda, int32_t *__restrict__ semi_list,
-                                                        int32_t *__restrict__ semi_count)
+                                                        int32_t *__restrict__ semi_count, float *__restrict__ F,
+                                                        int64_t ldf, const double *__restrict__ sc)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = t < nnz;
@@ -222,6 +223,7 @@ __global__ __launch_bounds__(256) void near_eval_kernel(const double *__restrict
     const double a = G / (4.0 * M_PI * pan[i].area * pan[j].area);
     A[i + j * lda] = a;
     A[j + i * lda] = a;
+    if (F) F[i + j * ldf] = (float)(sc[i] * a * sc[j]);   // j <= i
 }
 
 // Pass 2: one wave per queued pair.  The 100 (or 64) Gauss points x 4 corners
@@ -234,7 +236,8 @@ __global__ __launch_bounds__(256) void near_semi_kernel(const double *__restrict
                                                         const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ semi_list,
                                                         const int32_t *__restrict__ semi_count,
-                                                        double *__restrict__ A, int64_t lda)
+                                                        double *__restrict__ A, int64_t lda, float *__restrict__ F,
+                                                        int64_t ldf, const double *__restrict__ sc)
 {
     const int lane = threadIdx.x & 63;
     const int nwaves = gridDim.x * (blockDim.x >> 6);
@@ -289,14 +292,49 @@ __global__ __launch_bounds__(256) void near_semi_kernel(const double *__restrict
             const double a = acc * (4.0 * h1 * h2) / (4.0 * M_PI * pan[i].area * pan[j].area);
             A[i + j * lda] = a;
             A[j + i * lda] = a;
+            if (F) F[i + j * ldf] = (float)(sc[i] * a * sc[j]);   // j <= i
         }
     }
 }
 
+// sc[i] = a_ii^(-1/2): the same closed form and expression as near_eval_kernel
+// for the pair (i, i) (diagonal pairs are near and never semi-analytic: their
+// gap is 0), so the value matches the diagonal the near pass writes.
+__global__ __launch_bounds__(256) void self_scale_kernel(const double *__restrict__ lo,
+                                                         const double *__restrict__ hi,
+                                                         const Panel *__restrict__ pan, int n, int npad,
+                                                         double *__restrict__ sc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    if (i >= n) {
+        sc[i] = 1.0;   // identity padding
+        return;
+    }
+    double li[3], hi_[3];
+    for (int k = 0; k < 3; ++k) {
+        li[k] = lo[3 * i + k];
+        hi_[k] = hi[3 * i + k];
+    }
+    const double G = pair_integral_closed(li, hi_, pan[i].nrm, li, hi_, pan[i].nrm);
+    const double a = G / (4.0 * M_PI * pan[i].area * pan[i].area);
+    sc[i] = 1.0 / sqrt(a);
+}
+
+hipError_t launch_self_scale(const double *lo, const double *hi, const Panel *pan, int n, int npad, double *sc,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(self_scale_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, lo, hi, pan, n,
+                       npad, sc);
+    return hipGetLastError();
+}
+
 hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
                             const int32_t *row, const int32_t *col, int64_t nnz, double *A,
-                            int64_t lda, int32_t *semi_buf, hipStream_t s)
+                            int64_t lda, int32_t *semi_buf, hipStream_t s, float *F, int64_t ldf,
+                            const double *sc)
 {
+    if ((F == nullptr) != (sc == nullptr)) return hipErrorInvalidValue;
     if (nnz <= 0) return hipSuccess;
     NearRule g;
     gauss_legendre(kNearOrder, g.x, g.w);
@@ -307,10 +345,10 @@ hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan
     e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(near_eval_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, lo, hi,
-                       pan, row, col, nnz, A, lda, list, count);
+                       pan, row, col, nnz, A, lda, list, count, F, ldf, sc);
     const int64_t waves = std::min<int64_t>(nnz, 4096);
     hipLaunchKernelGGL(near_semi_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, lo, hi, pan, row, col,
-                       list, count, A, lda);
+                       list, count, A, lda, F, ldf, sc);
     return hipGetLastError();
 }
 

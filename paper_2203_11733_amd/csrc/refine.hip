@@ -20,7 +20,6 @@ hipError_t launch_jacobi_scale(const double *A, int64_t lda, int npad, double *s
     return hipGetLastError();
 }
 
-// F = S A S in FP32, lower triangle (column j = blockIdx.x, rows i >= j).
 // F = S A S (lower triangle) in FP32.  Workgroup: 1024 rows x 8 columns;
 // thread: 4 consecutive rows (one 32-byte load and one 16-byte store per
 // column).  npad is a multiple of 512 and lda, ldf multiples of 4, so every
