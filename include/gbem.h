@@ -248,6 +248,15 @@ gbem_status gbem_assemble(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts 
  * entries out[k] = A[ii[k], jj[k]] (host arrays). */
 gbem_status gbem_assemble_sample(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
                                  int64_t m, const int32_t *ii, const int32_t *jj, double *out);
+/* Input of a low-precision factorisation (the Cholesky factorisation of
+ * section 3.2, applied to the Jacobi-scaled system): F = S A S in FP32 with
+ * S = diag(A)^(-1/2), which the far and near assembly passes write beside A.
+ * Assembles with the same launches as gbem_extract and returns m sampled
+ * entries out[k] = F[ii[k], jj[k]] (host arrays; F holds the lower triangle,
+ * so 0 <= jj[k] <= ii[k] < n_panels).  GBEM_EINVAL when opts->factor_dtype
+ * is GBEM_F64 (no scaled copy is made) or an index is out of range. */
+gbem_status gbem_assemble_scaled_sample(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                        int64_t m, const int32_t *ii, const int32_t *jj, float *out);
 /* In-place Cholesky A = L L^T of a device matrix (column-major, lower
  * triangle referenced, leading dimension lda >= n).  dtype GBEM_F64 takes
  * double*, GBEM_F32/F16/BF16 take float* (F16/BF16 = FP32 storage with 16-bit

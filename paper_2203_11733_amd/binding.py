@@ -25,8 +25,8 @@ EXPORTS = [
     "gbem_version", "gbem_status_str", "gbem_last_error", "gbem_default_opts", "gbem_create",
     "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit", "gbem_poll", "gbem_wait",
     "gbem_job_free", "gbem_server_stats", "gbem_mesh_boxes", "gbem_mesh_buf_free", "gbem_near_list",
-    "gbem_assemble", "gbem_assemble_sample", "gbem_cholesky_device", "gbem_cholesky_solve_device",
-    "gbem_mesh_partition", "gbem_extract_partitioned",
+    "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
+    "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
 ]
 
 
@@ -129,13 +129,15 @@ def load():
     lib.gbem_assemble.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp]
     lib.gbem_assemble_sample.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), ctypes.c_int64,
                                          _vp, _vp, _vp]
+    lib.gbem_assemble_scaled_sample.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), ctypes.c_int64,
+                                                _vp, _vp, _vp]
     lib.gbem_cholesky_device.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_int32), _vp]
     lib.gbem_cholesky_solve_device.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
                                                ctypes.c_int32, _vp, ctypes.c_int64, _vp]
     for name in ("gbem_create", "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit",
                  "gbem_poll", "gbem_wait", "gbem_server_stats", "gbem_mesh_boxes", "gbem_near_list",
-                 "gbem_assemble", "gbem_assemble_sample", "gbem_cholesky_device",
+                 "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
                  "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
@@ -325,6 +327,17 @@ class Context:
         o = opts or make_opts()
         _check(self.lib.gbem_assemble_sample(self.h, ctypes.byref(m), ctypes.byref(o), ii.shape[0], _ptr(ii),
                                              _ptr(jj), _ptr(out)))
+        return out
+
+    def assemble_scaled_sample(self, lo, hi, ii, jj, opts: Opts):
+        """Sampled entries F[ii, jj] (ii >= jj) of the FP32 factor input S A S."""
+        n = np.asarray(lo).shape[0]
+        m, keep = self._mesh(lo, hi, np.zeros(n, dtype=np.int32), 1, 1.0, 1.0)
+        ii = np.ascontiguousarray(ii, dtype=np.int32)
+        jj = np.ascontiguousarray(jj, dtype=np.int32)
+        out = np.zeros(ii.shape[0], dtype=np.float32)
+        _check(self.lib.gbem_assemble_scaled_sample(self.h, ctypes.byref(m), ctypes.byref(opts), ii.shape[0],
+                                                    _ptr(ii), _ptr(jj), _ptr(out)))
         return out
 
     def cholesky_device(self, A, dtype="f64", stream=None):

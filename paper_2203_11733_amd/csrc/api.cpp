@@ -262,7 +262,9 @@ struct Timing {
     float assemble = 0, factor = 0, solve = 0, total = 0;
 };
 
-enum class Stop { kAssembled, kFull };
+// kAssembled: A only; kScaled: A and the FP32 factor input F (low-precision
+// factor); kFull: the whole extraction
+enum class Stop { kAssembled, kScaled, kFull };
 
 // The extraction pipeline on one stream and workspace.  Mesh arrays and C
 // are device pointers.
@@ -326,7 +328,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     // passes write F beside A, so no pass over the finished A is needed
     float *Fasm = nullptr;
     const double *sasm = nullptr;
-    if (stop == Stop::kFull && o.factor_dtype != GBEM_F64) {
+    if (stop != Stop::kAssembled && o.factor_dtype != GBEM_F64) {
         HIPCHK(ws.F.ensure((size_t)npad * npad * 4), "alloc F");
         HIPCHK(ws.s.ensure((size_t)npad * 8), "alloc s");
         HIPCHK(launch_self_scale(dlo, dhi, ws.pan.as<Panel>(), n, (int)npad, ws.s.as<double>(), st), "self scale");
@@ -377,7 +379,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         rep->n_near = nnz;
         rep->n_panels = n;
     }
-    if (stop == Stop::kAssembled) {
+    if (stop != Stop::kFull) {
         HIPCHK(hipStreamSynchronize(st), "hipStreamSynchronize");
         pf.collect(rep);
         return GBEM_OK;
@@ -1027,7 +1029,8 @@ extern "C" gbem_status gbem_near_list(gbem_ctx *ctx, const gbem_mesh *mesh, doub
     return GBEM_OK;
 }
 
-static gbem_status assemble_common(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, gbem_report *r)
+static gbem_status assemble_common(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, gbem_report *r,
+                                   Stop stop = Stop::kAssembled)
 {
     gbem_opts o;
     gbem_status s = check_args(ctx, mesh, opts, o);
@@ -1036,7 +1039,7 @@ static gbem_status assemble_common(gbem_ctx *ctx, const gbem_mesh *mesh, const g
     if ((s = upload_mesh(ctx, mesh)) != GBEM_OK) return s;
     return run_pipeline(ctx->ws, ctx->stream, mesh->n_panels, mesh->n_conductors, ctx->ws.lo.as<double>(),
                         ctx->ws.hi.as<double>(), ctx->ws.cond.as<int32_t>(), mesh->eps_r, mesh->length_unit_m, o,
-                        nullptr, r, Stop::kAssembled);
+                        nullptr, r, stop);
 }
 
 extern "C" gbem_status gbem_assemble(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, double *A_out)
@@ -1086,6 +1089,46 @@ extern "C" gbem_status gbem_assemble_sample(gbem_ctx *ctx, const gbem_mesh *mesh
     HIPCHK(launch_gather(ws.A.as<double>(), round_up(n, kPad), di.as<int32_t>(), dj.as<int32_t>(), m,
                          dout.as<double>(), ctx->stream), "gather");
     HIPCHK(hipMemcpyAsync(out, dout.p, sizeof(double) * m, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
+    di.release();
+    dj.release();
+    dout.release();
+    return GBEM_OK;
+}
+
+// m sampled entries of the FP32 factor input F = S A S written by the
+// assembly passes (lower triangle: ii[k] >= jj[k])
+extern "C" gbem_status gbem_assemble_scaled_sample(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                                   int64_t m, const int32_t *ii, const int32_t *jj, float *out)
+{
+    if (!ctx || !opts || m < 0 || (m > 0 && (!ii || !jj || !out))) {
+        set_error("gbem_assemble_scaled_sample: bad arguments");
+        return GBEM_EINVAL;
+    }
+    if (opts->factor_dtype == GBEM_F64) {
+        set_error("gbem_assemble_scaled_sample: an FP64 factor has no scaled FP32 copy");
+        return GBEM_EINVAL;
+    }
+    const int n = mesh ? mesh->n_panels : 0;
+    for (int64_t k = 0; k < m; ++k)
+        if (jj[k] < 0 || ii[k] < jj[k] || ii[k] >= n) {
+            set_error("gbem_assemble_scaled_sample: index out of range or above the diagonal");
+            return GBEM_EINVAL;
+        }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    gbem_report r{};
+    gbem_status s = assemble_common(ctx, mesh, opts, &r, Stop::kScaled);
+    if (s != GBEM_OK || m == 0) return s;
+    Workspace &ws = ctx->ws;
+    DevBuf di, dj, dout;
+    HIPCHK(di.ensure(sizeof(int32_t) * m), "alloc");
+    HIPCHK(dj.ensure(sizeof(int32_t) * m), "alloc");
+    HIPCHK(dout.ensure(sizeof(float) * m), "alloc");
+    HIPCHK(hipMemcpyAsync(di.p, ii, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream), "H2D");
+    HIPCHK(hipMemcpyAsync(dj.p, jj, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream), "H2D");
+    HIPCHK(launch_gather(ws.F.as<float>(), round_up(n, kPad), di.as<int32_t>(), dj.as<int32_t>(), m,
+                         dout.as<float>(), ctx->stream), "gather");
+    HIPCHK(hipMemcpyAsync(out, dout.p, sizeof(float) * m, hipMemcpyDeviceToHost, ctx->stream), "D2H");
     HIPCHK(hipStreamSynchronize(ctx->stream), "sync");
     di.release();
     dj.release();

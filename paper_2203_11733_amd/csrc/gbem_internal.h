@@ -133,6 +133,8 @@ hipError_t launch_charge_finish(const double *partial, int nchunks, int m, doubl
                                 double *C, hipStream_t s);
 hipError_t launch_gather(const double *A, int64_t lda, const int32_t *ii, const int32_t *jj, int64_t m,
                          double *out, hipStream_t s);
+hipError_t launch_gather(const float *A, int64_t lda, const int32_t *ii, const int32_t *jj, int64_t m, float *out,
+                         hipStream_t s);
 hipError_t launch_identity_pad(void *A, int64_t lda, int n, int npad, bool f64, hipStream_t s);
 
 // near.hip (compiled with -ffp-contract=off: the near/far test is bit-exact)

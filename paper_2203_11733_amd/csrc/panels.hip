@@ -157,19 +157,31 @@ hipError_t launch_identity_pad(void *A, int64_t lda, int n, int npad, bool f64, 
 }
 
 // out[k] = A[ii[k], jj[k]] (indices validated on the host)
-__global__ void gather_kernel(const double *__restrict__ A, int64_t lda, const int32_t *__restrict__ ii,
-                              const int32_t *__restrict__ jj, int64_t m, double *__restrict__ out)
+template <typename T>
+__global__ void gather_kernel(const T *__restrict__ A, int64_t lda, const int32_t *__restrict__ ii,
+                              const int32_t *__restrict__ jj, int64_t m, T *__restrict__ out)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < m) out[k] = A[ii[k] + (int64_t)jj[k] * lda];
 }
 
+template <typename T>
+static hipError_t gather(const T *A, int64_t lda, const int32_t *ii, const int32_t *jj, int64_t m, T *out,
+                         hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_kernel<T>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A, lda, ii, jj, m, out);
+    return hipGetLastError();
+}
 hipError_t launch_gather(const double *A, int64_t lda, const int32_t *ii, const int32_t *jj, int64_t m,
                          double *out, hipStream_t s)
 {
-    if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A, lda, ii, jj, m, out);
-    return hipGetLastError();
+    return gather(A, lda, ii, jj, m, out, s);
+}
+hipError_t launch_gather(const float *A, int64_t lda, const int32_t *ii, const int32_t *jj, int64_t m, float *out,
+                         hipStream_t s)
+{
+    return gather(A, lda, ii, jj, m, out, s);
 }
 
 }  // namespace gbem

@@ -186,6 +186,59 @@ def test_matrix_orders_and_thresholds(ctx, p, eta):
     assert (np.abs(A - Ao) / np.abs(Ao)).max() < ENTRY_TOL
 
 
+# ------------------------------------------------- scaled FP32 factor input
+# F = S A S, S = diag(A)^(-1/2), rounded once to FP32: within one FP32 ulp
+# (2^-23 relative) of the oracle's FP64 value when the far field is FP64;
+# FP32 far sums add the far-entry bar of A (2e-6).
+F_TOL = {"f64": 2.0 ** -23, "f32": 2e-6 + 2.0 ** -23}
+
+
+def scaled_ref(lo, hi, ii, jj, p=3, eta=2.0):
+    d = np.unique(np.concatenate([ii, jj]))
+    sd = np.zeros(lo.shape[0])
+    sd[d] = 1.0 / np.sqrt(oracle.entries(lo, hi, d, d, p, eta))
+    return sd[ii] * oracle.entries(lo, hi, ii, jj, p, eta) * sd[jj]
+
+
+def check_scaled(ctx, lo, hi, ii, jj, far, factor="f16"):
+    got = ctx.assemble_scaled_sample(lo, hi, ii, jj, binding.make_opts(3, 2.0, far, factor))
+    ref = scaled_ref(lo, hi, ii, jj)
+    err = np.abs(got.astype(np.float64) - ref) / np.abs(ref)
+    diag = ii == jj
+    say(f"  far {far} factor {factor}: {ii.shape[0]} entries, max rel err {err.max():.3e}, "
+        f"diagonal max |F_ii - 1| {np.abs(got[diag] - 1.0).max() if diag.any() else 0:.3e}")
+    assert err.max() <= F_TOL[far]
+    assert np.all(np.abs(got[diag].astype(np.float64) - 1.0) <= 2.0 ** -23)
+
+
+@pytest.mark.parametrize("layout", [gi.two_plates(), gi.random_small_layout(5)], ids=["two_plates", "random5"])
+@pytest.mark.parametrize("far", ["f64", "f32"])
+def test_scaled_copy_all_entries(ctx, layout, far):
+    """Every lower entry of F (480 and 214 panels: several far tiles, ragged tails)."""
+    lo, hi, cond = mesh(layout)
+    say(f"scaled copy {layout.name} N={lo.shape[0]}")
+    ii, jj = np.tril_indices(lo.shape[0])
+    check_scaled(ctx, lo, hi, ii.astype(np.int32), jj.astype(np.int32), far)
+
+
+@pytest.mark.parametrize("factor", ["f32", "bf16"])
+def test_scaled_copy_factor_dtypes(ctx, factor):
+    lo, hi, cond = mesh(gi.crossing_bars_in_box())
+    rng = np.random.default_rng(11)
+    ii, jj = _sample_pairs(lo, hi, 2.0, rng, 2000)
+    ii, jj = np.maximum(ii, jj), np.minimum(ii, jj)
+    check_scaled(ctx, lo, hi, ii, jj, "f32", factor)
+
+
+def test_scaled_copy_rejects_bad_requests(ctx):
+    lo, hi, cond = mesh(gi.two_plates())
+    one = np.array([1], np.int32)
+    with pytest.raises(binding.GbemError):   # an FP64 factor makes no scaled copy
+        ctx.assemble_scaled_sample(lo, hi, one, one, binding.make_opts(3, 2.0, "f32", "f64"))
+    with pytest.raises(binding.GbemError):   # above the diagonal
+        ctx.assemble_scaled_sample(lo, hi, np.array([0], np.int32), one, binding.make_opts(3, 2.0, "f32", "f16"))
+
+
 # ---------------------------------------------------------------- capacitance
 def test_capacitance_f64_vs_oracle_two_plates(ctx):
     lay = gi.two_plates()
@@ -322,6 +375,17 @@ def test_full_size_matrix_samples(ctx, layout):
     sym = ctx.assemble_sample(lo, hi, jj, ii, binding.make_opts(3, 2.0, "f64"))
     got = ctx.assemble_sample(lo, hi, ii, jj, binding.make_opts(3, 2.0, "f64"))
     assert np.array_equal(sym, got)
+
+
+def test_full_size_scaled_copy_samples(ctx):
+    """F at the crossing bus's full size, in the mixed mode the bench times."""
+    lo, hi, cond = mesh(gi.crossing_bus())
+    say(f"full-size scaled copy crossing_bus N={lo.shape[0]}")
+    rng = np.random.default_rng(5)
+    ii, jj = _sample_pairs(lo, hi, 2.0, rng)
+    ii, jj = np.maximum(ii, jj), np.minimum(ii, jj)
+    d = rng.integers(0, lo.shape[0], 200).astype(np.int32)
+    check_scaled(ctx, lo, hi, np.concatenate([ii, d]), np.concatenate([jj, d]), "f32")
 
 
 def test_full_size_crossing_bus_capacitance(ctx):
