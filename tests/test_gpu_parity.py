@@ -123,6 +123,65 @@ def test_cholesky_solve_f32_storage(ctx, n, r):
     assert rel_err(X, np.linalg.solve(L64 @ L64.T, B0)) < 2e-5
 
 
+# Order 16,500 (padded to 16,896): 512-wide outer panels with look-ahead and
+# a ragged last block, as in the full-size extractions.  Elementwise backward
+# error of the factor, |L L^T - A| <= g |L| |L^T| (Higham, Thm 10.3:
+# g = (n+1)u; inputs rounded to FP32 add u32, 16-bit trailing-update
+# operands add about 2 u16), and of the two triangular solves with it,
+# |L L^T X - B| <= 3 (n+1) u |L| |L^T| |X|.
+LARGE_N = 16500
+U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.fixture(scope="module")
+def large_spd(gpu_lib):
+    import torch
+    n = LARGE_N
+    g = torch.Generator(device="cuda").manual_seed(n)
+    M = torch.randn((n, n), generator=g, dtype=torch.float64, device="cuda")
+    A = M @ M.T.contiguous()
+    del M
+    A = torch.tril(A) / n
+    A = A + torch.tril(A, -1).T + torch.eye(n, dtype=torch.float64, device="cuda")   # exactly symmetric
+    return A, g
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
+def test_cholesky_large_order_backward_error(ctx, large_spd, dtype):
+    import torch
+    A, g = large_spd
+    n = LARGE_N
+    say(f"cholesky {dtype} n={n}")
+    T = A.clone() if dtype == "f64" else A.float()
+    assert ctx.cholesky_device(T, dtype) == 0
+    L = torch.tril(T.T).double()              # T holds the column-major factor
+    assert bool((torch.diagonal(L) > 0).all())
+    Lab = L.abs()
+    bound = torch.tril(Lab @ Lab.T.contiguous())
+    err = torch.tril(L @ L.T.contiguous() - A).abs()
+    if dtype == "f64":
+        gam = (n + 1) * U["f64"]
+    else:
+        gam = (n + 2) * U["f32"] + (2.1 * U[dtype] if dtype in ("f16", "bf16") else 0.0)
+    ratio = float((err / bound.clamp_min(1e-300)).max())
+    say(f"  max |LL^T - A| / (|L||L^T|) = {ratio:.3e} (bound {gam:.3e})")
+    assert ratio <= gam
+    del err, bound
+    if dtype not in ("f64", "f32"):
+        return
+    r = 10
+    Bt = torch.randn((r, n), generator=g, dtype=torch.float64, device="cuda")   # column-major n x r
+    B0 = Bt.T.clone()
+    ctx.cholesky_solve_device(T.T, Bt.T, dtype)
+    X = Bt.T
+    res = (L @ (L.T.contiguous() @ X) - B0).abs()
+    bound = Lab @ (Lab.T.contiguous() @ X.abs())
+    gs = 3 * (n + 1) * U[dtype]
+    ratio = float((res / bound).max())
+    say(f"  solve: max |LL^T X - B| / (|L||L^T||X|) = {ratio:.3e} (bound {gs:.3e})")
+    assert ratio <= gs
+
+
 def test_cholesky_reports_indefinite(ctx):
     import torch
     n = 200
