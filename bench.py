@@ -121,18 +121,33 @@ def layout_of(name):
             "two_plates": gi.two_plates, "crossing_bars_in_box": gi.crossing_bars_in_box}[name]()
 
 
-def cpu_baseline(lo, hi, cond, layout, p, eta):
-    """Time the CPU oracle on a bounded sample and scale to whole extractions.
+FULL_ORACLE_MAX_N = 25000   # whole oracle extractions up to this order take ~10-30 s on 16 cores
 
-    Sample: all matrix entries of 1 % of the rows (chosen at random) through the
-    oracle's assembly (near pairs by the section 3.4 reductions, far pairs by
-    Gauss), plus a LAPACK Cholesky solve of an (N/2)-order matrix; the whole
-    extraction time is estimated as pairs / (pairs/s of the sample) + 8 x the
-    half-order Cholesky time."""
+
+def cpu_baseline(lo, hi, cond, layout, p, eta):
+    """Time the CPU oracle on the workload (or a bounded sample of it).
+
+    Up to FULL_ORACLE_MAX_N panels the oracle runs the whole extraction: every
+    matrix entry (near pairs by the section 3.4 reductions, far pairs by
+    Gauss), the LAPACK Cholesky solve and the charge sums; its capacitance
+    matrix is returned beside the timing.  Larger meshes: all entries of 1 %
+    of the rows (chosen at random) plus a LAPACK Cholesky solve of an
+    (N/2)-order matrix, the extraction time estimated as pairs / (pairs/s of
+    the sample) + 8 x the half-order solve time."""
     import numpy as np
 
     import oracle
     n = lo.shape[0]
+    total_pairs = n * (n + 1) / 2
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if n <= FULL_ORACLE_MAX_N:
+        t0 = time.perf_counter()
+        C = oracle.extract_panels(lo, hi, cond, layout.n_conductors, layout.eps_r, layout.length_unit_m, p, eta)
+        t = time.perf_counter() - t0
+        return {"value": total_pairs / t, "unit": "panel-pair integrals/s", "cores": threads, "kind": "oracle",
+                "sample": f"the whole oracle extraction of this workload ({total_pairs:.0f} entries, LAPACK "
+                          f"Cholesky solve of order {n}, charge sums): {t:.1f} s",
+                "extractions_per_s": 1.0 / t}, C
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(n, max(1, n // 100), replace=False))
     ii = np.concatenate([np.full(r + 1, r, np.int32) for r in rows])
@@ -151,15 +166,13 @@ def cpu_baseline(lo, hi, cond, layout, p, eta):
     t0 = time.perf_counter()
     oracle.solve(M, B)
     t_chol_half = time.perf_counter() - t0
-    total_pairs = n * (n + 1) / 2
     t_est = total_pairs / pairs_per_s + 8.0 * t_chol_half
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": total_pairs / t_est, "unit": "panel-pair integrals/s", "cores": threads,
             "kind": "oracle",
             "sample": f"oracle assembly of {len(rows)} random rows ({ii.shape[0]} entries, {t_asm:.1f} s) + "
                       f"LAPACK Cholesky solve of order {h} ({t_chol_half:.1f} s) scaled by 8 to order {n}; "
                       f"estimated {t_est:.1f} s per extraction",
-            "extractions_per_s": 1.0 / t_est}
+            "extractions_per_s": 1.0 / t_est}, None
 
 
 def serving(args, binding, np):
@@ -505,7 +518,12 @@ def main():
         out["copy_calibration_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(lo, hi, cond, lay, args.p, args.eta)
+        out["cpu_baseline"], C_or = cpu_baseline(lo, hi, cond, lay, args.p, args.eta)
+        if C_or is not None:
+            # the whole extraction against the oracle's, at the workload's full size
+            out["C_rel_err_vs_oracle"] = {
+                args.mode: float(np.abs(C - C_or).max() / np.abs(C_or).max()),
+                "f64": float(np.abs(C64 - C_or).max() / np.abs(C_or).max())}
     ctx.close()
     print(json.dumps(out))
 

@@ -466,3 +466,9 @@ def test_full_size_crossing_bus_capacitance(ctx):
     err = rel_err(Cm, C64)
     say(f"  mixed vs f64 rel err {err:.3e}")
     assert err < 1e-3
+    # the whole oracle extraction at this size (about 12 s on 16 host cores)
+    Co = oracle.extract_panels(lo, hi, cond, 10, lay.eps_r, lay.length_unit_m, 3, 2.0)
+    e64, em = rel_err(C64, Co), rel_err(Cm, Co)
+    say(f"  vs oracle: f64 {e64:.3e}, mixed {em:.3e}")
+    assert e64 < 1e-10
+    assert em < 1e-3
