@@ -472,3 +472,24 @@ def test_full_size_crossing_bus_capacitance(ctx):
     say(f"  vs oracle: f64 {e64:.3e}, mixed {em:.3e}")
     assert e64 < 1e-10
     assert em < 1e-3
+
+
+def test_full_size_three_layer_bus_capacitance(ctx):
+    """N = 59,904, M = 48 (the oracle's whole extraction would take minutes
+    here): Maxwell invariants in both modes and mixed vs FP64 within 1e-3."""
+    lay = gi.three_layer_bus()
+    lo, hi, cond = mesh(lay)
+    m = lay.n_conductors
+    say(f"full-size extract three_layer_bus N={lo.shape[0]} M={m}")
+    C64, r64 = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, binding.make_opts())
+    say(f"  f64 report {r64}")
+    Cm, rm = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, binding.make_opts(3, 2.0, "f32", "f16"))
+    say(f"  mixed report {rm}")
+    for C in (C64, Cm):
+        assert np.abs(C - C.T).max() <= 1e-6 * np.abs(C).max()
+        assert np.all(np.diag(C) > 0)
+        assert np.all(C[~np.eye(m, dtype=bool)] < 0)
+        assert np.all(C.sum(1) > 0)
+    err = rel_err(Cm, C64)
+    say(f"  mixed vs f64 rel err {err:.3e}")
+    assert err < 1e-3
