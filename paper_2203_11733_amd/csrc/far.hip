@@ -41,6 +41,15 @@ template <> __device__ __forceinline__ double rsqrt_t<double>(double x)
     return y;
 }
 
+// fused multiply-add in the arithmetic type itself (the plain builtin is the
+// double one and would widen FP32 operands)
+template <typename T> __device__ __forceinline__ T fma_t(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fma_t<double>(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
+}
+
 template <typename T> __device__ __forceinline__ T node(const GaussRule &g, int a);
 template <> __device__ __forceinline__ float node<float>(const GaussRule &g, int a) { return g.xf[a]; }
 template <> __device__ __forceinline__ double node<double>(const GaussRule &g, int a) { return g.x[a]; }
@@ -113,8 +122,8 @@ __device__ __forceinline__ T far_pair(const Panel &pi, const Panel &pj, const Ga
             for (int c = 0; c < P; ++c)
 #pragma unroll
                 for (int d = 0; d < P; ++d)
-                    in = __builtin_fma(wprod<T>(g, c * P + d), rsqrt_t<T>(s1 + S2[c * P + d]), in);
-            acc = __builtin_fma(wprod<T>(g, a * P + b), in, acc);
+                    in = fma_t<T>(wprod<T>(g, c * P + d), rsqrt_t<T>(s1 + S2[c * P + d]), in);
+            acc = fma_t<T>(wprod<T>(g, a * P + b), in, acc);
         }
     return acc;
 }
