@@ -393,6 +393,39 @@ def test_invalid_inputs(ctx):
         ctx.extract(lo[:0], hi[:0], cond[:0], 1, 1.0, 1e-6)   # empty mesh
 
 
+def _plates_512(extra):
+    """Two 1 x 1 plates 0.2 apart, 16 x 16 panels each (512 panels), plus
+    `extra` small squares of conductor 1 well away from them."""
+    h = 1.0 / 16
+    lo, hi, cond = [], [], []
+    for k, z in enumerate((0.0, 0.2)):
+        for a in range(16):
+            for b in range(16):
+                lo.append((a * h, b * h, z))
+                hi.append(((a + 1) * h, (b + 1) * h, z))
+                cond.append(k)
+    for e in range(extra):
+        lo.append((3.0 + 0.1 * e, 3.0, 0.0))
+        hi.append((3.05 + 0.1 * e, 3.05, 0.0))
+        cond.append(1)
+    return np.array(lo), np.array(hi), np.array(cond, np.int32)
+
+
+@pytest.mark.parametrize("extra", [0, 1], ids=["n512_unpadded", "n513_padded_to_1024"])
+def test_padding_edges_vs_oracle(ctx, extra):
+    """The matrix order is padded to a multiple of 512 with an identity block:
+    no padding at N = 512, 511 padded rows at N = 513."""
+    lo, hi, cond = _plates_512(extra)
+    say(f"padding edge N={lo.shape[0]}")
+    Co = oracle.extract_panels(lo, hi, cond, 2, 3.9, 1e-6, 3, 2.0)
+    C64, _ = ctx.extract(lo, hi, cond, 2, 3.9, 1e-6, binding.make_opts())
+    Cm, rm = ctx.extract(lo, hi, cond, 2, 3.9, 1e-6, binding.make_opts(3, 2.0, "f32", "f16"))
+    e64, em = rel_err(C64, Co), rel_err(Cm, Co)
+    say(f"  f64 {e64:.3e} mixed {em:.3e} (refinement sweeps {rm['refine_iters']})")
+    assert e64 < 1e-10
+    assert em < 1e-3
+
+
 def test_single_panel_plate(ctx):
     """One square panel: A = a_11, X = 1/a_11, C = eps l / a_11."""
     lo = np.array([[0.0, 0.0, 0.0]])
