@@ -49,7 +49,8 @@ typedef enum {
     GBEM_ENOMEM = 2,    /* device memory or the HBM budget cannot hold the job */
     GBEM_EDEVICE = 3,   /* a HIP call failed */
     GBEM_ENOTPD = 4,    /* Cholesky met a non-positive pivot */
-    GBEM_ENOCONV = 5,   /* iterative refinement did not reach the tolerance */
+    GBEM_ENOCONV = 5,   /* iterative refinement did not reach the tolerance (kept for the ABI: a
+                         * stalled refinement now retries with a stronger factor instead) */
     GBEM_EBUSY = 6,     /* job still running (gbem_poll) */
     GBEM_ETIMEOUT = 7   /* gbem_wait timed out */
 } gbem_status;
@@ -60,6 +61,13 @@ typedef enum {
     GBEM_F16 = 2,       /* factor stored FP32, trailing updates on FP16 MFMA, FP32 accumulate */
     GBEM_BF16 = 3       /* factor stored FP32, trailing updates on BF16 MFMA, FP32 accumulate */
 } gbem_dtype;
+
+/* Basis of the surface charge.  The method uses a piecewise constant density,
+ * one unknown per panel (section 3.1: q_j constant on I_j); it is the only
+ * basis, and the field exists so a mesh states it. */
+typedef enum {
+    GBEM_BASIS_P0 = 0
+} gbem_basis;
 
 /* A mesh: n_panels axis-aligned rectangles.  Panel i is the box lo[3i..3i+2] ..
  * hi[3i..3i+2] with exactly one axis where lo == hi (its normal axis) and
@@ -74,11 +82,14 @@ typedef struct {
     const int32_t *conductor;   /* [n_panels] */
     double eps_r;               /* relative permittivity of the uniform dielectric, > 0 */
     double length_unit_m;       /* metres per coordinate unit (1e-6 for micrometres), > 0 */
+    int32_t basis;              /* gbem_basis; must be GBEM_BASIS_P0 (zero-initialised structs are) */
 } gbem_mesh;
 
 typedef struct {
     int32_t far_order;          /* p: Gauss points per panel direction for far pairs, 1..8 (default 3) */
-    double near_eta;            /* near iff dist^2 < eta^2 * max(diam_i^2, diam_j^2) (default 2);
+    double near_eta;            /* near iff dist^2 < eta^2 * max(diam_i^2, diam_j^2) (default 2, at least
+                                 * 1e-6 so that pairs at zero distance, each panel with itself
+                                 * included, are near: GBEM_EINVAL below);
                                  * near pairs get the exact integral, far pairs p x p Gauss.  A value
                                  * above every separation/diameter ratio of the mesh (e.g. 1e6) puts
                                  * every pair on the exact path: the exact reference mode (all
@@ -162,8 +173,12 @@ gbem_status gbem_poll(gbem_job *job);
 gbem_status gbem_wait(gbem_job *job, double timeout_s, double *C_out, gbem_report *rep);
 /* Release a finished job (waits for it if it is still running). */
 void gbem_job_free(gbem_job *job);
-/* Serving statistics: jobs finished, peak admitted bytes. */
-gbem_status gbem_server_stats(gbem_ctx *ctx, int64_t *jobs_done, size_t *peak_bytes);
+/* Serving statistics (each output may be NULL): jobs finished; the largest
+ * sum of admitted footprints (the scheduler's estimates); the largest sum of
+ * the device bytes the workers' workspaces really held, taken at the end of
+ * each job.  Both peaks stay within the context's HBM budget. */
+gbem_status gbem_server_stats(gbem_ctx *ctx, int64_t *jobs_done, size_t *peak_reserved_bytes,
+                              size_t *peak_held_bytes);
 
 /* Mesher.  Boxes -> rectangles with a deterministic order (boxes as given;
  * faces -x,+x,-y,+y,-z,+z; lower in-plane axis outer).  Edge rules:

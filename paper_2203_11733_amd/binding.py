@@ -39,7 +39,7 @@ class GbemError(RuntimeError):
 class Mesh(ctypes.Structure):
     _fields_ = [("n_panels", ctypes.c_int32), ("n_conductors", ctypes.c_int32),
                 ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("conductor", ctypes.c_void_p),
-                ("eps_r", ctypes.c_double), ("length_unit_m", ctypes.c_double)]
+                ("eps_r", ctypes.c_double), ("length_unit_m", ctypes.c_double), ("basis", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -114,7 +114,8 @@ def load():
     lib.gbem_wait.argtypes = [_vp, ctypes.c_double, _vp, ctypes.POINTER(Report)]
     lib.gbem_job_free.argtypes = [_vp]
     lib.gbem_job_free.restype = None
-    lib.gbem_server_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]
+    lib.gbem_server_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t)]
     lib.gbem_mesh_boxes.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(MeshRule),
                                     ctypes.POINTER(MeshBuf)]
     lib.gbem_mesh_partition.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Partition),
@@ -368,10 +369,13 @@ class Context:
         return Job(self.lib, j, n_conductors)
 
     def server_stats(self):
+        """jobs_done; peak_bytes: largest admitted reservation (footprints);
+        peak_held_bytes: largest sum of the workers' real workspace sizes."""
         d = ctypes.c_int64(0)
         p = ctypes.c_size_t(0)
-        _check(self.lib.gbem_server_stats(self.h, ctypes.byref(d), ctypes.byref(p)))
-        return {"jobs_done": d.value, "peak_bytes": p.value}
+        h = ctypes.c_size_t(0)
+        _check(self.lib.gbem_server_stats(self.h, ctypes.byref(d), ctypes.byref(p), ctypes.byref(h)))
+        return {"jobs_done": d.value, "peak_bytes": p.value, "peak_held_bytes": h.value}
 
 
 class Job:

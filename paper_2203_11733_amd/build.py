@@ -43,8 +43,6 @@ def _compile(src: str, extra: list[str]) -> str:
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function",
            *extra, "-o", obj, os.path.join(CSRC, src)]
-    if src.endswith(".cpp"):
-        cmd.insert(2, "-xhip") if False else None
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile {src} failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -103,7 +103,7 @@ struct Readback {
 };
 
 struct Workspace {
-    DevBuf lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, D, s, partial, C,
+    DevBuf lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, s, partial, C,
         flags, norms, sflags, rpart, semi, nmask;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t evrb = nullptr;          // readback point
@@ -123,11 +123,17 @@ struct Workspace {
     // flags of the persistent solves: zeroed once when (re)allocated; the
     // epoch restarts with them
     // (published words are epoch-tagged: zero tags never match an epoch >= 1)
+    // layout: flag words (error, tickets, per-block flags), published blocks, M_k / N_k
+    static size_t sync_flag_bytes(int64_t npad) { return (((size_t)2 * (npad / kNB) * 4 + 256) + 255) / 256 * 256; }
+    static size_t sync_bytes(int64_t npad)
+    {
+        return sync_flag_bytes(npad) + (size_t)2 * npad * kMaxPub * 8 + (size_t)2 * npad * kNB * 4;
+    }
     hipError_t ensure_sync(int64_t npad, hipStream_t st)
     {
-        const size_t nflag = (((size_t)2 * (npad / kNB) * 4 + 256) + 255) / 256 * 256;
-        const size_t npub = (size_t)2 * npad * kMaxPub * 8, nsub = (size_t)2 * npad * kNB * 4;
-        const size_t need = nflag + npub + nsub;
+        const size_t nflag = sync_flag_bytes(npad);
+        const size_t npub = (size_t)2 * npad * kMaxPub * 8;
+        const size_t need = sync_bytes(npad);
         if (sflags.cap < need || sync_npad != npad) {
             hipError_t e = sflags.ensure(need);
             if (e != hipSuccess) return e;
@@ -147,19 +153,21 @@ struct Workspace {
     }
     int64_t sync_npad = -1;
 
-    size_t bytes() const
+    template <typename Fn> void each(Fn f)
     {
-        const DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
-                               &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi, &nmask};
+        DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
+                         &P16, &B, &X, &R, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi, &nmask};
+        for (auto *b : all) f(*b);
+    }
+    size_t bytes()
+    {
         size_t t = 0;
-        for (auto *b : all) t += b->cap;
+        each([&](DevBuf &b) { t += b.cap; });
         return t;
     }
     void release_all()
     {
-        DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
-                         &P16, &B, &X, &R, &D, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi, &nmask};
-        for (auto *b : all) b->release();
+        each([](DevBuf &b) { b.release(); });
     }
     hipError_t init_events()
     {
@@ -189,19 +197,36 @@ struct Workspace {
     }
 };
 
-// Device bytes one extraction needs (near list estimated at 512 entries/row).
+// Device bytes one extraction holds at most: the buffers run_pipeline sizes,
+// from the same helpers, for the requested factor and every fallback level
+// above it (a failed or stalled 16-bit factor retries in FP32, then FP64).
+// The near list is estimated at 512 pairs per row (at most n(n+1)/2); the
+// real size is only known after the near test.
+static size_t chunks_of(int64_t n) { return (size_t)((n + 1023) / 1024); }
 static size_t footprint(int64_t n, int m, int factor_dtype)
 {
     const int64_t npad = round_up(n, kPad);
-    size_t b = (size_t)npad * npad * 8;                                   // A
-    if (factor_dtype != GBEM_F64) b += (size_t)npad * npad * 4;           // FP32 factor
-    const size_t es = factor_dtype == GBEM_F64 ? 8 : 4;
-    b += (size_t)npad * kNB * es + (size_t)npad * kPad * 2 * 2;          // W, 16-bit panels
-    b += (size_t)npad * (2 * kMaxPub * 8 + 2 * kNB * 4);                 // solve: published blocks, M_k, N_k
-    b += 4 * (size_t)npad * m * 8 + (size_t)npad * 8;                    // B X R D, s
-    b += (size_t)n * (48 + 64 + 8 + 8) + (size_t)n * 512 * 12;           // mesh, panels, near list + queue
-    b += (size_t)n * near_mask_words(n) * 8;                              // near-test bit masks
-    return b;
+    const int64_t nnz = std::min<int64_t>(n * 512, n * (n + 1) / 2);
+    size_t b = 0;
+    b += (size_t)n * (2 * 3 * sizeof(double) + sizeof(int32_t)) + sizeof(double) * m * m;   // mesh copy, C
+    b += (size_t)n * (sizeof(Panel) + 2 * sizeof(int64_t)) + sizeof(int64_t) + 64;          // panels, counts, row_ptr, flags
+    b += sizeof(uint64_t) * (size_t)n * near_mask_words(n);                                 // near-test bit masks
+    b += 2 * sizeof(int32_t) * (size_t)nnz + near_semi_bytes(nnz);                          // near rows, cols, queue
+    b += (size_t)npad * npad * 8;                                                           // A
+    b += 2 * (size_t)npad * m * 8 + 2 * kMaxRhs * sizeof(double);                            // B, X, norms
+    b += Workspace::sync_bytes(npad) + chunks_of(n) * m * m * 8;                           // solve flags, charge partials
+    if (factor_dtype != GBEM_F64) {
+        b += (size_t)npad * npad * 4 + (size_t)npad * 8;                                    // F = S A S, s
+        b += (size_t)npad * m * 8 + (size_t)residual_splits((int)npad) * m * npad * 8;      // R, residual partials
+    }
+    // factor scratch: the largest over the dtypes the job may reach
+    size_t w = 0, q = 64;
+    for (int d = factor_dtype;; d = d == GBEM_F32 ? GBEM_F64 : GBEM_F32) {
+        w = std::max(w, chol_winv_bytes(d, npad));
+        q = std::max(q, chol_panel16_bytes(d, npad));
+        if (d == GBEM_F64) break;
+    }
+    return b + w + q + chol_panel_bytes(factor_dtype, npad);
 }
 
 static gbem_status dev_fail(hipError_t e, const char *where)
@@ -222,8 +247,12 @@ static bool opts_ok(const gbem_opts &o, std::string &why)
         why = "far_order must be 1..6 or 8";
         return false;
     }
-    if (!(o.near_eta >= 0.0) || !isfinite(o.near_eta)) {
-        why = "near_eta must be a finite number >= 0";
+    // the near test is strict (dist^2 < eta^2 diam^2): with eta = 0 not even a
+    // panel and itself would be near, and the far rule would put r = 0 into
+    // 1/r on the self pairs
+    if (!(o.near_eta >= kMinNearEta) || !isfinite(o.near_eta)) {
+        why = "near_eta must be a finite number >= 1e-6 (pairs at zero separation, a panel with itself "
+              "included, must be near)";
         return false;
     }
     if (o.far_dtype != GBEM_F64 && o.far_dtype != GBEM_F32) {
@@ -253,6 +282,10 @@ static bool mesh_header_ok(const gbem_mesh *m, std::string &why)
     }
     if (!(m->eps_r > 0.0) || !(m->length_unit_m > 0.0) || !isfinite(m->eps_r) || !isfinite(m->length_unit_m)) {
         why = "eps_r and length_unit_m must be positive and finite";
+        return false;
+    }
+    if (m->basis != GBEM_BASIS_P0) {
+        why = "basis must be GBEM_BASIS_P0 (piecewise constant, the only basis of the method)";
         return false;
     }
     return true;
@@ -426,6 +459,8 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
         if (dtype == GBEM_F64) {
             HIPCHK(chol_solve(dtype, npad, A, lda, ws.Winv.p, m, X, npad, ws.sync, st, &pf), "solve");
+            iters = 0;      // no refinement on an FP64 factor (also after an escalation)
+            resid = 0.0;
             break;
         }
         // mixed precision: X = S F^{-1} S B, then FP64 refinement with A
@@ -437,7 +472,8 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(ws.rpart.ensure((size_t)residual_splits((int)npad) * m * npad * 8), "alloc residual partials");
         double *R = ws.R.as<double>();
         double *rnorm = ws.norms.as<double>();
-        bool converged = false, retry = false;
+        bool retry = false;
+        double prev = INFINITY;
         for (iters = 0;; ++iters) {
             tok = pf.start(st, GBEM_K_RESIDUAL);
             HIPCHK(launch_residual(A, lda, (int)npad, X, npad, B, npad, m, R, npad, ws.rpart.as<double>(), st),
@@ -464,12 +500,15 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             }
             resid = 0.0;
             for (int k = 0; k < m; ++k) resid = std::max(resid, sqrt(rn[k] / bn[k]));
-            if (!(resid == resid)) break;   // NaN: give up
-            if (resid <= o.refine_tol) {
-                converged = true;
+            if (resid <= o.refine_tol) break;
+            // NaN or infinite, not contracting by at least half per sweep, or
+            // out of sweeps: the factor is too weak for this matrix, and the
+            // extraction retries one precision level up (as on a bad pivot)
+            if (!isfinite(resid) || !(resid < 0.5 * prev) || iters >= o.max_refine) {
+                retry = true;
                 break;
             }
-            if (iters >= o.max_refine) break;
+            prev = resid;
             HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
             HIPCHK(chol_solve(dtype, npad, Fm, lda, ws.Winv.p, m, R, npad, ws.sync, st, &pf), "solve");
             HIPCHK(launch_scale_rows(R, npad, sv, (int)npad, m, st), "scale");
@@ -479,18 +518,9 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             dtype = (dtype == GBEM_F32) ? GBEM_F64 : GBEM_F32;   // BF16/F16 -> F32 -> F64
             continue;
         }
-        if (!converged) {
-            if (rep) {
-                rep->residual = resid;
-                rep->refine_iters = iters;
-            }
-            set_error("iterative refinement stopped at residual " + std::to_string(resid) + " after " +
-                      std::to_string(iters) + " iterations");
-            return GBEM_ENOCONV;
-        }
         break;
     }
-    const int nchunks = (n + 1023) / 1024;
+    const int nchunks = (int)chunks_of(n);
     HIPCHK(ws.partial.ensure((size_t)nchunks * m * m * 8), "alloc partials");
     HIPCHK(launch_charge_partials(X, npad, dcond, n, m, ws.partial.as<double>(), nchunks, st), "charges");
     const double eps0 = 8.8541878128e-12;
@@ -568,7 +598,8 @@ struct Worker {
     Workspace ws;
     gbem_job *job = nullptr;
     bool busy = false;
-    size_t held = 0;   // device bytes this worker may hold while busy (set at dispatch)
+    size_t held = 0;    // device bytes this worker may hold while busy (set at dispatch)
+    size_t bytes = 0;   // device bytes its workspace holds (updated at each job's end and release)
 };
 
 struct gbem_ctx {
@@ -586,6 +617,7 @@ struct gbem_ctx {
     std::thread sched;
     bool started = false, stopping = false;
     size_t reserved = 0, peak = 0;
+    size_t peak_held = 0;   // largest sum of the workspaces' real sizes seen at a job's end
     int64_t done = 0;
 };
 
@@ -638,10 +670,15 @@ static void worker_main(gbem_ctx *ctx, Worker *w)
             j->state = 2;
         }
         j->cv.notify_all();
+        const size_t held_now = w->ws.bytes();   // only this thread touches a busy workspace
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
             w->job = nullptr;
             w->busy = false;
+            w->bytes = held_now;
+            size_t t = 0;
+            for (Worker *c : ctx->workers) t += c->bytes;
+            ctx->peak_held = std::max(ctx->peak_held, t);
             ctx->reserved -= j->need;
             ctx->done += 1;
         }
@@ -684,16 +721,26 @@ static void sched_main(gbem_ctx *ctx)
                 auto held_by_others = [&](bool count_idle) {
                     size_t t = 0;
                     for (Worker *c : ctx->workers)
-                        if (c != w) t += c->busy ? c->held : (count_idle ? c->ws.bytes() : 0);
+                        if (c != w) t += c->busy ? std::max(c->held, c->bytes) : (count_idle ? c->bytes : 0);
                     return t;
                 };
                 size_t held_others = held_by_others(true);
-                size_t mine = std::max(w->ws.bytes(), j->need);
+                size_t mine = std::max(w->bytes, j->need);
                 if (held_others + mine > ctx->budget) {
+                    // free the idle workspaces without holding the lock (hipFree
+                    // may wait for the device, and workers finishing a job need
+                    // the lock); only this thread dispatches, so an idle worker
+                    // stays idle meanwhile
+                    std::vector<Worker *> idle;
                     for (Worker *c : ctx->workers)
-                        if (!c->busy && c->ws.bytes() > 0) c->ws.release_all();
+                        if (!c->busy && c->bytes > 0) idle.push_back(c);
+                    lk.unlock();
+                    for (Worker *c : idle) c->ws.release_all();
+                    lk.lock();
+                    for (Worker *c : idle) c->bytes = 0;
                     held_others = held_by_others(false);
                     mine = j->need;
+                    if (ctx->queue.size() <= qi || ctx->queue[qi] != j) break;   // the queue moved: rescan
                 }
                 if (held_others + mine <= ctx->budget) {
                     ctx->queue.erase(ctx->queue.begin() + qi);
@@ -833,13 +880,11 @@ static gbem_status upload_mesh(gbem_ctx *ctx, const gbem_mesh *mesh)
     return GBEM_OK;
 }
 
+// Mesh header and options are checked before the context, so argument
+// errors are reported the same way with or without a device.
 static gbem_status check_args(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts, gbem_opts &o)
 {
     std::string why;
-    if (!ctx) {
-        set_error("context is NULL");
-        return GBEM_EINVAL;
-    }
     if (!mesh_header_ok(mesh, why)) {
         set_error(why);
         return GBEM_EINVAL;
@@ -847,6 +892,10 @@ static gbem_status check_args(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_o
     if (opts) o = *opts; else gbem_default_opts(&o);
     if (!opts_ok(o, why)) {
         set_error(why);
+        return GBEM_EINVAL;
+    }
+    if (!ctx) {
+        set_error("context is NULL");
         return GBEM_EINVAL;
     }
     return GBEM_OK;
@@ -978,12 +1027,14 @@ extern "C" void gbem_job_free(gbem_job *j)
     delete j;
 }
 
-extern "C" gbem_status gbem_server_stats(gbem_ctx *ctx, int64_t *jobs_done, size_t *peak_bytes)
+extern "C" gbem_status gbem_server_stats(gbem_ctx *ctx, int64_t *jobs_done, size_t *peak_reserved_bytes,
+                                         size_t *peak_held_bytes)
 {
     if (!ctx) return GBEM_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (jobs_done) *jobs_done = ctx->done;
-    if (peak_bytes) *peak_bytes = ctx->peak;
+    if (peak_reserved_bytes) *peak_reserved_bytes = ctx->peak;
+    if (peak_held_bytes) *peak_held_bytes = ctx->peak_held;
     return GBEM_OK;
 }
 

@@ -22,6 +22,7 @@ constexpr int kMaxPanelBlocks = 4;   // widest outer panel / kNB; chol_factor's 
 constexpr int kPad = 512;         // padding of the matrix order (one outer Cholesky panel)
 constexpr int kMaxOrder = 8;      // largest Gauss order of the far rule
 constexpr int kMaxRhs = 64;       // right-hand sides handled per solve pass
+constexpr double kMinNearEta = 1e-6;   // smallest near threshold accepted
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -81,3 +81,45 @@ def test_context_without_gpu_fails_cleanly():
     with pytest.raises(binding.GbemError) as e:
         binding.Context(0)
     assert e.value.status == binding.EDEVICE
+
+
+def _host_mesh(lo, hi, cond, m=2, basis=0):
+    return binding.Mesh(cond.shape[0], m, lo.ctypes.data, hi.ctypes.data, cond.ctypes.data, 3.9, 1e-6, basis)
+
+
+@pytest.mark.parametrize("eta", [0.0, -1.0, 1e-9, float("nan"), float("inf")])
+def test_near_threshold_that_misses_self_pairs_is_refused(eta):
+    """The near test is strict (dist^2 < eta^2 diam^2): at eta = 0 no pair, not
+    even a panel with itself, would be near, and the far rule would evaluate
+    1/r at r = 0.  Such thresholds are refused before any device work (the
+    arguments are checked before the context, so this runs without a GPU)."""
+    lib = binding.load()
+    lo, hi, cond = binding.mesh_layout(gi.two_plates(h=0.5))
+    mesh = _host_mesh(lo, hi, cond)
+    o = binding.make_opts(3, eta)
+    C = np.zeros((2, 2))
+    st = lib.gbem_extract(None, ctypes.byref(mesh), ctypes.byref(o), C.ctypes.data, None)
+    assert st == binding.EINVAL
+    assert b"near_eta" in lib.gbem_last_error()
+    rp = np.zeros(lo.shape[0] + 1, dtype=np.int64)
+    nnz = ctypes.c_int64(0)
+    st = lib.gbem_near_list(None, ctypes.byref(mesh), eta, rp.ctypes.data, None, 0, ctypes.byref(nnz))
+    assert st == binding.EINVAL
+
+
+def test_argument_checks_before_context():
+    lib = binding.load()
+    lo, hi, cond = binding.mesh_layout(gi.two_plates(h=0.5))
+    C = np.zeros((2, 2))
+    o = binding.make_opts()
+    # only the piecewise constant basis exists
+    mesh = _host_mesh(lo, hi, cond, basis=1)
+    assert lib.gbem_extract(None, ctypes.byref(mesh), ctypes.byref(o), C.ctypes.data, None) == binding.EINVAL
+    assert b"basis" in lib.gbem_last_error()
+    # a valid mesh and options reach the context check
+    mesh = _host_mesh(lo, hi, cond)
+    assert lib.gbem_extract(None, ctypes.byref(mesh), ctypes.byref(o), C.ctypes.data, None) == binding.EINVAL
+    assert b"context" in lib.gbem_last_error()
+    o = binding.make_opts(0)
+    assert lib.gbem_extract(None, ctypes.byref(mesh), ctypes.byref(o), C.ctypes.data, None) == binding.EINVAL
+    assert b"far_order" in lib.gbem_last_error()

@@ -206,6 +206,21 @@ def test_near_list_bit_exact(ctx, layout, eta):
     assert np.array_equal(col, colo)
 
 
+@pytest.mark.parametrize("layout,eta", [(gi.crossing_bus(), 2.0), (gi.three_layer_bus(), 2.0),
+                                        (gi.crossing_bus(), 1.0)],
+                         ids=["crossing_bus", "three_layer_bus", "crossing_bus_eta1"])
+def test_near_list_bit_exact_full_size(ctx, layout, eta):
+    """The whole near list of the full-size layouts (N = 21,420 graded, with the
+    most threshold ties, and N = 59,904) against the oracle's O(N^2) test."""
+    lo, hi, cond = mesh(layout)
+    say(f"near list full size {layout.name} N={lo.shape[0]} eta={eta}")
+    rp, col = ctx.near_list(lo, hi, eta)
+    rpo, colo = oracle.near_csr(lo, hi, eta)
+    say(f"  nnz GPU {rp[-1]} oracle {rpo[-1]}")
+    assert np.array_equal(rp, rpo)
+    assert np.array_equal(col, colo)
+
+
 # ---------------------------------------------------------------- matrix
 @pytest.mark.parametrize("layout", [gi.two_plates(), gi.crossing_bars_in_box(), gi.random_small_layout(5)],
                          ids=["two_plates", "bars_in_box", "random5"])
@@ -508,21 +523,34 @@ def test_full_size_crossing_bus_capacitance(ctx):
 
 
 def test_full_size_three_layer_bus_capacitance(ctx):
-    """N = 59,904, M = 48 (the oracle's whole extraction would take minutes
-    here): Maxwell invariants in both modes and mixed vs FP64 within 1e-3."""
+    """N = 59,904, M = 48, both modes against the oracle's whole extraction of
+    the same layout (stored by tests/golden/make_golden.py, which calls only
+    the oracle: about ten minutes and 30 GB of host memory), plus the Maxwell
+    invariants and mixed vs FP64."""
+    import json
+    import os
     lay = gi.three_layer_bus()
     lo, hi, cond = mesh(lay)
     m = lay.n_conductors
+    gpath = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "three_layer_bus_C.json")
+    with open(gpath) as f:
+        gold = json.load(f)
+    assert (gold["n_panels"], gold["n_conductors"], gold["far_order"], gold["near_eta"]) == (lo.shape[0], m, 3, 2.0)
+    Cg = np.array(gold["C"])
     say(f"full-size extract three_layer_bus N={lo.shape[0]} M={m}")
     C64, r64 = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, binding.make_opts())
     say(f"  f64 report {r64}")
-    Cm, rm = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, binding.make_opts(3, 2.0, "f32", "f16"))
+    Cm, rm = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m,
+                         binding.make_opts(3, 2.0, "f32", "f16", 1e-8, 40))
     say(f"  mixed report {rm}")
     for C in (C64, Cm):
         assert np.abs(C - C.T).max() <= 1e-6 * np.abs(C).max()
         assert np.all(np.diag(C) > 0)
         assert np.all(C[~np.eye(m, dtype=bool)] < 0)
         assert np.all(C.sum(1) > 0)
-    err = rel_err(Cm, C64)
-    say(f"  mixed vs f64 rel err {err:.3e}")
-    assert err < 1e-3
+    e64, em = rel_err(C64, Cg), rel_err(Cm, Cg)
+    say(f"  vs oracle: f64 {e64:.3e}, mixed {em:.3e}; mixed vs f64 {rel_err(Cm, C64):.3e}")
+    assert e64 <= 1e-10
+    assert em <= 1e-3
+    # refinement to a 1e-8 residual leaves errors of that order: a lost digit fails here
+    assert em <= 1e-6

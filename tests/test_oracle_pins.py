@@ -74,6 +74,30 @@ def test_near_pairs_vs_bruteforce(case, desc):
     assert got == pytest.approx(ref, rel=5e-14)
 
 
+# Pairs of very different sizes (a 0.05 or 0.01 panel against a 4 x 4 one, as
+# a fine bar panel against a coarse enclosure panel): the 16-term corner sum
+# of the coplanar closed form cancels about (D/h)^4 of its magnitude, which the
+# oracle's extended-precision arithmetic must absorb.  Reference: mpmath at 25
+# digits by the convolution-weight route.
+RATIO_CASES = [
+    (((0, 0, 0), (0.05, 0.05, 0), (0.3, -2, 0), (4.3, 2, 0)), "coplanar separated, ratio 80"),
+    (((4, 0, 0), (4.05, 0.05, 0), (0, -2, 0), (4, 2, 0)), "coplanar partial shared edge, ratio 80"),
+    (((4, 0, 0), (4.01, 0.01, 0), (0, -2, 0), (4, 2, 0)), "coplanar partial shared edge, ratio 400"),
+    (((1.0, 0.2, 1.0), (1.05, 0.25, 1.0), (0, -2, 0), (4, 2, 0)), "parallel above, ratio 80"),
+    (((4.1, 0.0, 0.0), (4.15, 0.0, 0.05), (0, -2, 0), (4, 2, 0)), "orthogonal beside, ratio 80"),
+    (((2.0, 0.0, 0.0), (2.05, 0.0, 0.05), (0, -2, 0), (4, 2, 0)), "orthogonal standing on, ratio 80"),
+]
+
+
+@pytest.mark.parametrize("case,desc", RATIO_CASES, ids=[c[1] for c in RATIO_CASES])
+def test_large_size_ratio_pairs_vs_bruteforce(case, desc):
+    got = oracle.pair_integral(*case)
+    ref = bf.pair_integral_mp(*case, dps=25)
+    assert got == pytest.approx(ref, rel=1e-13)
+    # both orders of the pair
+    assert oracle.pair_integral(case[2], case[3], case[0], case[1]) == pytest.approx(ref, rel=1e-13)
+
+
 def test_pair_symmetry_and_invariance():
     """Int Int is symmetric in (I_i, I_j) and invariant under translation and mirroring."""
     rng = np.random.default_rng(5)
