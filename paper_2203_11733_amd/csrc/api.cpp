@@ -661,16 +661,11 @@ static void worker_main(gbem_ctx *ctx, Worker *w)
             }
         }
         if (st == GBEM_OK) rep.asym = asym_of(C.data(), j->m);
-        {
-            std::lock_guard<std::mutex> lk(j->mu);
-            j->status = st;
-            j->rep = rep;
-            j->C.swap(C);
-            if (st != GBEM_OK) j->err = gbem_last_error();
-            j->state = 2;
-        }
-        j->cv.notify_all();
         const size_t held_now = w->ws.bytes();   // only this thread touches a busy workspace
+        const size_t need = j->need;
+        std::string err = st != GBEM_OK ? std::string(gbem_last_error()) : std::string();
+        // the context's statistics first, then the job's completion: a caller
+        // woken by gbem_wait already sees this job counted
         {
             std::lock_guard<std::mutex> lk(ctx->mu);
             w->job = nullptr;
@@ -679,10 +674,21 @@ static void worker_main(gbem_ctx *ctx, Worker *w)
             size_t t = 0;
             for (Worker *c : ctx->workers) t += c->bytes;
             ctx->peak_held = std::max(ctx->peak_held, t);
-            ctx->reserved -= j->need;
+            ctx->reserved -= need;
             ctx->done += 1;
         }
         ctx->cv_sched.notify_all();
+        {
+            std::lock_guard<std::mutex> lk(j->mu);
+            j->status = st;
+            j->rep = rep;
+            j->C.swap(C);
+            if (st != GBEM_OK) j->err = err;
+            j->state = 2;
+            // notified under the job's lock: its owner cannot free it before
+            // this thread lets go of the lock, and nothing of j is touched after
+            j->cv.notify_all();
+        }
     }
 }
 
