@@ -162,6 +162,29 @@ gbem_status gbem_extract(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *
 gbem_status gbem_extract_device(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
                                 double *C_out_device, void *stream, gbem_report *rep);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * extraction as gbem_extract_device (same kernels, same launches, same
+ * results), except that the call allocates nothing: no hipMalloc, hipFree or
+ * other allocating routine.  Every intermediate (panel table, near list, A,
+ * the scaled FP32 copy, the factor's workspaces, right-hand sides and
+ * residuals) is carved from one static device array of 256 MiB per GPU,
+ * which the first gbem_create on that GPU sets up and which stays held until
+ * the process ends; the events, side stream and pinned readback words of
+ * the call are made at that set-up too.  The caller passes the device mesh,
+ * the device C_out and the stream as for gbem_extract_device.
+ * Limits: padded order <= 5,632 (meshes up to about 5,600 panels with an FP64
+ * factor, about 4,000 with a low-precision factor, whose scaled copy and
+ * refinement buffers need room too).  A larger mesh, or a near list that
+ * does not fit what is left of the array, returns GBEM_ENOMEM with the size in
+ * gbem_last_error() before or instead of any result.  opts->profile must be 0
+ * (GBEM_EINVAL).  The array keeps the last call's contents; every call
+ * re-zeroes what must start at zero.  All calls on one GPU share the array:
+ * the library makes them take turns (a per-GPU lock held until the call's
+ * last kernel has finished), since overlapping calls would race on it. */
+gbem_status gbem_extract_device_noalloc(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                        double *C_out_device, void *stream, gbem_report *rep);
+
 /* Serving loop (continuous batching): submit copies the mesh and returns at
  * once; jobs are admitted as their HBM footprint fits the budget and run
  * concurrently on their own streams. */

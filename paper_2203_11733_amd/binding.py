@@ -27,6 +27,7 @@ EXPORTS = [
     "gbem_job_free", "gbem_server_stats", "gbem_mesh_boxes", "gbem_mesh_buf_free", "gbem_near_list",
     "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
     "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
+    "gbem_extract_device_noalloc",
 ]
 
 
@@ -109,6 +110,8 @@ def load():
     lib.gbem_extract.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp, ctypes.POINTER(Report)]
     lib.gbem_extract_device.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp, _vp,
                                         ctypes.POINTER(Report)]
+    lib.gbem_extract_device_noalloc.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp, _vp,
+                                                ctypes.POINTER(Report)]
     lib.gbem_submit.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
     lib.gbem_poll.argtypes = [_vp]
     lib.gbem_wait.argtypes = [_vp, ctypes.c_double, _vp, ctypes.POINTER(Report)]
@@ -139,7 +142,8 @@ def load():
     for name in ("gbem_create", "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit",
                  "gbem_poll", "gbem_wait", "gbem_server_stats", "gbem_mesh_boxes", "gbem_near_list",
                  "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
-                 "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned"):
+                 "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
+                 "gbem_extract_device_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -296,6 +300,21 @@ class Context:
         st = stream.cuda_stream if stream is not None else None
         _check(self.lib.gbem_extract_device(self.h, ctypes.byref(m), ctypes.byref(o), ctypes.c_void_p(d_C.data_ptr()),
                                             ctypes.c_void_p(st), ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def extract_device_noalloc(self, d_lo, d_hi, d_cond, n_conductors, eps_r, length_unit_m, d_C,
+                               opts: Opts | None = None, stream=None):
+        """As extract_device, through gbem_extract_device_noalloc (no device
+        allocation during the call; intermediates in the library's static
+        per-GPU scratch)."""
+        m = Mesh(d_cond.shape[0], n_conductors, d_lo.data_ptr(), d_hi.data_ptr(), d_cond.data_ptr(), eps_r,
+                 length_unit_m)
+        rep = Report()
+        o = opts or make_opts()
+        st = stream.cuda_stream if stream is not None else None
+        _check(self.lib.gbem_extract_device_noalloc(self.h, ctypes.byref(m), ctypes.byref(o),
+                                                    ctypes.c_void_p(d_C.data_ptr()), ctypes.c_void_p(st),
+                                                    ctypes.byref(rep)))
         return rep.as_dict()
 
     def near_list(self, lo, hi, near_eta=2.0):

@@ -67,12 +67,38 @@ void gauss_legendre_rule(int p, GaussRule *r)
 // ------------------------------------------------------------------------
 // device buffers
 // ------------------------------------------------------------------------
+// A bump allocator over a fixed device region (the no-allocation entry
+// point's scratch array): buffers are carved in call order and the whole
+// region is handed back at once (reset) before the next call.
+struct Arena {
+    unsigned char *base = nullptr;
+    size_t size = 0, used = 0;
+    bool exhausted = false;   // a request did not fit (the call fails with GBEM_ENOMEM)
+    void reset()
+    {
+        used = 0;
+        exhausted = false;
+    }
+};
+
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    Arena *arena = nullptr;   // set: memory comes from the arena, never from hipMalloc
     hipError_t ensure(size_t bytes)
     {
         if (bytes <= cap) return hipSuccess;
+        if (arena) {
+            const size_t want = (bytes + 255) & ~(size_t)255;
+            if (want > arena->size - arena->used) {
+                arena->exhausted = true;
+                return hipErrorOutOfMemory;
+            }
+            p = arena->base + arena->used;
+            arena->used += want;
+            cap = want;
+            return hipSuccess;
+        }
         release();
         size_t want = (bytes + 4095) & ~(size_t)4095;
         hipError_t e = hipMalloc(&p, want);
@@ -85,7 +111,7 @@ struct DevBuf {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && !arena) (void)hipFree(p);
         p = nullptr;
         cap = 0;
     }
@@ -203,15 +229,14 @@ struct Workspace {
 // The near list is estimated at 512 pairs per row (at most n(n+1)/2); the
 // real size is only known after the near test.
 static size_t chunks_of(int64_t n) { return (size_t)((n + 1023) / 1024); }
-static size_t footprint(int64_t n, int m, int factor_dtype)
+// The buffers whose size the mesh fixes: everything but the mesh copy, C and
+// the near list.
+static size_t footprint_fixed(int64_t n, int m, int factor_dtype)
 {
     const int64_t npad = round_up(n, kPad);
-    const int64_t nnz = std::min<int64_t>(n * 512, n * (n + 1) / 2);
     size_t b = 0;
-    b += (size_t)n * (2 * 3 * sizeof(double) + sizeof(int32_t)) + sizeof(double) * m * m;   // mesh copy, C
     b += (size_t)n * (sizeof(Panel) + 2 * sizeof(int64_t)) + sizeof(int64_t) + 64;          // panels, counts, row_ptr, flags
     b += sizeof(uint64_t) * (size_t)n * near_mask_words(n);                                 // near-test bit masks
-    b += 2 * sizeof(int32_t) * (size_t)nnz + near_semi_bytes(nnz);                          // near rows, cols, queue
     b += (size_t)npad * npad * 8;                                                           // A
     b += 2 * (size_t)npad * m * 8 + 2 * kMaxRhs * sizeof(double);                            // B, X, norms
     b += Workspace::sync_bytes(npad) + chunks_of(n) * m * m * 8;                           // solve flags, charge partials
@@ -227,6 +252,13 @@ static size_t footprint(int64_t n, int m, int factor_dtype)
         if (d == GBEM_F64) break;
     }
     return b + w + q + chol_panel_bytes(factor_dtype, npad);
+}
+static size_t footprint(int64_t n, int m, int factor_dtype)
+{
+    const int64_t nnz = std::min<int64_t>(n * 512, n * (n + 1) / 2);
+    return footprint_fixed(n, m, factor_dtype) +
+           (size_t)n * (2 * 3 * sizeof(double) + sizeof(int32_t)) + sizeof(double) * m * m +   // mesh copy, C
+           2 * sizeof(int32_t) * (size_t)nnz + near_semi_bytes(nnz);                        // near rows, cols, queue
 }
 
 static gbem_status dev_fail(hipError_t e, const char *where)
@@ -569,6 +601,67 @@ static double asym_of(const double *C, int m)
     return mx > 0 ? d / mx : 0.0;
 }
 
+// ------------------------------------------------------------------------
+// Scratch of the no-allocation entry point (gbem_extract_device_noalloc).
+// One static device array per GPU: the loader gives every device that loads
+// the library its own copy, held until the process ends.  In host code the
+// name `scratch` is only a host-side stand-in; its device address on a GPU
+// comes from hipGetSymbolAddress with that GPU current, taken once per device
+// when the first context on it is created (noalloc_setup), and only that
+// address is ever handed to kernels or copies.
+// ------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// largest padded order whose FP64 matrix alone fits the scratch
+constexpr int64_t kNoAllocMaxPad = 5632;
+static_assert((size_t)kNoAllocMaxPad * kNoAllocMaxPad * 8 <= kNoAllocBytes &&
+                  (size_t)(kNoAllocMaxPad + kPad) * (kNoAllocMaxPad + kPad) * 8 > kNoAllocBytes,
+              "kNoAllocMaxPad must be the largest padded order with an FP64 matrix inside the scratch");
+
+struct NoAllocDev {
+    std::mutex mu;          // calls on this device take turns: they share the array
+    void *ptr = nullptr;    // device address of `scratch` on this device
+    Arena arena;
+    Workspace ws;           // every buffer borrowed from the arena; events, side stream,
+                            // pinned readback and the factor's event pool created at set-up
+};
+static std::mutex g_noalloc_mu;
+static std::vector<NoAllocDev *> g_noalloc;   // by device; entries live until the process ends
+
+// Called by gbem_create with `device` current.
+static hipError_t noalloc_setup(int device)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if ((int)g_noalloc.size() <= device) g_noalloc.resize(device + 1, nullptr);
+    if (g_noalloc[device]) return hipSuccess;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    NoAllocDev *d = new NoAllocDev();
+    d->ptr = ptr;
+    d->arena.base = static_cast<unsigned char *>(ptr);
+    d->arena.size = kNoAllocBytes;
+    d->ws.each([&](DevBuf &b) { b.arena = &d->arena; });
+    if ((e = d->ws.init_events()) != hipSuccess || (e = d->ws.ensure_side()) != hipSuccess) {
+        delete d;
+        return e;
+    }
+    // the factorisation's event pool: two events per outer panel of the
+    // largest order that fits, with room to spare
+    for (int64_t k = 0; k < 4 * (kNoAllocMaxPad / kNB) + 8; ++k) {
+        hipEvent_t x;
+        if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming | hipEventDisableSystemFence)) != hipSuccess) {
+            delete d;
+            return e;
+        }
+        d->ws.fev.push_back(x);
+    }
+    g_noalloc[device] = d;
+    return hipSuccess;
+}
+
 }  // namespace gbem
 
 using namespace gbem;
@@ -844,6 +937,11 @@ extern "C" gbem_status gbem_create(int device, size_t budget, gbem_ctx **out)
         delete c;
         return dev_fail(e, "hipStreamCreate");
     }
+    if ((e = noalloc_setup(device)) != hipSuccess) {
+        (void)hipStreamDestroy(c->stream);
+        delete c;
+        return dev_fail(e, "scratch of the no-allocation entry point (hipGetSymbolAddress)");
+    }
     *out = c;
     return GBEM_OK;
 }
@@ -956,6 +1054,62 @@ extern "C" gbem_status gbem_extract_device(gbem_ctx *ctx, const gbem_mesh *mesh,
     s = run_pipeline(ctx->ws, st, mesh->n_panels, m, mesh->lo, mesh->hi, mesh->conductor, mesh->eps_r,
                      mesh->length_unit_m, o, C_out_device, &r, Stop::kFull, rep ? C.data() : nullptr);
     if (s == GBEM_OK && rep) r.asym = asym_of(C.data(), m);
+    if (rep) *rep = r;
+    return s;
+}
+
+extern "C" gbem_status gbem_extract_device_noalloc(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
+                                                   double *C_out_device, void *stream, gbem_report *rep)
+{
+    gbem_opts o;
+    gbem_status s = check_args(ctx, mesh, opts, o);
+    if (s != GBEM_OK) return s;
+    if (!C_out_device) {
+        set_error("C_out_device is NULL");
+        return GBEM_EINVAL;
+    }
+    if (o.profile != 0) {
+        set_error("gbem_extract_device_noalloc: opts->profile must be 0 (the timing events would be created "
+                  "during the call)");
+        return GBEM_EINVAL;
+    }
+    const int n = mesh->n_panels, m = mesh->n_conductors;
+    const int64_t npad = round_up(n, kPad);
+    // the buffers whose size the mesh fixes, for the requested factor and
+    // every fallback level (the near list is checked once its size is known)
+    const size_t fixed = footprint_fixed(n, m, o.factor_dtype);
+    if (npad > kNoAllocMaxPad || fixed > kNoAllocBytes) {
+        set_error("gbem_extract_device_noalloc: a mesh of " + std::to_string(n) + " panels needs about " +
+                  std::to_string(fixed >> 20) + " MiB of scratch; the no-allocation entry point has " +
+                  std::to_string(kNoAllocBytes >> 20) + " MiB per GPU (use gbem_extract_device)");
+        return GBEM_ENOMEM;
+    }
+    NoAllocDev *d = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (ctx->device < (int)g_noalloc.size()) d = g_noalloc[ctx->device];
+    }
+    if (!d) {
+        set_error("gbem_extract_device_noalloc: the context's device has no scratch set up");
+        return GBEM_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(d->mu);
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    // hand the whole array back to the arena: every buffer is carved again,
+    // and the triangular solves' flags are zeroed again when carved
+    d->ws.release_all();
+    d->arena.reset();
+    d->ws.sync_npad = -1;
+    hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
+    gbem_report r{};
+    double hC[kMaxRhs * kMaxRhs];
+    s = run_pipeline(d->ws, st, n, m, mesh->lo, mesh->hi, mesh->conductor, mesh->eps_r, mesh->length_unit_m, o,
+                     C_out_device, &r, Stop::kFull, hC);
+    if (s == GBEM_ENOMEM && d->arena.exhausted)
+        set_error("gbem_extract_device_noalloc: the " + std::to_string(kNoAllocBytes >> 20) +
+                  " MiB scratch cannot hold this job (" + gbem_last_error() +
+                  "); use gbem_extract_device");
+    if (s == GBEM_OK) r.asym = asym_of(hC, m);
     if (rep) *rep = r;
     return s;
 }
