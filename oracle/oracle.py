@@ -182,6 +182,24 @@ def solve(A, B):
     return sla.cho_solve((c, low), B, check_finite=False)
 
 
+def solve_inplace(A, B):
+    """Cholesky solve A X = B for orders whose dense matrix is too large for a
+    second copy: LAPACK potrf/potrs as PyTorch's CPU build ships them (MKL),
+    factoring A (symmetric, C-contiguous, n x n) in place.  (scipy's bundled
+    OpenBLAS potrf fails on this host for orders above about 30,000.)
+    A C-contiguous symmetric matrix read column by column is itself; on
+    return A holds the Cholesky factor L (lower, zero above).  Returns X."""
+    import torch
+    assert A.flags.c_contiguous and A.dtype == np.float64 and A.shape[0] == A.shape[1]
+    T = torch.from_numpy(A)                       # shares A's memory
+    info = torch.empty((), dtype=torch.int32)
+    torch.linalg.cholesky_ex(T, out=(T, info))    # in place: out is the input's own storage
+    if int(info) != 0:
+        raise np.linalg.LinAlgError(f"potrf: info = {int(info)}")
+    Bt = torch.from_numpy(np.ascontiguousarray(np.asarray(B, dtype=np.float64).reshape(A.shape[0], -1)))
+    return torch.cholesky_solve(Bt, T).numpy().copy()
+
+
 def charges(X, cond, n_conductors: int, eps_r: float, length_unit_m: float) -> np.ndarray:
     """C_kl = eps_r eps0 l * sum_{i on conductor k} X_il, summed exactly (math.fsum)."""
     cond = np.asarray(cond)
@@ -214,4 +232,4 @@ def extract(layout, p: int = 3, eta: float = 2.0, return_matrix: bool = False):
 
 __all__ = ["EPS0", "gauss_legendre", "pair_integral", "pair_gauss_mean", "panel_area", "is_near",
            "entry", "mesh_boxes", "mesh_layout", "near_csr", "assemble", "entries", "rhs",
-           "solve", "charges", "extract_panels", "extract"]
+           "solve", "solve_inplace", "charges", "extract_panels", "extract"]

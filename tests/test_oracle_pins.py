@@ -316,3 +316,20 @@ def test_table2_window():
     row = g["gbem"][-1]
     for key, val in (("C11", C[0, 0]), ("C12", C[0, 1]), ("C22", C[1, 1])):
         assert abs(val - row[key]) <= 0.05 * abs(row[key]), (key, val)
+
+
+def test_inplace_solve_is_the_library_cholesky(c1):
+    """The in-place solve used for orders too large for a second copy (the
+    stored result of the three-layer bus) is LAPACK's Cholesky as well: on the
+    C1 matrix it reproduces scipy's cho_factor/cho_solve, and it leaves the
+    factor L (L L^T = A) in the matrix's memory."""
+    import scipy.linalg as sla
+    L, lo, hi, cond, C, A, X = c1
+    B = oracle.rhs(cond, 2)
+    X0 = sla.cho_solve(sla.cho_factor(A, lower=True), B)
+    A2 = np.ascontiguousarray(A.copy())
+    X1 = oracle.solve_inplace(A2, B)
+    assert np.abs(X1 - X0).max() <= 1e-12 * np.abs(X0).max()
+    Lf = np.tril(A2)
+    assert np.abs(np.triu(A2, 1)).max() == 0.0
+    assert np.abs(Lf @ Lf.T - A).max() <= 1e-12 * np.abs(A).max()
