@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -179,10 +180,11 @@ struct Workspace {
     }
     int64_t sync_npad = -1;
 
+    static constexpr int kBuffers = 25;
     template <typename Fn> void each(Fn f)
     {
-        DevBuf *all[] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
-                         &P16, &B, &X, &R, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi, &nmask};
+        DevBuf *all[kBuffers] = {&lo, &hi, &cond, &pan, &cnt, &rowptr, &nrow, &ncol, &A, &F, &Winv, &Pw,
+                                 &P16, &B, &X, &R, &s, &partial, &C, &flags, &norms, &sflags, &rpart, &semi, &nmask};
         for (auto *b : all) f(*b);
     }
     size_t bytes()
@@ -229,36 +231,59 @@ struct Workspace {
 // The near list is estimated at 512 pairs per row (at most n(n+1)/2); the
 // real size is only known after the near test.
 static size_t chunks_of(int64_t n) { return (size_t)((n + 1023) / 1024); }
-// The buffers whose size the mesh fixes: everything but the mesh copy, C and
-// the near list.
-static size_t footprint_fixed(int64_t n, int m, int factor_dtype)
+static size_t page_round(size_t b) { return b ? (b + 4095) & ~(size_t)4095 : 0; }   // DevBuf::ensure's unit
+
+// Bytes of each workspace buffer a job may allocate (Workspace::each order),
+// for the requested factor and every fallback level above it (a failed or
+// stalled 16-bit factor retries in FP32, then FP64).  The near list is
+// estimated at 512 pairs per row (at most n(n+1)/2); its real size is only
+// known after the near test.  include_near/include_mesh: the near list and
+// the device copy of the mesh and C (what a synchronous call brings in).
+static std::array<size_t, Workspace::kBuffers> buffer_needs(int64_t n, int m, int factor_dtype, bool include_near,
+                                                            bool include_mesh)
 {
     const int64_t npad = round_up(n, kPad);
-    size_t b = 0;
-    b += (size_t)n * (sizeof(Panel) + 2 * sizeof(int64_t)) + sizeof(int64_t) + 64;          // panels, counts, row_ptr, flags
-    b += sizeof(uint64_t) * (size_t)n * near_mask_words(n);                                 // near-test bit masks
-    b += (size_t)npad * npad * 8;                                                           // A
-    b += 2 * (size_t)npad * m * 8 + 2 * kMaxRhs * sizeof(double);                            // B, X, norms
-    b += Workspace::sync_bytes(npad) + chunks_of(n) * m * m * 8;                           // solve flags, charge partials
-    if (factor_dtype != GBEM_F64) {
-        b += (size_t)npad * npad * 4 + (size_t)npad * 8;                                    // F = S A S, s
-        b += (size_t)npad * m * 8 + (size_t)residual_splits((int)npad) * m * npad * 8;      // R, residual partials
-    }
-    // factor scratch: the largest over the dtypes the job may reach
+    const int64_t nnz = std::min<int64_t>(n * 512, n * (n + 1) / 2);
+    const bool low = factor_dtype != GBEM_F64;
     size_t w = 0, q = 64;
     for (int d = factor_dtype;; d = d == GBEM_F32 ? GBEM_F64 : GBEM_F32) {
         w = std::max(w, chol_winv_bytes(d, npad));
         q = std::max(q, chol_panel16_bytes(d, npad));
         if (d == GBEM_F64) break;
     }
-    return b + w + q + chol_panel_bytes(factor_dtype, npad);
+    const size_t mesh3 = include_mesh ? (size_t)n * 3 * sizeof(double) : 0;
+    const size_t near4 = include_near ? sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1) : 0;
+    // lo, hi, cond, pan, cnt, rowptr, nrow, ncol, A, F, Winv, Pw, P16, B, X, R, s, partial, C, flags,
+    // norms, sflags, rpart, semi, nmask
+    const size_t v[Workspace::kBuffers] = {
+        mesh3, mesh3, include_mesh ? (size_t)n * sizeof(int32_t) : 0,
+        sizeof(Panel) * (size_t)n, sizeof(int64_t) * (size_t)n, sizeof(int64_t) * (size_t)(n + 1),
+        near4, near4,
+        (size_t)npad * npad * 8, low ? (size_t)npad * npad * 4 : 0, w, chol_panel_bytes(factor_dtype, npad), q,
+        (size_t)npad * m * 8, (size_t)npad * m * 8, low ? (size_t)npad * m * 8 : 0, low ? (size_t)npad * 8 : 0,
+        chunks_of(n) * m * m * 8, include_mesh ? sizeof(double) * m * m : 0, 64,
+        sizeof(double) * 2 * kMaxRhs, Workspace::sync_bytes(npad),
+        low ? (size_t)residual_splits((int)npad) * m * npad * 8 : 0, include_near ? near_semi_bytes(nnz) : 0,
+        sizeof(uint64_t) * (size_t)n * near_mask_words(n)};
+    std::array<size_t, Workspace::kBuffers> out;
+    for (int i = 0; i < Workspace::kBuffers; ++i) out[i] = page_round(v[i]);
+    return out;
 }
+// Device bytes one extraction holds at most in an empty workspace.
 static size_t footprint(int64_t n, int m, int factor_dtype)
 {
-    const int64_t nnz = std::min<int64_t>(n * 512, n * (n + 1) / 2);
-    return footprint_fixed(n, m, factor_dtype) +
-           (size_t)n * (2 * 3 * sizeof(double) + sizeof(int32_t)) + sizeof(double) * m * m +   // mesh copy, C
-           2 * sizeof(int32_t) * (size_t)nnz + near_semi_bytes(nnz);                        // near rows, cols, queue
+    size_t t = 0;
+    for (size_t b : buffer_needs(n, m, factor_dtype, true, true)) t += b;
+    return t;
+}
+// Bytes the workspace holds after a job with these needs: every buffer
+// ends at the larger of its current capacity and the job's need.
+static size_t grown_bytes(Workspace &ws, const std::array<size_t, Workspace::kBuffers> &need)
+{
+    size_t t = 0;
+    int i = 0;
+    ws.each([&](DevBuf &b) { t += std::max(b.cap, need[i++]); });
+    return t;
 }
 
 static gbem_status dev_fail(hipError_t e, const char *where)
@@ -676,7 +701,8 @@ struct gbem_job {
     int n = 0, m = 0;
     double eps_r = 1, lu = 1;
     gbem_opts opts{};
-    size_t need = 0;
+    size_t need = 0;                                  // footprint in an empty workspace
+    std::array<size_t, Workspace::kBuffers> needs{};   // per workspace buffer
     int state = 0;   // 0 queued, 1 running, 2 done
     gbem_status status = GBEM_OK;
     gbem_report rep{};
@@ -786,10 +812,12 @@ static void worker_main(gbem_ctx *ctx, Worker *w)
 }
 
 // Admission: the device memory held by all worker workspaces never exceeds
-// the budget.  A queued job goes to an idle worker when the worker's
-// workspace, grown to the job's footprint, still fits; idle workspaces are
-// released to make room.  Jobs that fit may pass a larger job at the head of
-// the queue for up to one second.
+// the budget (the near list aside, which is estimated before its size is
+// known).  A queued job goes to an idle worker when that worker's workspace,
+// each buffer grown to the job's need, fits beside what the other workers
+// hold (busy ones: their reservation; idle ones: their workspace); idle
+// workspaces are released to make room.  Jobs that fit may pass a larger job
+// at the head of the queue for up to one second.
 static void sched_main(gbem_ctx *ctx)
 {
     (void)hipSetDevice(ctx->device);
@@ -817,14 +845,16 @@ static void sched_main(gbem_ctx *ctx)
                 if (!w) break;
                 // idle workspaces are only touched by this thread; busy ones
                 // are bounded by what was recorded when they were dispatched
-                auto held_by_others = [&](bool count_idle) {
+                auto held_by_others = [&]() {
                     size_t t = 0;
                     for (Worker *c : ctx->workers)
-                        if (c != w) t += c->busy ? std::max(c->held, c->bytes) : (count_idle ? c->bytes : 0);
+                        if (c != w) t += c->busy ? std::max(c->held, c->bytes) : c->bytes;
                     return t;
                 };
-                size_t held_others = held_by_others(true);
-                size_t mine = std::max(w->bytes, j->need);
+                // what w's workspace will hold after the job: each buffer
+                // grows to the job's need or keeps its larger capacity
+                size_t held_others = held_by_others();
+                size_t mine = grown_bytes(w->ws, j->needs);
                 if (held_others + mine > ctx->budget) {
                     // free the idle workspaces without holding the lock (hipFree
                     // may wait for the device, and workers finishing a job need
@@ -837,8 +867,11 @@ static void sched_main(gbem_ctx *ctx)
                     for (Worker *c : idle) c->ws.release_all();
                     lk.lock();
                     for (Worker *c : idle) c->bytes = 0;
-                    held_others = held_by_others(false);
-                    mine = j->need;
+                    // a worker that finished while the lock was released is
+                    // idle now and holds its last job's workspace: count the
+                    // idle workers again (the ones just released hold nothing)
+                    held_others = held_by_others();
+                    mine = grown_bytes(w->ws, j->needs);
                     if (ctx->queue.size() <= qi || ctx->queue[qi] != j) break;   // the queue moved: rescan
                 }
                 if (held_others + mine <= ctx->budget) {
@@ -1077,7 +1110,8 @@ extern "C" gbem_status gbem_extract_device_noalloc(gbem_ctx *ctx, const gbem_mes
     const int64_t npad = round_up(n, kPad);
     // the buffers whose size the mesh fixes, for the requested factor and
     // every fallback level (the near list is checked once its size is known)
-    const size_t fixed = footprint_fixed(n, m, o.factor_dtype);
+    size_t fixed = 0;
+    for (size_t b : buffer_needs(n, m, o.factor_dtype, false, false)) fixed += b;
     if (npad > kNoAllocMaxPad || fixed > kNoAllocBytes) {
         set_error("gbem_extract_device_noalloc: a mesh of " + std::to_string(n) + " panels needs about " +
                   std::to_string(fixed >> 20) + " MiB of scratch; the no-allocation entry point has " +
@@ -1133,6 +1167,7 @@ extern "C" gbem_status gbem_submit(gbem_ctx *ctx, const gbem_mesh *mesh, const g
     j->eps_r = mesh->eps_r;
     j->lu = mesh->length_unit_m;
     j->opts = o;
+    j->needs = buffer_needs(j->n, j->m, o.factor_dtype, true, true);
     j->need = footprint(j->n, j->m, o.factor_dtype);
     if (j->need > ctx->budget) {
         delete j;

@@ -488,7 +488,7 @@ static size_t gemm_smem_bytes() { return (size_t)2 * 2 * kBK * kLdsLd * sizeof(T
 // access covers 16 consecutive rows.
 // Q16 (f32 only; 1: bf16, 2: f16): the tile is also written, rounded to 16
 // bits, row-major into Q (row stride qld): tile row R goes to Q row R + qrow
-// (skipped when negative), tile column c to Q column qcol + c.  The tile is
+// (skipped below qmin), tile column c to Q column qcol + c.  The tile is
 // transposed through LDS so that Q is written 16 bytes at a time.
 // One 128 x 128 tile (I, J) by the whole workgroup; smem: gemm_smem_bytes<T>()
 // bytes of LDS.  MASK: the tile lies on or below the diagonal of C's origin
@@ -496,7 +496,7 @@ static size_t gemm_smem_bytes() { return (size_t)2 * 2 * kBK * kLdsLd * sizeof(T
 template <typename T, bool MASK, bool SUB, int Q16 = 0>
 __device__ __forceinline__ void gemm_tile(int I, int J, int K, const T *A, int64_t lda, const T *B, int64_t ldb,
                                           T *C, int64_t ldc, void *Q, int qrow, int qcol, unsigned char *smem_raw,
-                                          int qld = 0)
+                                          int qld = 0, int qmin = 0)
 {
     typedef typename Mfma4<T>::acc_t acc_t;
     constexpr int LD = kLdsLd;
@@ -610,7 +610,7 @@ __device__ __forceinline__ void gemm_tile(int I, int J, int K, const T *A, int64
             for (int u = 0; u < 8; ++u) {
                 const int idx = tid + 256 * u, rl = idx >> 4, cc = (idx & 15) * 8;
                 const int64_t qr = (int64_t)I * kBM + rl + qrow;
-                if (qr >= 0)
+                if (qr >= qmin)
                     *reinterpret_cast<u4_t *>(reinterpret_cast<H *>(Q) + qr * qld + qcol + J * kBM + cc) =
                         *reinterpret_cast<const u4_t *>(t16 + rl * (kBM + 8) + cc);
             }
@@ -684,8 +684,9 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(int tm, int K, const T *A,
 // row block q" / "W_q" flags, holding the launch's epoch when published
 // (release after the stores, acquire after the flag: agent scope, since the
 // workgroups sit on different XCDs).  For 16-bit trailing updates the solve
-// also writes the 16-bit copy of the rows below the panel (row-major Q,
-// columns 128 j ..).
+// also writes the 16-bit copy of the rows below the panel: row-major Q with
+// row stride qld, panel row 128 q + r (q >= ns) to Q row 128 q + r - 128 ns +
+// qoff, column block j to Q columns qcol0 + 128 j ...
 // ------------------------------------------------------------------------
 __device__ __forceinline__ bool panel_wait(const int32_t *flag, int32_t epoch, int32_t *err, int limit)
 {
@@ -712,7 +713,8 @@ __device__ __forceinline__ void panel_publish(int32_t *flag, int32_t epoch)
 
 template <typename T, int Q16>
 __global__ __launch_bounds__(256) void panel_kernel(T *P, int64_t lda, int ns, T *W, int32_t *info, int kn0, void *Q,
-                                                    int32_t *pf, int32_t epoch, int limit)
+                                                    int qoff, int qcol0, int qld, int32_t *pf, int32_t epoch,
+                                                    int limit)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     __shared__ int ticket;
@@ -751,7 +753,7 @@ __global__ __launch_bounds__(256) void panel_kernel(T *P, int64_t lda, int ns, T
             if (!panel_wait(pf + 1 + ns + j, epoch, pf, limit)) return;
         }
         gemm_tile<T, false, false, Q16>(0, 0, kNB, C, lda, W + (int64_t)kNB * j * kNB, kNB, C, lda, Q,
-                                        (int)(r0 - kNB * ns), kNB * j, smem_raw, kNB * ns);
+                                        (int)(r0 - kNB * ns) + qoff, qcol0 + kNB * j, smem_raw, qld, qoff);
         __syncthreads();
     }
     if (q >= ns) return;
@@ -932,8 +934,9 @@ size_t chol_winv_bytes(int dtype, int64_t npad) { return (size_t)npad * kNB * el
 size_t chol_panel_bytes(int, int64_t) { return 64; }
 size_t chol_panel16_bytes(int dtype, int64_t npad)
 {
-    // two outer panels in flight (look-ahead): ping-pong buffers
-    return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)2 * npad * outer_width(npad) * 2 : 0;
+    // two super-panels (two outer panels each) in flight (look-ahead):
+    // ping-pong buffers of npad rows x 2 ow 16-bit values
+    return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)2 * npad * 2 * outer_width(npad) * 2 : 0;
 }
 
 template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
@@ -950,40 +953,39 @@ static hipError_t launch_gemm(int tm, int ntiles, int K, const T *A, int64_t lda
 }
 
 // Wd != nullptr: also factor the first diagonal block (DIAG0, kRect only)
+template <typename H, int MODE, int NK, bool D0>
+static hipError_t launch_syrk16_nk(int tm, int ntiles, int K, const H *QA, const H *QB, int64_t ldq, float *C,
+                                   int64_t ldc, hipStream_t s, float *Wd, int32_t *info, int k0)
+{
+    const size_t smem = std::max(syrk16_smem_bytes(), D0 ? diag_smem_bytes(sizeof(float)) : (size_t)0);
+    const void *fn = (const void *)syrk16_kernel<H, MODE, NK, D0>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((syrk16_kernel<H, MODE, NK, D0>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C,
+                       ldc, Wd, info, k0);
+    return hipGetLastError();
+}
+template <typename H, int MODE, bool D0>
+static hipError_t launch_syrk16_k(int tm, int ntiles, int K, const H *QA, const H *QB, int64_t ldq, float *C,
+                                  int64_t ldc, hipStream_t s, float *Wd, int32_t *info, int k0)
+{
+    switch (K) {
+    case 256: return launch_syrk16_nk<H, MODE, 4, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
+    case 512: return launch_syrk16_nk<H, MODE, 8, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
+    case 1024: return launch_syrk16_nk<H, MODE, 16, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
+    default: return hipErrorInvalidValue;
+    }
+}
 template <typename H, int MODE>
 static hipError_t launch_syrk16(int tm, int ntiles, int K, const H *QA, const H *QB, int64_t ldq, float *C,
                                 int64_t ldc, hipStream_t s, float *Wd = nullptr, int32_t *info = nullptr, int k0 = 0)
 {
-    const size_t smem = std::max(syrk16_smem_bytes(), Wd ? diag_smem_bytes(sizeof(float)) : (size_t)0);
-    if (K != 512 && K != 256) return hipErrorInvalidValue;
-    hipError_t e;
     if constexpr (MODE == kRect) {
-        if (Wd) {
-            const void *fn = K == 512 ? (const void *)syrk16_kernel<H, MODE, 8, true>
-                                      : (const void *)syrk16_kernel<H, MODE, 4, true>;
-            if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)) != hipSuccess)
-                return e;
-            if (K == 512)
-                hipLaunchKernelGGL((syrk16_kernel<H, MODE, 8, true>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB,
-                                   ldq, C, ldc, Wd, info, k0);
-            else
-                hipLaunchKernelGGL((syrk16_kernel<H, MODE, 4, true>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB,
-                                   ldq, C, ldc, Wd, info, k0);
-            return hipGetLastError();
-        }
+        if (Wd) return launch_syrk16_k<H, MODE, true>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
     } else if (Wd) {
         return hipErrorInvalidValue;
     }
-    const void *fn = K == 512 ? (const void *)syrk16_kernel<H, MODE, 8> : (const void *)syrk16_kernel<H, MODE, 4>;
-    if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem)) != hipSuccess) return e;
-    if (K == 512) {
-        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 8>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc,
-                           nullptr, nullptr, 0);
-    } else {
-        hipLaunchKernelGGL((syrk16_kernel<H, MODE, 4>), dim3(ntiles), dim3(256), smem, s, tm, K, QA, QB, ldq, C, ldc,
-                           nullptr, nullptr, 0);
-    }
-    return hipGetLastError();
+    return launch_syrk16_k<H, MODE, false>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, nullptr, nullptr, 0);
 }
 
 // Factor the outer panel at P0 (ow columns, rows P0 .. npad): diagonal
@@ -991,9 +993,11 @@ static hipError_t launch_syrk16(int tm, int ntiles, int K, const H *QA, const H 
 // then the rest of the panel in one launch.  info[1 .. 1 + 2 ns]:
 // error word and flags of panel_kernel.
 static std::atomic<int32_t> g_panel_epoch{0};
+// Q16 placement (16-bit updates): see panel_kernel (qoff, qcol0, qld)
 template <typename T, int Q16T>
 static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
-                               int64_t P0, hipStream_t s, Prof *prof, bool diag0_done)
+                               int64_t P0, hipStream_t s, Prof *prof, bool diag0_done, int qoff = 0, int qcol0 = 0,
+                               int qld = 0)
 {
     const double es = (double)sizeof(T);
     const int ns = ow / kNB;
@@ -1014,7 +1018,8 @@ static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv,
     const int32_t epoch = ++g_panel_epoch;
     tok = prof ? prof->start(s, GBEM_K_TRSM) : -1;
     hipLaunchKernelGGL((panel_kernel<T, Q16T>), dim3((unsigned)(m / kNB)), dim3(256), smem, s, A + P0 + P0 * lda,
-                       lda, ns, Winv + P0 * kNB, info, (int)P0, Q16, info + 1, epoch, 1 << 22);
+                       lda, ns, Winv + P0 * kNB, info, (int)P0, Q16, qoff, qcol0, qld > 0 ? qld : ow, info + 1,
+                       epoch, 1 << 22);
     if (prof) {
         double fl = 0.0, by = 0.0;
         for (int j = 0; j < ns; ++j) {
@@ -1031,71 +1036,161 @@ static hipError_t launch_panel(int64_t npad, int ow, T *A, int64_t lda, T *Winv,
 // updated the panel's columns
 template <typename T>
 static hipError_t factor_panel(int dtype, int64_t npad, int ow, T *A, int64_t lda, T *Winv, void *Q16,
-                               int32_t *info, int p, hipStream_t s, Prof *prof, bool diag0_done = false)
+                               int32_t *info, int p, hipStream_t s, Prof *prof, bool diag0_done = false,
+                               int qoff = 0, int qcol0 = 0, int qld = 0)
 {
     const int64_t P0 = (int64_t)p * ow;
     if (Q16 && dtype == GBEM_BF16)
-        return launch_panel<T, 1>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof, diag0_done);
+        return launch_panel<T, 1>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof, diag0_done, qoff, qcol0, qld);
     if (Q16 && dtype == GBEM_F16)
-        return launch_panel<T, 2>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof, diag0_done);
+        return launch_panel<T, 2>(npad, ow, A, lda, Winv, Q16, info, P0, s, prof, diag0_done, qoff, qcol0, qld);
     return launch_panel<T, 0>(npad, ow, A, lda, Winv, nullptr, info, P0, s, prof, diag0_done);
 }
 
 // Outer update of columns [c0, c0 + ncols) of the trailing matrix with the
-// outer panel at P0 (ow columns): C = A[c0.., c0..] (origin on the diagonal),
-// rows m = npad - c0.  TRI when the block is square.
-// Wd != nullptr (16-bit updates of a rectangular block only): the launch also
-// factors the diagonal block at C's origin (W into Wd, pivot status into info).
+// outer panel at P0 (ow columns, FP32 or FP64 storage): C = A[c0.., c0..]
+// (origin on the diagonal), rows m = npad - c0.  TRI when the block is square.
 template <typename T>
-static hipError_t outer_update(int dtype, int64_t npad, int ow, T *A, int64_t lda, int64_t P0, const void *Q16,
-                               int64_t c0, int64_t ncols, hipStream_t s, Prof *prof, int cls, T *Wd = nullptr,
-                               int32_t *info = nullptr)
+static hipError_t outer_update(int64_t npad, int ow, T *A, int64_t lda, int64_t P0, int64_t c0, int64_t ncols,
+                               hipStream_t s, Prof *prof, int cls)
 {
     const int64_t m = npad - c0;
     const int tm = (int)(m / kBM), tn = (int)(ncols / kBM);
-    // a square block takes the triangular tile grid, except when the launch
-    // also factors the diagonal block (rectangular grid; tiles above the
-    // diagonal return at once)
-    const bool tri = ncols == m && !Wd;
+    const bool tri = ncols == m;
     const int ntiles = tri ? tm * (tm + 1) / 2 : tm * tn;
     T *C = A + c0 + c0 * lda;
     const double es = (double)sizeof(T);
-    const bool b16 = dtype == GBEM_F16 || dtype == GBEM_BF16;
+    const double tiles_el = tri ? (double)tm * (tm + 1) / 2 * kBM * kBM : (double)m * ncols;
+    const int tok = prof ? prof->start(s, cls) : -1;
+    const T *Q = A + c0 + P0 * lda;   // L[c0:, P0:P0+ow], column-major
+    hipError_t e = tri ? launch_gemm<T, kTri, true, true>(tm, ntiles, ow, Q, lda, Q, lda, C, lda, s)
+                       : launch_gemm<T, kRect, true, true>(tm, ntiles, ow, Q, lda, Q, lda, C, lda, s);
+    if (prof) prof->stop(tok, cls, 2.0 * tiles_el * ow, 2.0 * tiles_el * es + (double)m * ow * es, s);
+    return e;
+}
+
+// 16-bit update of columns [c0, c0 + ncols) of the trailing matrix (origin
+// on the diagonal, rows m = npad - c0): C -= Q Q^T with Q the 16-bit copy of
+// the panel columns used (row-major, row stride ldq, K values per row, first
+// row = global row c0).  TRI when the block is square; Wd: the launch also
+// factors the diagonal block at C's origin (rectangular grid only).
+static hipError_t update16(int dtype, int64_t npad, float *A, int64_t lda, const void *Q, int64_t ldq, int K,
+                           int64_t c0, int64_t ncols, hipStream_t s, Prof *prof, int cls, float *Wd = nullptr,
+                           int32_t *info = nullptr)
+{
+    const int64_t m = npad - c0;
+    const int tm = (int)(m / kBM), tn = (int)(ncols / kBM);
+    const bool tri = ncols == m && !Wd;
+    const int ntiles = tri ? tm * (tm + 1) / 2 : tm * tn;
+    float *C = A + c0 + c0 * lda;
     const double tiles_el = tri ? (double)tm * (tm + 1) / 2 * kBM * kBM : (double)m * ncols;
     const int tok = prof ? prof->start(s, cls) : -1;
     hipError_t e;
-    if (!b16) {
-        const T *Q = A + c0 + P0 * lda;   // L[c0:, P0:P0+ow], column-major
-        e = tri ? launch_gemm<T, kTri, true, true>(tm, ntiles, ow, Q, lda, Q, lda, C, lda, s)
-                : launch_gemm<T, kRect, true, true>(tm, ntiles, ow, Q, lda, Q, lda, C, lda, s);
+    if (dtype == GBEM_BF16) {
+        const __bf16 *q = (const __bf16 *)Q;
+        e = tri ? launch_syrk16<__bf16, kTri>(tm, ntiles, K, q, q, ldq, C, lda, s)
+                : launch_syrk16<__bf16, kRect>(tm, ntiles, K, q, q, ldq, C, lda, s, Wd, info, (int)c0);
     } else {
-        const int64_t q0 = c0 - (P0 + ow);   // first row of Q16 used
-        float *W32 = (float *)Wd;
-        if (dtype == GBEM_BF16) {
-            const __bf16 *Q = (const __bf16 *)Q16 + q0 * ow;
-            e = tri ? launch_syrk16<__bf16, kTri>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s)
-                    : launch_syrk16<__bf16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s, W32, info, (int)c0);
-        } else {
-            const _Float16 *Q = (const _Float16 *)Q16 + q0 * ow;
-            e = tri ? launch_syrk16<_Float16, kTri>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s)
-                    : launch_syrk16<_Float16, kRect>(tm, ntiles, ow, Q, Q, ow, (float *)C, lda, s, W32, info,
-                                                     (int)c0);
-        }
+        const _Float16 *q = (const _Float16 *)Q;
+        e = tri ? launch_syrk16<_Float16, kTri>(tm, ntiles, K, q, q, ldq, C, lda, s)
+                : launch_syrk16<_Float16, kRect>(tm, ntiles, K, q, q, ldq, C, lda, s, Wd, info, (int)c0);
     }
     if (prof) {
-        double fl = 2.0 * tiles_el * ow, by = 2.0 * tiles_el * es + (double)m * ow * (b16 ? 2.0 : es);
-        if (Wd) fl += 2.0 * kNB * kNB * kNB / 3.0, by += 3.0 * kNB * kNB * es;   // the diagonal block
+        double fl = 2.0 * tiles_el * K, by = 2.0 * tiles_el * 4.0 + (double)m * K * 2.0;
+        if (Wd) fl += 2.0 * kNB * kNB * kNB / 3.0, by += 3.0 * kNB * kNB * 4.0;   // the diagonal block
         prof->stop(tok, cls, fl, by, s);
     }
     return e;
 }
 
+// Cholesky with 16-bit trailing updates on super-panels of two ow-wide outer
+// panels: the trailing matrix beyond a super-panel is updated once with
+// K = 2 ow (its FP32 read-modify-write traffic halves against one update per
+// panel), while the panel factorisations keep ow-wide panels.  Super-panel s
+// = panels 2s, 2s + 1 (the last may have one), columns from P0_s = 2 s ow.
+// Its 16-bit copy Q_s (ping-pong buffer s & 1, row stride 2 ow) holds row
+// R_s = P0_s + ow + i in row i: panel 2s in columns [0, ow) from row 0,
+// panel 2s + 1 in columns [ow, 2 ow) from row ow.
+//   side stream, super-panel s + 1 (after main finished its update with
+//   super-panel s - 1): its columns -= Q_s Q_s^T (K = 2 ow, the same launch
+//   factors the first diagonal block), factor panel 2s + 2; then panel
+//   2s + 3's columns -= its Q part (K = ow, first diagonal block again in the
+//   same launch) and factor panel 2s + 3;
+//   main stream (after the side stream factored super-panel s): the columns
+//   beyond super-panel s + 1 -= Q_s Q_s^T (K = 2 ow, lower triangle).
+static hipError_t factor16_t(int dtype, int64_t npad, float *A, int64_t lda, float *Winv, void *Q16, int32_t *info,
+                             hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
+{
+    const int ow = outer_width(npad), sw = 2 * ow;
+    const int nbo = (int)(npad / ow);
+    const int nsp = (nbo + 1) / 2;
+    hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<float, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)diag_smem_bytes(sizeof(float)));
+    if (e != hipSuccess) return e;
+    while ((int)ev.size() < 2 * nsp + 2) {   // evP[0..nsp), evB[0..nsp]
+        hipEvent_t x;
+        if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming | hipEventDisableSystemFence)) != hipSuccess) return e;
+        ev.push_back(x);
+    }
+    auto qbuf = [&](int sp) -> _Float16 * {   // 16-bit element type only sizes the pointer arithmetic
+        return (_Float16 *)Q16 + (size_t)(sp & 1) * npad * sw;
+    };
+    auto panels_in = [&](int sp) { return std::min(2, nbo - 2 * sp); };
+    // factor super-panel sp; its first panel's columns are up to date and,
+    // when d0, its first diagonal block already factored
+    auto factor_sp = [&](int sp, bool d0) -> hipError_t {
+        const int p0 = 2 * sp;
+        _Float16 *q = qbuf(sp);
+        hipError_t r;
+        if ((r = factor_panel<float>(dtype, npad, ow, A, lda, Winv, q, info, p0, side, prof, d0, 0, 0, sw)) !=
+            hipSuccess)
+            return r;
+        if (panels_in(sp) < 2) return hipSuccess;
+        // panel 2sp + 1's columns with panel 2sp (Q rows from R_sp), first diagonal block in the same launch
+        const int64_t c1 = (int64_t)(p0 + 1) * ow;
+        if ((r = update16(dtype, npad, A, lda, q, sw, ow, c1, ow, side, prof, GBEM_K_PANEL, Winv + c1 * kNB,
+                          info)) != hipSuccess)
+            return r;
+        return factor_panel<float>(dtype, npad, ow, A, lda, Winv, q, info, p0 + 1, side, prof, true, ow, ow, sw);
+    };
+    hipEvent_t *evP = ev.data(), *evB = ev.data() + nsp + 1;
+    if ((e = hipEventRecord(evB[nsp], s)) != hipSuccess) return e;   // inputs of this call are ready
+    if ((e = hipStreamWaitEvent(side, evB[nsp], 0)) != hipSuccess) return e;
+    if ((e = factor_sp(0, false)) != hipSuccess) return e;
+    if ((e = hipEventRecord(evP[0], side)) != hipSuccess) return e;
+    for (int sp = 0; sp + 1 < nsp; ++sp) {
+        const int64_t P0n = (int64_t)(2 * sp + 2) * ow;   // first column of super-panel sp + 1
+        const int64_t Rs = (int64_t)(2 * sp + 1) * ow;    // row 0 of Q_sp
+        // side: super-panel sp + 1's columns with super-panel sp (K = 2 ow), then factor it
+        if (sp > 0 && (e = hipStreamWaitEvent(side, evB[sp - 1], 0)) != hipSuccess) return e;
+        if ((e = update16(dtype, npad, A, lda, qbuf(sp) + (P0n - Rs) * sw, sw, sw, P0n,
+                          (int64_t)panels_in(sp + 1) * ow, side, prof, GBEM_K_PANEL, Winv + P0n * kNB, info)) !=
+            hipSuccess)
+            return e;
+        if ((e = factor_sp(sp + 1, true)) != hipSuccess) return e;
+        if ((e = hipEventRecord(evP[sp + 1], side)) != hipSuccess) return e;
+        // main: the columns beyond super-panel sp + 1 with super-panel sp
+        const int64_t c0 = P0n + (int64_t)panels_in(sp + 1) * ow;
+        if (c0 < npad) {
+            if ((e = hipStreamWaitEvent(s, evP[sp], 0)) != hipSuccess) return e;
+            if ((e = update16(dtype, npad, A, lda, qbuf(sp) + (c0 - Rs) * sw, sw, sw, c0, npad - c0, s, prof,
+                              GBEM_K_SYRK)) != hipSuccess)
+                return e;
+        }
+        if ((e = hipEventRecord(evB[sp], s)) != hipSuccess) return e;
+    }
+    if ((e = hipStreamWaitEvent(s, evP[nsp - 1], 0)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 // Right-looking Cholesky with ow-wide outer panels and one panel of
-// look-ahead: the side stream updates the next panel's columns and factors
-// it while the main stream applies the rest of the outer update.
+// look-ahead (FP32 and FP64 storage, trailing updates in the storage type):
+// the side stream updates the next panel's columns and factors it while the
+// main stream applies the rest of the outer update.
 template <typename T>
-static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, void *Q16, int32_t *info,
-                           hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
+static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, int32_t *info, hipStream_t s,
+                           hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
 {
     const int ow = outer_width(npad);
     const int nbo = (int)(npad / ow);
@@ -1107,10 +1202,6 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
         if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming | hipEventDisableSystemFence)) != hipSuccess) return e;
         ev.push_back(x);
     }
-    const bool b16 = dtype == GBEM_F16 || dtype == GBEM_BF16;
-    auto q16 = [&](int p) -> void * {
-        return b16 ? (void *)((char *)Q16 + (size_t)(p & 1) * npad * ow * 2) : nullptr;
-    };
     // Side stream: the latency-critical chain (update of the next panel's
     // columns, then its factorisation).  Main stream: the rest of each outer
     // update.  Events: evP[K] = panel K factored (side -> main), evB[K] =
@@ -1119,27 +1210,22 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
     hipEvent_t *evP = ev.data(), *evB = ev.data() + nbo + 1;
     if ((e = hipEventRecord(evB[nbo], s)) != hipSuccess) return e;   // inputs of this call are ready
     if ((e = hipStreamWaitEvent(side, evB[nbo], 0)) != hipSuccess) return e;
-    if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, q16(0), info, 0, side, prof)) != hipSuccess) return e;
+    if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, nullptr, info, 0, side, prof)) != hipSuccess) return e;
     if ((e = hipEventRecord(evP[0], side)) != hipSuccess) return e;
     for (int K = 0; K + 1 < nbo; ++K) {
         const int64_t P0 = (int64_t)K * ow;
         // side: (a) panel K+1's columns with panel K, then factor panel K+1
         if (K > 0 && (e = hipStreamWaitEvent(side, evB[K - 1], 0)) != hipSuccess) return e;
-        // 16-bit updates: the same launch factors panel K+1's first diagonal block
-        T *Wd = b16 ? Winv + (P0 + ow) * kNB : nullptr;
-        if ((e = outer_update<T>(dtype, npad, ow, A, lda, P0, q16(K), P0 + ow, ow, side, prof, GBEM_K_PANEL, Wd,
-                                 info)) != hipSuccess)
+        if ((e = outer_update<T>(npad, ow, A, lda, P0, P0 + ow, ow, side, prof, GBEM_K_PANEL)) != hipSuccess)
             return e;
-        if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, q16(K + 1), info, K + 1, side, prof, b16)) !=
-            hipSuccess)
+        if ((e = factor_panel<T>(dtype, npad, ow, A, lda, Winv, nullptr, info, K + 1, side, prof)) != hipSuccess)
             return e;
         if ((e = hipEventRecord(evP[K + 1], side)) != hipSuccess) return e;
         // main: (b) the columns beyond panel K+1 with panel K
         const int64_t c0 = P0 + 2 * ow;
         if (c0 < npad) {
             if ((e = hipStreamWaitEvent(s, evP[K], 0)) != hipSuccess) return e;
-            if ((e = outer_update<T>(dtype, npad, ow, A, lda, P0, q16(K), c0, npad - c0, s, prof, GBEM_K_SYRK)) !=
-                hipSuccess)
+            if ((e = outer_update<T>(npad, ow, A, lda, P0, c0, npad - c0, s, prof, GBEM_K_SYRK)) != hipSuccess)
                 return e;
         }
         if ((e = hipEventRecord(evB[K], s)) != hipSuccess) return e;
@@ -1153,8 +1239,10 @@ hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv
 {
     if (npad % outer_width(npad)) return hipErrorInvalidValue;
     if (dtype == GBEM_F64)
-        return factor_t<double>(dtype, npad, (double *)A, lda, (double *)Winv, nullptr, info, s, side, ev, prof);
-    return factor_t<float>(dtype, npad, (float *)A, lda, (float *)Winv, panel16, info, s, side, ev, prof);
+        return factor_t<double>(dtype, npad, (double *)A, lda, (double *)Winv, info, s, side, ev, prof);
+    if (dtype == GBEM_F16 || dtype == GBEM_BF16)
+        return factor16_t(dtype, npad, (float *)A, lda, (float *)Winv, panel16, info, s, side, ev, prof);
+    return factor_t<float>(dtype, npad, (float *)A, lda, (float *)Winv, info, s, side, ev, prof);
 }
 
 template <typename T>
