@@ -21,6 +21,7 @@
 #include "gbem_internal.h"
 
 #include <atomic>
+#include <cstdlib>
 #include <type_traits>
 
 namespace gbem {
@@ -932,11 +933,31 @@ static size_t elem_size(int dtype) { return dtype == GBEM_F64 ? 8 : 4; }
 
 size_t chol_winv_bytes(int dtype, int64_t npad) { return (size_t)npad * kNB * elem_size(dtype); }
 size_t chol_panel_bytes(int, int64_t) { return 64; }
+// Outer panels per super-panel of the 16-bit factorisation (the trailing
+// matrix beyond a super-panel is updated once, with K = that many panels).
+// Measured at the three-layer bus (order 59,904, mixed): 4 panels (K = 2048)
+// 199.8 ms per extraction against 217.2 ms with 2 (trailing update 109.5 vs
+// 130.4 ms, the look-ahead updates 36.2 vs 20.2 ms); at the crossing bus
+// (order 21,504) 2 panels stay ahead (25.25 vs 25.71 ms), the look-ahead
+// chain weighing more there.  GBEM_SUPER_PANELS (2 or 4) overrides the
+// default (read once).
+static int super_panels(int64_t npad)
+{
+    static const int forced = [] {
+        const char *e = getenv("GBEM_SUPER_PANELS");
+        const int x = e ? atoi(e) : 0;
+        return x == 2 || x == 4 ? x : 0;
+    }();
+    if (forced) return forced;
+    return npad >= 32768 ? 4 : 2;
+}
 size_t chol_panel16_bytes(int dtype, int64_t npad)
 {
-    // two super-panels (two outer panels each) in flight (look-ahead):
-    // ping-pong buffers of npad rows x 2 ow 16-bit values
-    return (dtype == GBEM_F16 || dtype == GBEM_BF16) ? (size_t)2 * npad * 2 * outer_width(npad) * 2 : 0;
+    // two super-panels in flight (look-ahead): ping-pong buffers of npad rows
+    // x (super-panel width) 16-bit values
+    return (dtype == GBEM_F16 || dtype == GBEM_BF16)
+               ? (size_t)2 * npad * super_panels(npad) * outer_width(npad) * 2
+               : 0;
 }
 
 template <typename T, int MODE, bool MASK, bool SUB, int Q16 = 0>
@@ -972,7 +993,10 @@ static hipError_t launch_syrk16_k(int tm, int ntiles, int K, const H *QA, const 
     switch (K) {
     case 256: return launch_syrk16_nk<H, MODE, 4, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
     case 512: return launch_syrk16_nk<H, MODE, 8, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
+    case 768: return launch_syrk16_nk<H, MODE, 12, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
     case 1024: return launch_syrk16_nk<H, MODE, 16, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
+    case 1536: return launch_syrk16_nk<H, MODE, 24, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
+    case 2048: return launch_syrk16_nk<H, MODE, 32, D0>(tm, ntiles, K, QA, QB, ldq, C, ldc, s, Wd, info, k0);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1079,8 +1103,8 @@ static hipError_t update16(int dtype, int64_t npad, float *A, int64_t lda, const
                            int32_t *info = nullptr)
 {
     const int64_t m = npad - c0;
-    const int tm = (int)(m / kBM), tn = (int)(ncols / kBM);
     const bool tri = ncols == m && !Wd;
+    const int tm = (int)(m / kBM), tn = (int)(ncols / kBM);
     const int ntiles = tri ? tm * (tm + 1) / 2 : tm * tn;
     float *C = A + c0 + c0 * lda;
     const double tiles_el = tri ? (double)tm * (tm + 1) / 2 * kBM * kBM : (double)m * ncols;
@@ -1103,27 +1127,28 @@ static hipError_t update16(int dtype, int64_t npad, float *A, int64_t lda, const
     return e;
 }
 
-// Cholesky with 16-bit trailing updates on super-panels of two ow-wide outer
-// panels: the trailing matrix beyond a super-panel is updated once with
-// K = 2 ow (its FP32 read-modify-write traffic halves against one update per
-// panel), while the panel factorisations keep ow-wide panels.  Super-panel s
-// = panels 2s, 2s + 1 (the last may have one), columns from P0_s = 2 s ow.
-// Its 16-bit copy Q_s (ping-pong buffer s & 1, row stride 2 ow) holds row
-// R_s = P0_s + ow + i in row i: panel 2s in columns [0, ow) from row 0,
-// panel 2s + 1 in columns [ow, 2 ow) from row ow.
+// Cholesky with 16-bit trailing updates on super-panels of P ow-wide outer
+// panels (P = super_panels): the trailing matrix beyond a super-panel is
+// updated once with K = P ow (its FP32 read-modify-write traffic falls as
+// 1 / P against one update per panel), while the panel factorisations keep
+// ow-wide panels.  Super-panel s = panels P s .. P s + P - 1 (the last may
+// have fewer), columns from P0_s = P s ow.  Its 16-bit copy Q_s (ping-pong
+// buffer s & 1, row stride P ow) holds global row R_s + i in row i, R_s =
+// P0_s + ow: panel P s + j in columns [j ow, (j + 1) ow) from row j ow on.
 //   side stream, super-panel s + 1 (after main finished its update with
-//   super-panel s - 1): its columns -= Q_s Q_s^T (K = 2 ow, the same launch
-//   factors the first diagonal block), factor panel 2s + 2; then panel
-//   2s + 3's columns -= its Q part (K = ow, first diagonal block again in the
-//   same launch) and factor panel 2s + 3;
+//   super-panel s - 1): its columns -= Q_s Q_s^T (K = P ow; the same launch
+//   factors the first diagonal block), factor its first panel; then for each
+//   further panel j of it, the panel's columns -= the Q_{s+1} columns of
+//   panels 0 .. j - 1 (K = j ow, first diagonal block in the same launch),
+//   and factor it;
 //   main stream (after the side stream factored super-panel s): the columns
-//   beyond super-panel s + 1 -= Q_s Q_s^T (K = 2 ow, lower triangle).
+//   beyond super-panel s + 1 -= Q_s Q_s^T (K = P ow, lower triangle).
 static hipError_t factor16_t(int dtype, int64_t npad, float *A, int64_t lda, float *Winv, void *Q16, int32_t *info,
                              hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
 {
-    const int ow = outer_width(npad), sw = 2 * ow;
+    const int ow = outer_width(npad), P = super_panels(npad), sw = P * ow;
     const int nbo = (int)(npad / ow);
-    const int nsp = (nbo + 1) / 2;
+    const int nsp = (nbo + P - 1) / P;
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<float, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)diag_smem_bytes(sizeof(float)));
@@ -1136,23 +1161,28 @@ static hipError_t factor16_t(int dtype, int64_t npad, float *A, int64_t lda, flo
     auto qbuf = [&](int sp) -> _Float16 * {   // 16-bit element type only sizes the pointer arithmetic
         return (_Float16 *)Q16 + (size_t)(sp & 1) * npad * sw;
     };
-    auto panels_in = [&](int sp) { return std::min(2, nbo - 2 * sp); };
+    auto panels_in = [&](int sp) { return std::min(P, nbo - P * sp); };
     // factor super-panel sp; its first panel's columns are up to date and,
     // when d0, its first diagonal block already factored
     auto factor_sp = [&](int sp, bool d0) -> hipError_t {
-        const int p0 = 2 * sp;
+        const int p0 = P * sp;
         _Float16 *q = qbuf(sp);
         hipError_t r;
         if ((r = factor_panel<float>(dtype, npad, ow, A, lda, Winv, q, info, p0, side, prof, d0, 0, 0, sw)) !=
             hipSuccess)
             return r;
-        if (panels_in(sp) < 2) return hipSuccess;
-        // panel 2sp + 1's columns with panel 2sp (Q rows from R_sp), first diagonal block in the same launch
-        const int64_t c1 = (int64_t)(p0 + 1) * ow;
-        if ((r = update16(dtype, npad, A, lda, q, sw, ow, c1, ow, side, prof, GBEM_K_PANEL, Winv + c1 * kNB,
-                          info)) != hipSuccess)
-            return r;
-        return factor_panel<float>(dtype, npad, ow, A, lda, Winv, q, info, p0 + 1, side, prof, true, ow, ow, sw);
+        for (int j = 1; j < panels_in(sp); ++j) {
+            // panel p0 + j's columns with panels p0 .. p0 + j - 1 (Q rows from
+            // global row cj), first diagonal block in the same launch
+            const int64_t cj = (int64_t)(p0 + j) * ow;
+            if ((r = update16(dtype, npad, A, lda, q + (size_t)(j - 1) * ow * sw, sw, j * ow, cj, ow, side, prof,
+                              GBEM_K_PANEL, Winv + cj * kNB, info)) != hipSuccess)
+                return r;
+            if ((r = factor_panel<float>(dtype, npad, ow, A, lda, Winv, q, info, p0 + j, side, prof, true, j * ow,
+                                         j * ow, sw)) != hipSuccess)
+                return r;
+        }
+        return hipSuccess;
     };
     hipEvent_t *evP = ev.data(), *evB = ev.data() + nsp + 1;
     if ((e = hipEventRecord(evB[nsp], s)) != hipSuccess) return e;   // inputs of this call are ready
@@ -1160,9 +1190,9 @@ static hipError_t factor16_t(int dtype, int64_t npad, float *A, int64_t lda, flo
     if ((e = factor_sp(0, false)) != hipSuccess) return e;
     if ((e = hipEventRecord(evP[0], side)) != hipSuccess) return e;
     for (int sp = 0; sp + 1 < nsp; ++sp) {
-        const int64_t P0n = (int64_t)(2 * sp + 2) * ow;   // first column of super-panel sp + 1
-        const int64_t Rs = (int64_t)(2 * sp + 1) * ow;    // row 0 of Q_sp
-        // side: super-panel sp + 1's columns with super-panel sp (K = 2 ow), then factor it
+        const int64_t P0n = (int64_t)P * (sp + 1) * ow;   // first column of super-panel sp + 1
+        const int64_t Rs = (int64_t)(P * sp + 1) * ow;    // row 0 of Q_sp
+        // side: super-panel sp + 1's columns with super-panel sp (K = P ow), then factor it
         if (sp > 0 && (e = hipStreamWaitEvent(side, evB[sp - 1], 0)) != hipSuccess) return e;
         if ((e = update16(dtype, npad, A, lda, qbuf(sp) + (P0n - Rs) * sw, sw, sw, P0n,
                           (int64_t)panels_in(sp + 1) * ow, side, prof, GBEM_K_PANEL, Winv + P0n * kNB, info)) !=
