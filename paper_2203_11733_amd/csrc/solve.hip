@@ -217,13 +217,13 @@ __global__ __launch_bounds__(256) void bwd_solve_kernel(const T *__restrict__ L,
 //             N_k = L_{k+1,k} W_k.
 // M_k and N_k are formed once per factor (solve_prep), so after the block a
 // workgroup waits for last has arrived only one 128 x 128 product remains;
-// everything else overlaps the wait.  Right-hand sides are solved in
-// independent chains of 16 columns (the columns never mix), each block of
-// each chain by one workgroup.  Per workgroup:
-//   - W_k stays in LDS and M_k / N_k in registers from the start; the L
-//     blocks stream through a second LDS tile, the next one loaded into
-//     registers while the MFMAs work on the current one, so nothing on the
-//     path after a published block waits for HBM;
+// everything else overlaps the wait.  One workgroup per block solves every
+// right-hand side (MC = 16 NCB >= m columns), so L is streamed once per
+// direction whatever the conductor count.  Per workgroup:
+//   - W_k and M_k / N_k wait in registers from the start and go through the
+//     LDS tile buffer once the dependency stream is over; the L blocks stream
+//     through that buffer, the next one loaded into registers while the MFMAs
+//     work on the current one;
 //   - each wave owns 32 rows of the block, so the products need no
 //     cross-wave reduction;
 //   - a finished block is published as 64-bit words (value bits, epoch) with
@@ -231,23 +231,23 @@ __global__ __launch_bounds__(256) void bwd_solve_kernel(const T *__restrict__ L,
 //     consumers load the words with agent-scope atomic loads and re-load the
 //     ones whose epoch is stale.  Data and readiness travel together, so there
 //     is no separate flag and no store-completion wait before one.
-// Word layout of a published block (128 x 16 values): word w = R * 256 +
-// q * 64 + l holds row 16 R + 4 (l / 16) + q, column l % 16 (the MFMA output
-// layout of the producing wave, so each store instruction covers 512
-// contiguous bytes).
-// LDS: two 128-row tiles of stride TLD (FWD 144, BWD 132: conflict-free
-// fragment reads in either orientation) and two 128 x 16 right-operand
-// buffers; in FWD those sit in the last 16 floats of each tile row, which the
-// tiles leave free, so the layout fits the 160 KB of a CU.
+// Word layout of a published block (128 x MC values): word
+// ((R NCB + cb) 4 + q) 64 + l holds row 16 R + 4 (l / 16) + q, column
+// 16 cb + l % 16 (the MFMA output layout of the producing wave, so each store
+// instruction covers 512 contiguous bytes).
+// LDS: the tile (row stride TLD: FWD 144, BWD 132, conflict-free fragment
+// reads in either orientation) and two 128 x MC right-operand buffers (row
+// stride YLD: the four rows a fragment read touches fall on distinct banks).
 // ------------------------------------------------------------------------
-constexpr int kChain = 16;   // right-hand sides per chain
-template <bool FWD> struct SolveCfg {
+template <bool FWD, int NCB> struct SolveCfg {
+    static constexpr int MC = 16 * NCB;               // right-hand sides per workgroup
     static constexpr int RB = 2;                      // 16-row blocks per wave
-    static constexpr int NW = 8;                      // published words per thread
+    static constexpr int NW = MC / 2;                 // published words per thread (128 MC / 256)
     static constexpr int TLD = FWD ? 144 : 132;       // LDS tile stride
-    static constexpr int YLD = FWD ? 144 : 16;        // right-operand stride
+    static constexpr int YLD = MC == 64 ? 80 : (MC == 32 ? 48 : MC);   // right-operand stride
     static constexpr size_t kTileBytes = (size_t)kNB * TLD * 4;
-    static constexpr size_t kSmem = 2 * kTileBytes + (FWD ? 0 : (size_t)2 * kNB * kChain * 4);
+    static constexpr size_t kYBytes = (size_t)kNB * YLD * 4;
+    static constexpr size_t kSmem = kTileBytes + 2 * kYBytes;
 };
 typedef float f4s_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u4s_t __attribute__((ext_vector_type(4)));
@@ -270,46 +270,53 @@ __device__ __forceinline__ void tile_store(float *tile, const u4s_t (&tr)[16])
     for (int q = 0; q < 16; ++q) dst[q] = tr[q];
 }
 
-// acc[rb] += A(i, t) Y(t, n) over t = 0..127 for the wave's rows
+// acc[rb][cb] += A(i, t) Y(t, n) over t = 0..127 for the wave's rows
 // i = 32 w + 16 rb + ..; A(i, t) = tile[t*TLD + i] (FWD: L_kj, W_k, M_k) or
-// tile[i*TLD + t] (BWD: L_jk^T, W_k^T, N_k^T); Y(t, n) = ys[t*YLD + n]
-template <bool FWD>
-__device__ __forceinline__ void tile_product(f4s_t (&acc)[2], const float *tile, const float *ys)
+// tile[i*TLD + t] (BWD: L_jk^T, W_k^T, N_k^T); Y(t, n) = ys[t*YLD + n],
+// n = 16 cb + ..
+template <bool FWD, int NCB>
+__device__ __forceinline__ void tile_product(f4s_t (&acc)[2][NCB], const float *tile, const float *ys)
 {
-    typedef SolveCfg<FWD> C;
+    typedef SolveCfg<FWD, NCB> C;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll 4
     for (int kk = 0; kk < kNB; kk += 4) {
         const int t = kk + (lane >> 4);
-        const float b = ys[t * C::YLD + (lane & 15)];
+        float b[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = ys[t * C::YLD + cb * 16 + (lane & 15)];
 #pragma unroll
         for (int rb = 0; rb < C::RB; ++rb) {
             const int i = (w * C::RB + rb) * 16 + (lane & 15);
             const float a = FWD ? tile[t * C::TLD + i] : tile[i * C::TLD + t];
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[rb], 0, 0, 0);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[cb], acc[rb][cb], 0, 0, 0);
         }
     }
 }
 
 // Issue the loads of this thread's words (w = tid + 256 u) of a published block.
-__device__ __forceinline__ void pub_issue(uint64_t (&wd)[8], const uint64_t *blk)
+template <int NW>
+__device__ __forceinline__ void pub_issue(uint64_t (&wd)[NW], const uint64_t *blk)
 {
     const uint64_t *p = blk + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) wd[u] = __hip_atomic_load(p + 256 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int u = 0; u < NW; ++u) wd[u] = __hip_atomic_load(p + 256 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Complete the loads of a block: when some word is stale, one thread polls
 // word 0 until it carries `tag` (a waiting workgroup then adds one load per
 // poll to the memory system, not the whole block), after which the stale
 // words are re-loaded until all carry `tag`.  Bounded; returns the same value
 // in every thread (false after a timeout, with the error word set).
-__device__ __forceinline__ bool pub_complete(uint64_t (&wd)[8], const uint64_t *blk, uint32_t tag, int32_t *err,
+template <int NW>
+__device__ __forceinline__ bool pub_complete(uint64_t (&wd)[NW], const uint64_t *blk, uint32_t tag, int32_t *err,
                                              int limit)
 {
     const uint64_t *p = blk + threadIdx.x;
     bool good = true;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) good = good && (uint32_t)(wd[u] >> 32) == tag;
+    for (int u = 0; u < NW; ++u) good = good && (uint32_t)(wd[u] >> 32) == tag;
     if (!__syncthreads_or(!good)) return true;
     if (threadIdx.x == 0) {
         for (int n = 0; n < limit; ++n) {
@@ -320,98 +327,103 @@ __device__ __forceinline__ bool pub_complete(uint64_t (&wd)[8], const uint64_t *
     __syncthreads();
     for (int n = 0;; ++n) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < NW; ++u)
             if ((uint32_t)(wd[u] >> 32) != tag)
                 wd[u] = __hip_atomic_load(p + 256 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         good = true;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) good = good && (uint32_t)(wd[u] >> 32) == tag;
+        for (int u = 0; u < NW; ++u) good = good && (uint32_t)(wd[u] >> 32) == tag;
         if (good || n >= limit) break;
         __builtin_amdgcn_s_sleep(2);
     }
     if (!good) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return !__syncthreads_or(!good);
 }
-// words -> ys[row * YLD + col] (FP32)
-template <bool FWD>
-__device__ __forceinline__ void pub_to_lds(float *ys, const uint64_t (&wd)[8])
+// words -> ys[row * YLD + col] (FP32): word t + 256 u is (R, cb) = (u / NCB,
+// u % NCB), q = wave, l = lane
+template <bool FWD, int NCB>
+__device__ __forceinline__ void pub_to_lds(float *ys, const uint64_t (&wd)[SolveCfg<FWD, NCB>::NW])
 {
+    typedef SolveCfg<FWD, NCB> C;
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-        ys[(u * 16 + 4 * (lane >> 4) + q) * SolveCfg<FWD>::YLD + (lane & 15)] = __uint_as_float((uint32_t)wd[u]);
+    for (int u = 0; u < C::NW; ++u) {
+        const int R = u / NCB, cb = u % NCB;
+        ys[(R * 16 + 4 * (lane >> 4) + q) * C::YLD + cb * 16 + (lane & 15)] = __uint_as_float((uint32_t)wd[u]);
+    }
 }
 
-// One workgroup per (block, chain).  Ticket t -> block t / nch in solve order,
-// chain t % nch (columns 16 c ..); Y holds the published words of chain c at
-// Y + c * npad * 16.
-template <bool FWD>
+// One workgroup per block (every right-hand side).  Ticket t -> block t in
+// solve order; Y holds the published words, block k at Y + k * 128 * MC.
+template <bool FWD, int NCB>
 __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__ L, int64_t lda,
                                                        const float *__restrict__ W, const float *__restrict__ S,
-                                                       double *B, int64_t ldb, uint64_t *Y, int m, int nb, int nch,
+                                                       double *B, int64_t ldb, uint64_t *Y, int m, int nb,
                                                        int32_t *__restrict__ counter, uint32_t base, uint32_t tag,
                                                        int32_t *err, int limit)
 {
-    typedef SolveCfg<FWD> C;
+    typedef SolveCfg<FWD, NCB> C;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    float *tile = reinterpret_cast<float *>(smem_raw);                  // streaming L blocks, then M_k / N_k
-    float *wtile = reinterpret_cast<float *>(smem_raw + C::kTileBytes);   // W_k
-    float *ys0 = FWD ? tile + kNB : reinterpret_cast<float *>(smem_raw + 2 * C::kTileBytes);
-    float *ys1 = FWD ? wtile + kNB : ys0 + kNB * kChain;
-    const int t = take_ticket(counter, base);
-    if (t < 0 || t >= nb * nch) {
+    float *tile = reinterpret_cast<float *>(smem_raw);                     // L blocks, then W_k, then M_k / N_k
+    float *ys0 = reinterpret_cast<float *>(smem_raw + C::kTileBytes);
+    float *ys1 = reinterpret_cast<float *>(smem_raw + C::kTileBytes + C::kYBytes);
+    const int tk = take_ticket(counter, base);
+    if (tk < 0 || tk >= nb) {
         if (threadIdx.x == 0) __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    const int tk = t / nch, ch = t % nch;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // solve order: FWD blocks 0, 1, ..; BWD blocks nb-1, nb-2, ..
     const int k = FWD ? tk : nb - 1 - tk, k0 = k * kNB;
     const int cnt = tk;                      // blocks this one depends on
     const int nn = cnt > 0 ? cnt - 1 : 0;    // all but the last of them
-    const int mc = min(kChain, m - ch * kChain);   // columns of this chain
-    B += (int64_t)ch * kChain * ldb;
-    Y += (int64_t)ch * nb * kNB * kChain;
+    constexpr int BW = kNB * C::MC;          // words per published block
     auto jof = [&](int idx) { return FWD ? idx : nb - 1 - idx; };
-    auto pblk = [&](int idx) { return Y + (int64_t)jof(idx) * kNB * kChain; };
+    auto pblk = [&](int idx) { return Y + (int64_t)jof(idx) * BW; };
     auto lsrc = [&](int idx) {   // L_kj (FWD) or L_jk (BWD) of the idx-th dependency
         const int j = jof(idx);
         return FWD ? L + k0 + (int64_t)j * kNB * lda : L + (int64_t)j * kNB + (int64_t)k0 * lda;
     };
-    // element (rb, q) of this thread: row within the block; column lane % 16
+    // element (rb, q) of this thread: row within the block; column 16 cb + lane % 16
     auto erow = [&](int rb, int q) { return (wave * C::RB + rb) * 16 + 4 * (lane >> 4) + q; };
     const int col = lane & 15;
 
-    double bk[C::RB][4];
+    double bk[C::RB][NCB][4];
 #pragma unroll
     for (int rb = 0; rb < C::RB; ++rb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bk[rb][q] = col < mc ? B[(k0 + erow(rb, q)) + (int64_t)col * ldb] : 0.0;
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                bk[rb][cb][q] = cb * 16 + col < m ? B[(k0 + erow(rb, q)) + (int64_t)(cb * 16 + col) * ldb] : 0.0;
 
-    u4s_t tr[16], sr[16];
-    tile_load(tr, W + (int64_t)k * kNB * kNB, kNB);
+    u4s_t tr[16], wr[16], sr[16];
+    tile_load(wr, W + (int64_t)k * kNB * kNB, kNB);
     if (cnt > 0) tile_load(sr, S + (int64_t)k * kNB * kNB, kNB);
-    tile_store<C::TLD>(wtile, tr);
     if (nn > 0) tile_load(tr, lsrc(0), lda);
 
-    f4s_t acc[2] = {f4s_t{0.f, 0.f, 0.f, 0.f}, f4s_t{0.f, 0.f, 0.f, 0.f}};
-    uint64_t wd[8];
+    f4s_t acc[2][NCB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
+    uint64_t wd[C::NW];
     if (nn > 0) {
-        pub_issue(wd, pblk(0));
-        if (!pub_complete(wd, pblk(0), tag, err, limit)) return;
-        pub_to_lds<FWD>(ys0, wd);
+        pub_issue<C::NW>(wd, pblk(0));
+        if (!pub_complete<C::NW>(wd, pblk(0), tag, err, limit)) return;
+        pub_to_lds<FWD, NCB>(ys0, wd);
         tile_store<C::TLD>(tile, tr);
         if (nn > 1) tile_load(tr, lsrc(1), lda);
         __syncthreads();
         for (int idx = 0; idx < nn; ++idx) {
             const bool more = idx + 1 < nn;
-            if (more) pub_issue(wd, pblk(idx + 1));
-            tile_product<FWD>(acc, tile, (idx & 1) ? ys1 : ys0);
+            if (more) pub_issue<C::NW>(wd, pblk(idx + 1));
+            tile_product<FWD, NCB>(acc, tile, (idx & 1) ? ys1 : ys0);
             if (!more) break;
-            if (!pub_complete(wd, pblk(idx + 1), tag, err, limit)) return;
+            if (!pub_complete<C::NW>(wd, pblk(idx + 1), tag, err, limit)) return;
             __syncthreads();
             tile_store<C::TLD>(tile, tr);
-            pub_to_lds<FWD>(((idx + 1) & 1) ? ys1 : ys0, wd);
+            pub_to_lds<FWD, NCB>(((idx + 1) & 1) ? ys1 : ys0, wd);
             if (idx + 2 < nn) tile_load(tr, lsrc(idx + 2), lda);
             __syncthreads();
         }
@@ -419,41 +431,54 @@ __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__
     __syncthreads();   // the last product is done with tile, ys0 and ys1
     // Z = W_k (B_k - acc): the difference goes through LDS as the right operand
 #pragma unroll
-    for (int rb = 0; rb < C::RB; ++rb) {
+    for (int rb = 0; rb < C::RB; ++rb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ys0[erow(rb, q) * C::YLD + col] = (float)(bk[rb][q] - (double)acc[rb][q]);
-        acc[rb] = f4s_t{0.f, 0.f, 0.f, 0.f};
-    }
-    if (cnt > 0) {
-        tile_store<C::TLD>(tile, sr);   // M_k / N_k
-        pub_issue(wd, pblk(cnt - 1));   // the last dependency, completed after the product
-    }
+        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ys0[erow(rb, q) * C::YLD + cb * 16 + col] = (float)(bk[rb][cb][q] - (double)acc[rb][cb][q]);
+            acc[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
+        }
+    tile_store<C::TLD>(tile, wr);
+    if (cnt > 0) pub_issue<C::NW>(wd, pblk(cnt - 1));   // the last dependency, completed after the product
     __syncthreads();
-    tile_product<FWD>(acc, wtile, ys0);
+    tile_product<FWD, NCB>(acc, tile, ys0);
     if (cnt > 0) {
         // Y_k = Z - M_k Y_{k-1} (FWD) or X_k = Z - N_k^T X_{k+1} (BWD)
-        if (!pub_complete(wd, pblk(cnt - 1), tag, err, limit)) return;
-        pub_to_lds<FWD>(ys1, wd);
+        __syncthreads();   // every wave is done with W_k in the tile
+        tile_store<C::TLD>(tile, sr);
+        if (!pub_complete<C::NW>(wd, pblk(cnt - 1), tag, err, limit)) return;
+        pub_to_lds<FWD, NCB>(ys1, wd);
         __syncthreads();
-        f4s_t acc2[2] = {f4s_t{0.f, 0.f, 0.f, 0.f}, f4s_t{0.f, 0.f, 0.f, 0.f}};
-        tile_product<FWD>(acc2, tile, ys1);
-        acc[0] -= acc2[0];
-        acc[1] -= acc2[1];
+        f4s_t acc2[2][NCB];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc2[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
+        tile_product<FWD, NCB>(acc2, tile, ys1);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] -= acc2[rb][cb];
     }
     // publish, then the FP64 result
-    uint64_t *yk = Y + (int64_t)k * kNB * kChain;
+    uint64_t *yk = Y + (int64_t)k * BW;
 #pragma unroll
     for (int rb = 0; rb < C::RB; ++rb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            __hip_atomic_store(yk + (wave * C::RB + rb) * 256 + q * 64 + lane,
-                               ((uint64_t)tag << 32) | __float_as_uint(acc[rb][q]), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                __hip_atomic_store(yk + (((wave * C::RB + rb) * NCB + cb) * 4 + q) * 64 + lane,
+                                   ((uint64_t)tag << 32) | __float_as_uint(acc[rb][cb][q]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
     for (int rb = 0; rb < C::RB; ++rb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (col < mc) B[(k0 + erow(rb, q)) + (int64_t)col * ldb] = (double)acc[rb][q];
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (cb * 16 + col < m) B[(k0 + erow(rb, q)) + (int64_t)(cb * 16 + col) * ldb] = (double)acc[rb][cb][q];
 }
 
 // M_k = W_k L_{k,k-1} (k = 1 .. nb-1, slot k of S) and N_k = L_{k+1,k} W_k
@@ -519,33 +544,35 @@ __global__ __launch_bounds__(256) void solve_prep_kernel(const float *__restrict
     }
 }
 
-static hipError_t solve32(int64_t npad, const float *L, int64_t lda, const float *W, int m, double *B, int64_t ldb,
-                          SolveSync &sync, hipStream_t s, Prof *prof)
+template <int NCB>
+static hipError_t solve32_n(int64_t npad, const float *L, int64_t lda, const float *W, int m, double *B, int64_t ldb,
+                            SolveSync &sync, hipStream_t s, Prof *prof)
 {
     const int nb = (int)(npad / kNB);
-    const int nch = (m + kChain - 1) / kChain;
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void *)tsolve32_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)SolveCfg<true>::kSmem)) != hipSuccess ||
-        (e = hipFuncSetAttribute((const void *)tsolve32_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)SolveCfg<false>::kSmem)) != hipSuccess)
+    if ((e = hipFuncSetAttribute((const void *)tsolve32_kernel<true, NCB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)SolveCfg<true, NCB>::kSmem)) != hipSuccess ||
+        (e = hipFuncSetAttribute((const void *)tsolve32_kernel<false, NCB>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)SolveCfg<false, NCB>::kSmem)) !=
+            hipSuccess)
         return e;
     const int limit = 1 << 22;
     ++sync.epoch;
     const uint32_t tag = (uint32_t)sync.epoch;
     uint64_t *Yf = sync.pub, *Yb = sync.pub + (size_t)npad * kMaxPub;
-    const unsigned grid = (unsigned)(nb * nch);
+    const unsigned grid = (unsigned)nb;
     const int tok = prof ? prof->start(s, GBEM_K_SOLVE) : -1;
-    hipLaunchKernelGGL(tsolve32_kernel<true>, dim3(grid), dim3(256), SolveCfg<true>::kSmem, s, L, lda, W,
-                       (const float *)sync.sub, B, ldb, Yf, m, nb, nch, sync.err + 1, sync.base_f, tag, sync.err,
-                       limit);
-    hipLaunchKernelGGL(tsolve32_kernel<false>, dim3(grid), dim3(256), SolveCfg<false>::kSmem, s, L, lda, W,
-                       (const float *)sync.sub + npad * kNB, B, ldb, Yb, m, nb, nch, sync.err + 2, sync.base_b, tag,
+    hipLaunchKernelGGL((tsolve32_kernel<true, NCB>), dim3(grid), dim3(256), (SolveCfg<true, NCB>::kSmem), s, L, lda, W,
+                       (const float *)sync.sub, B, ldb, Yf, m, nb, sync.err + 1, sync.base_f, tag, sync.err, limit);
+    hipLaunchKernelGGL((tsolve32_kernel<false, NCB>), dim3(grid), dim3(256), (SolveCfg<false, NCB>::kSmem), s, L, lda,
+                       W, (const float *)sync.sub + npad * kNB, B, ldb, Yb, m, nb, sync.err + 2, sync.base_b, tag,
                        sync.err, limit);
     if (prof) {
+        // L once per direction, W and M/N per block, B read/written, published blocks read by every later block
         const double lbytes = (double)npad * (npad + kNB) / 2.0 * 4.0;
+        const double pub = (double)nb * (nb - 1) / 2.0 * kNB * 16 * NCB * 8.0;
         prof->stop(tok, GBEM_K_SOLVE, 2.0 * 2.0 * (double)npad * npad / 2.0 * m,
-                   2.0 * nch * lbytes + 4.0 * nch * npad * kNB * 4.0 + 4.0 * npad * m * 8.0, s, 2);
+                   2.0 * lbytes + 4.0 * npad * kNB * 4.0 + 4.0 * npad * m * 8.0 + 2.0 * pub, s, 2);
     }
     e = hipGetLastError();
     if (e == hipSuccess) {   // each launch consumes exactly grid tickets
@@ -553,6 +580,15 @@ static hipError_t solve32(int64_t npad, const float *L, int64_t lda, const float
         sync.base_b += grid;
     }
     return e;
+}
+
+static hipError_t solve32(int64_t npad, const float *L, int64_t lda, const float *W, int m, double *B, int64_t ldb,
+                          SolveSync &sync, hipStream_t s, Prof *prof)
+{
+    if (m <= 16) return solve32_n<1>(npad, L, lda, W, m, B, ldb, sync, s, prof);
+    if (m <= 32) return solve32_n<2>(npad, L, lda, W, m, B, ldb, sync, s, prof);
+    if (m <= 48) return solve32_n<3>(npad, L, lda, W, m, B, ldb, sync, s, prof);
+    return solve32_n<4>(npad, L, lda, W, m, B, ldb, sync, s, prof);
 }
 
 template <typename T, int MC>
@@ -744,6 +780,8 @@ hipError_t launch_residual(const double *A, int64_t lda, int npad, const double 
         hipLaunchKernelGGL(residual_partial_kernel<16>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
     else if (m <= 32)
         hipLaunchKernelGGL(residual_partial_kernel<32>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
+    else if (m <= 48)   // FP64 MFMA work grows with the padded width: 48 saves a quarter against 64
+        hipLaunchKernelGGL(residual_partial_kernel<48>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
     else
         hipLaunchKernelGGL(residual_partial_kernel<64>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
     hipLaunchKernelGGL(residual_finish_kernel, dim3((npad + 255) / 256, m), dim3(256), 0, st, partial, ns, npad, m, B,
