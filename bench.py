@@ -526,6 +526,9 @@ def main():
         "C_rel_err_vs_f64": err,
         "refine_iters": r_last["refine_iters"], "residual": r_last["residual"],
         "factor_used": r_last["factor_used"],
+        "tile_shapes": {"outer_width": r_last["outer_width"], "super_panels": r_last["super_panels"],
+                        "source": os.path.relpath(binding.tuning_source(), ROOT)
+                        if os.path.isabs(binding.tuning_source()) else binding.tuning_source()},
         "stage_ms": stage,
         "f64": f64,
         "kernel_ms_per_step": {c: d["ms"] / args.steps for c, d in sorted(profile.items(), key=lambda kv: -kv[1]["ms"])},

@@ -133,7 +133,32 @@ typedef struct {
     int64_t prof_launches[GBEM_K_COUNT];
     double prof_flops[GBEM_K_COUNT];     /* algorithmic floating-point operations */
     double prof_bytes[GBEM_K_COUNT];     /* algorithmic HBM bytes (compulsory reads + writes) */
+    int32_t outer_width;        /* tile shapes the factorisation used (see gbem_tuning) */
+    int32_t super_panels;
 } gbem_report;
+
+/* Tile shapes of the Cholesky factorisation (schedule only: results do not
+ * depend on them beyond rounding order).  outer_width: columns per outer
+ * panel, 256 or 512.  super_panels: outer panels per trailing update of the
+ * 16-bit factors, 2 or 4 (K = super_panels * outer_width).  The library picks
+ * them per padded matrix order and factor dtype from a cache written by the
+ * project's autotuner (paper_2203_11733_amd/autotune.py, which times every
+ * candidate on the GPU): tune_gfx950.json next to the library, or the file
+ * named by GBEM_TUNE_FILE, read when the first context is created; without
+ * a cache, built-in defaults apply. */
+typedef struct {
+    int32_t outer_width;
+    int32_t super_panels;
+} gbem_tuning;
+/* Replace the shape cache with the file at path (process-wide; NULL: back to
+ * the built-in defaults).  GBEM_EINVAL when the file is missing or malformed
+ * (the previous cache stays). */
+gbem_status gbem_load_tuning(const char *path);
+/* Force shapes for every later factorisation in the process (fields 0: from
+ * the cache); t = NULL clears the override.  Used by the autotuner. */
+gbem_status gbem_set_tuning_override(const gbem_tuning *t);
+/* Where the current shapes come from (a path or "built-in defaults"). */
+const char *gbem_tuning_source(void);
 
 /* Version string of the library. */
 const char *gbem_version(void);

@@ -27,7 +27,7 @@ EXPORTS = [
     "gbem_job_free", "gbem_server_stats", "gbem_mesh_boxes", "gbem_mesh_buf_free", "gbem_near_list",
     "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
     "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
-    "gbem_extract_device_noalloc",
+    "gbem_extract_device_noalloc", "gbem_load_tuning", "gbem_set_tuning_override", "gbem_tuning_source",
 ]
 
 
@@ -57,7 +57,8 @@ class Report(ctypes.Structure):
                 ("refine_iters", ctypes.c_int32), ("factor_used", ctypes.c_int32),
                 ("n_near", ctypes.c_int64), ("n_panels", ctypes.c_int64),
                 ("prof_ms", ctypes.c_double * NCLS), ("prof_launches", ctypes.c_int64 * NCLS),
-                ("prof_flops", ctypes.c_double * NCLS), ("prof_bytes", ctypes.c_double * NCLS)]
+                ("prof_flops", ctypes.c_double * NCLS), ("prof_bytes", ctypes.c_double * NCLS),
+                ("outer_width", ctypes.c_int32), ("super_panels", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -70,6 +71,28 @@ class Report(ctypes.Structure):
         for k in ("prof_ms", "prof_launches", "prof_flops", "prof_bytes"):
             del d[k]
         return d
+
+
+class Tuning(ctypes.Structure):
+    """Tile shapes of the factorisation (gbem_tuning)."""
+    _fields_ = [("outer_width", ctypes.c_int32), ("super_panels", ctypes.c_int32)]
+
+
+def load_tuning(path: str | None):
+    """Replace the process-wide shape cache (None: built-in defaults)."""
+    lib = load()
+    _check(lib.gbem_load_tuning(path.encode() if path else None))
+
+
+def set_tuning_override(outer_width: int = 0, super_panels: int = 0):
+    """Force shapes for later factorisations (0: from the cache)."""
+    lib = load()
+    t = Tuning(outer_width, super_panels)
+    _check(lib.gbem_set_tuning_override(ctypes.byref(t) if (outer_width or super_panels) else None))
+
+
+def tuning_source() -> str:
+    return load().gbem_tuning_source().decode()
 
 
 class MeshRule(ctypes.Structure):
@@ -112,6 +135,9 @@ def load():
                                         ctypes.POINTER(Report)]
     lib.gbem_extract_device_noalloc.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), _vp, _vp,
                                                 ctypes.POINTER(Report)]
+    lib.gbem_load_tuning.argtypes = [ctypes.c_char_p]
+    lib.gbem_set_tuning_override.argtypes = [ctypes.POINTER(Tuning)]
+    lib.gbem_tuning_source.restype = ctypes.c_char_p
     lib.gbem_submit.argtypes = [_vp, ctypes.POINTER(Mesh), ctypes.POINTER(Opts), ctypes.POINTER(_vp)]
     lib.gbem_poll.argtypes = [_vp]
     lib.gbem_wait.argtypes = [_vp, ctypes.c_double, _vp, ctypes.POINTER(Report)]
@@ -143,7 +169,7 @@ def load():
                  "gbem_poll", "gbem_wait", "gbem_server_stats", "gbem_mesh_boxes", "gbem_near_list",
                  "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
                  "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
-                 "gbem_extract_device_noalloc"):
+                 "gbem_extract_device_noalloc", "gbem_load_tuning", "gbem_set_tuning_override"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib

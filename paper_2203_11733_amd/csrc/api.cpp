@@ -612,6 +612,9 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         rep->residual = resid;
         rep->refine_iters = iters;
         rep->factor_used = dtype;
+        const CholShape sh = chol_shape(dtype, npad);
+        rep->outer_width = sh.outer_width;
+        rep->super_panels = sh.super_panels;
         pf.collect(rep);
     }
     return GBEM_OK;
@@ -957,6 +960,7 @@ extern "C" gbem_status gbem_create(int device, size_t budget, gbem_ctx **out)
         return GBEM_EDEVICE;
     }
     HIPCHK(hipSetDevice(device), "hipSetDevice");
+    tuning_autoload();
     gbem_ctx *c = new gbem_ctx();
     c->device = device;
     if (budget == 0) {

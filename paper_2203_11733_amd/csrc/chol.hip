@@ -439,7 +439,8 @@ constexpr int kBM = 128, kBK = 16;
 // outer panel width for a matrix of order npad
 // (measured on the MI355X in mixed mode: 512 wins from order ~16k up, e.g.
 // 26.7 vs 28.2 ms at 20k panels; 256 below, where the panel chain dominates)
-static int outer_width(int64_t npad) { return npad >= 16384 ? 512 : 256; }
+// (the autotuner's cache may move the threshold: chol_shape in tune.cpp)
+static int outer_width(int dtype, int64_t npad) { return chol_shape(dtype, npad).outer_width; }
 constexpr int kLdsLd = kBM + 16;   // LDS row stride: the four k-rows of a fragment load hit distinct banks
 constexpr int kRect = 0, kTri = 1;
 
@@ -939,24 +940,15 @@ size_t chol_panel_bytes(int, int64_t) { return 64; }
 // 199.8 ms per extraction against 217.2 ms with 2 (trailing update 109.5 vs
 // 130.4 ms, the look-ahead updates 36.2 vs 20.2 ms); at the crossing bus
 // (order 21,504) 2 panels stay ahead (25.25 vs 25.71 ms), the look-ahead
-// chain weighing more there.  GBEM_SUPER_PANELS (2 or 4) overrides the
-// default (read once).
-static int super_panels(int64_t npad)
-{
-    static const int forced = [] {
-        const char *e = getenv("GBEM_SUPER_PANELS");
-        const int x = e ? atoi(e) : 0;
-        return x == 2 || x == 4 ? x : 0;
-    }();
-    if (forced) return forced;
-    return npad >= 32768 ? 4 : 2;
-}
+// chain weighing more there.  Default thresholds and the autotuner's cache:
+// chol_shape (tune.cpp).
+static int super_panels(int dtype, int64_t npad) { return chol_shape(dtype, npad).super_panels; }
 size_t chol_panel16_bytes(int dtype, int64_t npad)
 {
     // two super-panels in flight (look-ahead): ping-pong buffers of npad rows
     // x (super-panel width) 16-bit values
     return (dtype == GBEM_F16 || dtype == GBEM_BF16)
-               ? (size_t)2 * npad * super_panels(npad) * outer_width(npad) * 2
+               ? (size_t)2 * npad * super_panels(dtype, npad) * outer_width(dtype, npad) * 2
                : 0;
 }
 
@@ -1146,7 +1138,7 @@ static hipError_t update16(int dtype, int64_t npad, float *A, int64_t lda, const
 static hipError_t factor16_t(int dtype, int64_t npad, float *A, int64_t lda, float *Winv, void *Q16, int32_t *info,
                              hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
 {
-    const int ow = outer_width(npad), P = super_panels(npad), sw = P * ow;
+    const int ow = outer_width(dtype, npad), P = super_panels(dtype, npad), sw = P * ow;
     const int nbo = (int)(npad / ow);
     const int nsp = (nbo + P - 1) / P;
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<float, true>,
@@ -1222,7 +1214,7 @@ template <typename T>
 static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, int32_t *info, hipStream_t s,
                            hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
 {
-    const int ow = outer_width(npad);
+    const int ow = outer_width(dtype, npad);
     const int nbo = (int)(npad / ow);
     hipError_t e = hipFuncSetAttribute((const void *)diag_kernel<T, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_smem_bytes(sizeof(T)));
@@ -1267,7 +1259,7 @@ static hipError_t factor_t(int dtype, int64_t npad, T *A, int64_t lda, T *Winv, 
 hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *, void *panel16,
                        int32_t *info, hipStream_t s, hipStream_t side, std::vector<hipEvent_t> &ev, Prof *prof)
 {
-    if (npad % outer_width(npad)) return hipErrorInvalidValue;
+    if (npad % outer_width(dtype, npad)) return hipErrorInvalidValue;
     if (dtype == GBEM_F64)
         return factor_t<double>(dtype, npad, (double *)A, lda, (double *)Winv, info, s, side, ev, prof);
     if (dtype == GBEM_F16 || dtype == GBEM_BF16)

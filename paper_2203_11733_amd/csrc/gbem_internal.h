@@ -168,6 +168,17 @@ hipError_t launch_far(const Panel *pan, int n, int npad, int p, const GaussRule 
                       int far_dtype, double *A, int64_t lda, hipStream_t s, float *F = nullptr,
                       int64_t ldf = 0, const double *sc = nullptr);
 
+// tune.cpp: tile shapes of the factorisation per matrix order and factor
+// dtype (the autotuner's cache, else built-in defaults); tuning_autoload
+// reads the default cache once (GBEM_TUNE_FILE or tune_gfx950.json next to
+// the library)
+struct CholShape {
+    int outer_width;    // columns per outer panel: 256 or 512
+    int super_panels;   // outer panels per 16-bit trailing update: 2 or 4 (1 for FP32/FP64)
+};
+CholShape chol_shape(int dtype, int64_t npad);
+void tuning_autoload();
+
 // chol.hip
 // side: second stream for the look-ahead panel factorisation; ev: event pool
 hipError_t chol_factor(int dtype, int64_t npad, void *A, int64_t lda, void *Winv, void *panel,

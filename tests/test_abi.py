@@ -2,6 +2,7 @@
 every entry point include/gbem.h declares, and its mesher is bit-exact with
 the oracle's."""
 import ctypes
+import json
 import os
 import re
 
@@ -123,3 +124,56 @@ def test_argument_checks_before_context():
     o = binding.make_opts(0)
     assert lib.gbem_extract(None, ctypes.byref(mesh), ctypes.byref(o), C.ctypes.data, None) == binding.EINVAL
     assert b"far_order" in lib.gbem_last_error()
+
+
+def test_tuning_cache_loader(tmp_path):
+    """The shape cache the autotuner writes is parsed strictly: a valid file
+    becomes the source, malformed ones and unsupported shapes are refused
+    (the previous cache stays), NULL returns to the built-in defaults, and
+    the override accepts only supported shapes."""
+    lib = binding.load()
+    good = tmp_path / "tune.json"
+    good.write_text(json.dumps({"entries": [
+        {"factor": "16bit", "npad_min": 0, "npad_max": 32768, "outer_width": 256, "super_panels": 2,
+         "ms": {"256x2": 1.0, "512x4": 2.0}},
+        {"factor": "f64", "npad_min": 0, "npad_max": 1 << 30, "outer_width": 512, "super_panels": 1}]}))
+    binding.load_tuning(str(good))
+    assert binding.tuning_source() == str(good)
+    for bad in ({"nothing": []}, {"entries": [{"factor": "f16", "npad_min": 0, "npad_max": 1, "outer_width": 256}]},
+                {"entries": [{"factor": "16bit", "npad_min": 0, "npad_max": 10, "outer_width": 384,
+                              "super_panels": 2}]},
+                {"entries": [{"factor": "16bit", "npad_min": 0, "npad_max": 10, "outer_width": 512,
+                              "super_panels": 3}]},
+                {"entries": [{"factor": "f64", "npad_min": 5, "npad_max": 5, "outer_width": 512}]}):
+        p = tmp_path / "bad.json"
+        p.write_text(json.dumps(bad))
+        with pytest.raises(binding.GbemError) as e:
+            binding.load_tuning(str(p))
+        assert e.value.status == binding.EINVAL
+        assert binding.tuning_source() == str(good)
+    with pytest.raises(binding.GbemError):
+        binding.load_tuning(str(tmp_path / "missing.json"))
+    binding.load_tuning(None)
+    assert binding.tuning_source() == "built-in defaults"
+    with pytest.raises(binding.GbemError):
+        binding.set_tuning_override(384, 0)
+    with pytest.raises(binding.GbemError):
+        binding.set_tuning_override(512, 3)
+    binding.set_tuning_override(512, 4)
+    binding.set_tuning_override(0, 0)
+
+
+def test_committed_tuning_cache_parses():
+    """The committed cache (written by the autotuner on the GPU) loads and
+    covers every padded order for both factor classes."""
+    path = os.path.join(ROOT, "paper_2203_11733_amd", "tune_gfx950.json")
+    if not os.path.exists(path):
+        pytest.skip("no tuning cache committed yet")
+    cache = json.load(open(path))
+    for cls in ("16bit", "f64"):
+        ranges = sorted((e["npad_min"], e["npad_max"]) for e in cache["entries"] if e["factor"] == cls)
+        assert ranges[0][0] == 0
+        assert all(a[1] == b[0] for a, b in zip(ranges, ranges[1:]))
+    binding.load_tuning(path)
+    assert binding.tuning_source() == path
+    binding.load_tuning(None)
