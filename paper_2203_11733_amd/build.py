@@ -59,6 +59,13 @@ def build(verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    # a kernel whose host launch stub the compiler dropped links fine and
+    # fails only when the library is loaded: refuse it here
+    nm = subprocess.run(["nm", "-D", "--undefined-only", tmp], capture_output=True, text=True)
+    missing = [ln.split()[-1] for ln in nm.stdout.splitlines() if "gbem" in ln]
+    if nm.returncode == 0 and missing:
+        os.remove(tmp)
+        raise RuntimeError("libgbem.so has undefined symbols of its own: " + ", ".join(missing[:5]))
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)
