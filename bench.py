@@ -9,7 +9,7 @@ path is timed over the same number of steps beside it, and both capacitance
 matrices are compared with the oracle's stored result for this layout.
 
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K,
---warmup W, --mode mixed|f64, --layout three_layer_bus|crossing_bus|two_plates,
+--warmup W, --mode mixed|f64, --layout three_layer_bus|crossing_bus|two_plates|small_job,
 --no-f64, --no-cpu-baseline.
 """
 from __future__ import annotations
@@ -131,10 +131,30 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def small_job():
+    """A serving-size job: the seeded random Manhattan layout of about 3,000
+    panels the autotuner times for its smallest order bucket."""
+    import numpy as np
+
+    import gbem_inputs as gi
+    rng = np.random.default_rng(11)
+    for _ in range(100):
+        lay = gi.random_manhattan(rng, n_target=3000)
+        if 2400 <= lay_panels(lay) <= 3600:
+            return lay
+    return lay
+
+
+def lay_panels(lay):
+    from paper_2203_11733_amd import binding
+    return binding.mesh_layout(lay)[0].shape[0]
+
+
 def layout_of(name):
     import gbem_inputs as gi
     return {"crossing_bus": gi.crossing_bus, "three_layer_bus": gi.three_layer_bus,
-            "two_plates": gi.two_plates, "crossing_bars_in_box": gi.crossing_bars_in_box}[name]()
+            "two_plates": gi.two_plates, "crossing_bars_in_box": gi.crossing_bars_in_box,
+            "small_job": small_job}[name]()
 
 
 FULL_ORACLE_MAX_N = 25000   # whole oracle extractions up to this order take ~10-30 s on 16 cores

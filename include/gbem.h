@@ -140,7 +140,7 @@ typedef struct {
 /* Tile shapes of the Cholesky factorisation (schedule only: results do not
  * depend on them beyond rounding order).  outer_width: columns per outer
  * panel, 256 or 512.  super_panels: outer panels per trailing update of the
- * 16-bit factors, 2 or 4 (K = super_panels * outer_width).  The library picks
+ * 16-bit factors, 1, 2 or 4 (K = super_panels * outer_width).  The library picks
  * them per padded matrix order and factor dtype from a cache written by the
  * project's autotuner (paper_2203_11733_amd/autotune.py, which times every
  * candidate on the GPU): tune_gfx950.json next to the library, or the file

@@ -44,7 +44,7 @@ BUCKETS = [
     (49152, 1 << 30, "three-layer bus (59,904 panels)", lambda: gi.three_layer_bus()),
 ]
 CANDIDATES = {
-    "16bit": [(256, 2), (256, 4), (512, 2), (512, 4)],
+    "16bit": [(256, 1), (256, 2), (256, 4), (512, 1), (512, 2), (512, 4)],
     "f64": [(256, 0), (512, 0)],
 }
 MODES = {

@@ -651,8 +651,11 @@ struct NoAllocDev {
     std::mutex mu;          // calls on this device take turns: they share the array
     void *ptr = nullptr;    // device address of `scratch` on this device
     Arena arena;
-    Workspace ws;           // every buffer borrowed from the arena; events, side stream,
-                            // pinned readback and the factor's event pool created at set-up
+    Workspace ws;           // every buffer borrowed from the arena; events, pinned readback and
+                            // the factor's event pool created at set-up; no stream of its own
+                            // (the look-ahead runs on the caller's stream: a stream more per
+                            // process would share the GPU's few hardware queues with the
+                            // serving workers' streams)
 };
 static std::mutex g_noalloc_mu;
 static std::vector<NoAllocDev *> g_noalloc;   // by device; entries live until the process ends
@@ -672,7 +675,7 @@ static hipError_t noalloc_setup(int device)
     d->arena.base = static_cast<unsigned char *>(ptr);
     d->arena.size = kNoAllocBytes;
     d->ws.each([&](DevBuf &b) { b.arena = &d->arena; });
-    if ((e = d->ws.init_events()) != hipSuccess || (e = d->ws.ensure_side()) != hipSuccess) {
+    if ((e = d->ws.init_events()) != hipSuccess) {
         delete d;
         return e;
     }
@@ -1141,8 +1144,10 @@ extern "C" gbem_status gbem_extract_device_noalloc(gbem_ctx *ctx, const gbem_mes
     hipStream_t st = stream ? (hipStream_t)stream : ctx->stream;
     gbem_report r{};
     double hC[kMaxRhs * kMaxRhs];
+    d->ws.side = st;   // the factorisation's look-ahead on the same stream (serial, same results)
     s = run_pipeline(d->ws, st, n, m, mesh->lo, mesh->hi, mesh->conductor, mesh->eps_r, mesh->length_unit_m, o,
                      C_out_device, &r, Stop::kFull, hC);
+    d->ws.side = nullptr;
     if (s == GBEM_ENOMEM && d->arena.exhausted)
         set_error("gbem_extract_device_noalloc: the " + std::to_string(kNoAllocBytes >> 20) +
                   " MiB scratch cannot hold this job (" + gbem_last_error() +

@@ -5,7 +5,8 @@
 //   outer_width   columns per outer panel (256 or 512; the matrix order is a
 //                 multiple of 512, so both divide it)
 //   super_panels  outer panels per trailing update of the 16-bit factors
-//                 (2 or 4, K = super_panels * outer_width <= 2048)
+//                 (1, 2 or 4, K = super_panels * outer_width <= 2048; 1: the
+//                 trailing matrix is updated after every panel)
 // Cache format (JSON, written by the autotuner): {"entries": [{"factor":
 // "16bit" | "f32" | "f64", "npad_min": a, "npad_max": b, "outer_width": w,
 // "super_panels": p, ...}, ...], ...}; an entry applies to padded orders
@@ -113,8 +114,8 @@ bool parse(const std::string &text, std::vector<Entry> &out, std::string &why)
             return false;
         }
         if (find_key(p, q, "super_panels", &v) && sscanf(v, "%lld", &sp) != 1) sp = 1;
-        if ((w != 256 && w != 512) || a < 0 || b <= a || (en.cls == 0 && sp != 2 && sp != 4)) {
-            why = "entry outside the supported shapes (outer_width 256 | 512, super_panels 2 | 4)";
+        if ((w != 256 && w != 512) || a < 0 || b <= a || (en.cls == 0 && sp != 1 && sp != 2 && sp != 4)) {
+            why = "entry outside the supported shapes (outer_width 256 | 512, super_panels 1 | 2 | 4)";
             return false;
         }
         en.lo = a;
@@ -206,8 +207,8 @@ extern "C" gbem_status gbem_load_tuning(const char *path)
 extern "C" gbem_status gbem_set_tuning_override(const gbem_tuning *t)
 {
     if (t && ((t->outer_width != 0 && t->outer_width != 256 && t->outer_width != 512) ||
-              (t->super_panels != 0 && t->super_panels != 2 && t->super_panels != 4))) {
-        set_error("gbem_set_tuning_override: outer_width must be 0, 256 or 512 and super_panels 0, 2 or 4");
+              (t->super_panels != 0 && t->super_panels != 1 && t->super_panels != 2 && t->super_panels != 4))) {
+        set_error("gbem_set_tuning_override: outer_width must be 0, 256 or 512 and super_panels 0, 1, 2 or 4");
         return GBEM_EINVAL;
     }
     std::lock_guard<std::mutex> lk(g_mu);
