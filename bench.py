@@ -7,10 +7,12 @@ panels, 48 conductors, the largest single-GPU workload.  Default mode: FP32
 far field + FP16 trailing updates + FP64 refinement to 1e-6; the plain FP64
 path is timed over the same number of steps beside it, and both capacitance
 matrices are compared with the oracle's stored result for this layout.
+After the timed steps the seeded 256-job serving stream is replayed in the
+same mode and in FP64 (p50/p99 latency at 50 jobs/s, saturation jobs/s).
 
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K,
 --warmup W, --mode mixed|f64, --layout three_layer_bus|crossing_bus|two_plates|small_job,
---no-f64, --no-cpu-baseline.
+--no-f64, --no-cpu-baseline, --no-serving.
 """
 from __future__ import annotations
 
@@ -418,6 +420,8 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="replay the seeded serving stream (256 jobs, Poisson 50 jobs/s) instead")
     ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="do not replay the serving stream (mixed and FP64) after the headline steps")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the library's per-launch HIP events (no roofline)")
     ap.add_argument("--sweep", action="store_true",
@@ -576,6 +580,16 @@ def main():
     if "near_eval" in pa:
         rates["near_pairs_per_s"] = nnz / (pa["near_eval"]["ms"] / 1e3)
     out["rates"] = rates
+    if not args.no_serving:
+        # the seeded 256-job serving stream in this mode and in plain FP64
+        # (its own context: jobs through gbem_submit / gbem_poll)
+        out["serving"] = {}
+        for smode in dict.fromkeys((args.mode, "f64")):
+            sargs = argparse.Namespace(**vars(args))
+            sargs.mode = smode
+            sv = serving(sargs, binding, np)
+            out["serving"].setdefault("workload", sv["config"]["workload"])
+            out["serving"][smode] = {"dtype": sv["dtype"], "poisson": sv["poisson"], "saturation": sv["saturation"]}
     if args.copy_calibration:
         # a plain copy kernel of known size: 256 MiB read + 256 MiB written per launch
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)

@@ -155,11 +155,11 @@ struct Workspace {
     // flags of the persistent solves: zeroed once when (re)allocated; the
     // epoch restarts with them
     // (published words are epoch-tagged: zero tags never match an epoch >= 1)
-    // layout: flag words (error, tickets, per-block flags), published blocks, M_k / N_k
+    // layout: flag words (error, tickets, per-block flags), published blocks, M_k, N_k, M2_k, N2_k
     static size_t sync_flag_bytes(int64_t npad) { return (((size_t)2 * (npad / kNB) * 4 + 256) + 255) / 256 * 256; }
     static size_t sync_bytes(int64_t npad)
     {
-        return sync_flag_bytes(npad) + (size_t)2 * npad * kMaxPub * 8 + (size_t)2 * npad * kNB * 4;
+        return sync_flag_bytes(npad) + (size_t)2 * npad * kMaxPub * 8 + (size_t)4 * npad * kNB * 4;
     }
     hipError_t ensure_sync(int64_t npad, hipStream_t st)
     {

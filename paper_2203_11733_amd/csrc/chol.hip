@@ -1124,8 +1124,8 @@ static hipError_t update16(int dtype, int64_t npad, float *A, int64_t lda, const
 // super-panel is updated once with K = P ow (its FP32 read-modify-write
 // traffic falls as 1 / P against one update per panel), while the panel
 // factorisations keep ow-wide panels.  The look-ahead chain carries more
-// update work per panel as P grows, so small matrices, whose factorisation
-// the chain bounds, take P = 1 (one update per panel).  Super-panel s = panels P s .. P s + P - 1 (the last may
+// update work per panel as P grows (P = 1: one update per panel); the tile
+// shape table picks P per matrix order.  Super-panel s = panels P s .. P s + P - 1 (the last may
 // have fewer), columns from P0_s = P s ow.  Its 16-bit copy Q_s (ping-pong
 // buffer s & 1, row stride P ow) holds global row R_s + i in row i, R_s =
 // P0_s + ow: panel P s + j in columns [j ow, (j + 1) ow) from row j ow on.

@@ -195,7 +195,7 @@ struct SolveSync {
     int32_t epoch = 0;
     uint32_t base_f = 0, base_b = 0;   // host copies of the two ticket counters
     // FP32 solves: published blocks (2 directions x npad x kMaxPub words) and
-    // the sub-diagonal products M_k, N_k (2 x npad x 128 floats) of the
+    // the products M_k, N_k, M2_k, N2_k (4 x npad x 128 floats) of the
     // factor prepared last
     uint64_t *pub = nullptr;
     float *sub = nullptr;

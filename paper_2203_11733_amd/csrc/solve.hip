@@ -211,19 +211,25 @@ __global__ __launch_bounds__(256) void bwd_solve_kernel(const T *__restrict__ L,
 // the block products on MFMA (v_mfma_f32_16x16x4f32, FP32 accumulation; the
 // solve only has to match the precision of the factor, the FP64 refinement
 // supplies the rest).  With D_k = L_kk and W_k = D_k^{-1}:
-//   forward   Y_k = W_k (B_k - sum_{j<k-1} L_kj Y_j) - M_k Y_{k-1},
-//             M_k = W_k L_{k,k-1};
-//   backward  X_k = W_k^T (Y_k - sum_{j>k+1} L_jk^T X_j) - N_k^T X_{k+1},
-//             N_k = L_{k+1,k} W_k.
-// M_k and N_k are formed once per factor (solve_prep), so after the block a
-// workgroup waits for last has arrived only one 128 x 128 product remains;
-// everything else overlaps the wait.  One workgroup per block solves every
-// right-hand side (MC = 16 NCB >= m columns), so L is streamed once per
-// direction whatever the conductor count.  Per workgroup:
-//   - W_k and M_k / N_k wait in registers from the start and go through the
-//     LDS tile buffer once the dependency stream is over; the L blocks stream
-//     through that buffer, the next one loaded into registers while the MFMAs
-//     work on the current one;
+//   forward   Y_k = W_k (B_k - sum_{j<k-2} L_kj Y_j) - M2_k Y_{k-2} - M_k Y_{k-1},
+//             M_k = W_k L_{k,k-1},  M2_k = W_k L_{k,k-2};
+//   backward  X_k = W_k^T (Y_k - sum_{j>k+2} L_jk^T X_j) - N2_k^T X_{k+2} - N_k^T X_{k+1},
+//             N_k = L_{k+1,k} W_k,  N2_k = L_{k+2,k} W_k.
+// The four products are formed once per factor (solve_prep).  A workgroup
+// finishes the W_k product while its block's second-to-last dependency is
+// being computed, applies M2_k / N2_k while the last one is, and after the
+// last has arrived only one 128 x 128 product remains (measured at order
+// 59,904 with 48 right-hand sides: with W_k applied after the second-to-last
+// dependency, a workgroup entered its final wait 3.6 us after the block it
+// waits for was published, against 1.8 us from publication to arrival).  One
+// workgroup per block solves every right-hand side (MC = 16 NCB >= m
+// columns), so L is streamed once per direction whatever the conductor
+// count.  Per workgroup:
+//   - W_k and M_k / N_k wait in registers from the start, M2_k / N2_k are
+//     loaded into the L-tile registers after the last L block; each goes
+//     through the LDS tile buffer once the dependency stream is over; the L
+//     blocks stream through that buffer, the next one loaded into registers
+//     while the MFMAs work on the current one;
 //   - each wave owns 32 rows of the block, so the products need no
 //     cross-wave reduction;
 //   - a finished block is published as 64-bit words (value bits, epoch) with
@@ -235,64 +241,85 @@ __global__ __launch_bounds__(256) void bwd_solve_kernel(const T *__restrict__ L,
 // ((R NCB + cb) 4 + q) 64 + l holds row 16 R + 4 (l / 16) + q, column
 // 16 cb + l % 16 (the MFMA output layout of the producing wave, so each store
 // instruction covers 512 contiguous bytes).
-// LDS: the tile (row stride TLD: FWD 144, BWD 132, conflict-free fragment
-// reads in either orientation) and two 128 x MC right-operand buffers (row
-// stride YLD: the four rows a fragment read touches fall on distinct banks).
+// LDS: the left operand A(i, t) of the block products (the L block, W_k,
+// M_k, M2_k, or their transposes) as tile[i * TLD + t], and two right-operand
+// buffers Y(t, n) as ys[n * YLD + t]: both contiguous in the summation index
+// t, so one 16-byte read gives a lane the operands of four MFMAs (lane group
+// g takes t = 16 s + 4 g .. 16 s + 4 g + 3 in step s; 7.2 against 8.8
+// thousand cycles per 128 x 128 x 48 product with one 4-byte read per
+// operand and MFMA).  Strides of 132 words put the 16-byte reads of eight
+// consecutive lanes on distinct banks.
 // ------------------------------------------------------------------------
 template <bool FWD, int NCB> struct SolveCfg {
     static constexpr int MC = 16 * NCB;               // right-hand sides per workgroup
     static constexpr int RB = 2;                      // 16-row blocks per wave
     static constexpr int NW = MC / 2;                 // published words per thread (128 MC / 256)
-    static constexpr int TLD = FWD ? 144 : 132;       // LDS tile stride
-    static constexpr int YLD = MC == 64 ? 80 : (MC == 32 ? 48 : MC);   // right-operand stride
+    static constexpr int TLD = 132;                   // LDS tile row stride
+    static constexpr int YLD = 132;                   // right-operand column stride
     static constexpr size_t kTileBytes = (size_t)kNB * TLD * 4;
-    static constexpr size_t kYBytes = (size_t)kNB * YLD * 4;
+    static constexpr size_t kYBytes = (size_t)MC * YLD * 4;
     static constexpr size_t kSmem = kTileBytes + 2 * kYBytes;
 };
 typedef float f4s_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u4s_t __attribute__((ext_vector_type(4)));
 
-// 128 x 128 block at P (column-major, ld) -> registers: thread = column c,
-// rows h*64 .. h*64+63 as 16-byte chunks
+// 128 x 128 block at P (column-major, ld) -> registers: thread = column
+// c = tid % 128, rows h*64 .. h*64+63 (h = tid / 128) as 16-byte chunks
 __device__ __forceinline__ void tile_load(u4s_t (&tr)[16], const float *P, int64_t ld)
 {
-    const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
+    const int c = threadIdx.x & 127, h = threadIdx.x >> 7;
     const u4s_t *src = reinterpret_cast<const u4s_t *>(P + h * 64 + (int64_t)c * ld);
 #pragma unroll
     for (int q = 0; q < 16; ++q) tr[q] = src[q];
 }
-template <int TLD>
+// Registers of tile_load -> the LDS tile, A(i, t) = tile[i * TLD + t].
+// FWD (A = L_kj, W_k, M_k, M2_k: the loaded column is t): transposing 4-byte
+// stores, a wave's lanes on 64 consecutive columns of one row (distinct
+// banks).  BWD (A = L_jk^T, W_k^T, N_k^T, N2_k^T: the loaded column is i):
+// the column as it is, in 16-byte stores (eight consecutive columns per
+// store cycle, distinct banks at the stride of 132 words).
+template <bool FWD, int TLD>
 __device__ __forceinline__ void tile_store(float *tile, const u4s_t (&tr)[16])
 {
-    const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
-    u4s_t *dst = reinterpret_cast<u4s_t *>(tile + c * TLD + h * 64);
+    const int c = threadIdx.x & 127, h = threadIdx.x >> 7;
+    if constexpr (FWD) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) dst[q] = tr[q];
+        for (int q = 0; q < 16; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tile[(h * 64 + 4 * q + e) * TLD + c] = __uint_as_float(tr[q][e]);
+    } else {
+        u4s_t *dst = reinterpret_cast<u4s_t *>(tile + c * TLD + h * 64);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) dst[q] = tr[q];
+    }
 }
 
 // acc[rb][cb] += A(i, t) Y(t, n) over t = 0..127 for the wave's rows
-// i = 32 w + 16 rb + ..; A(i, t) = tile[t*TLD + i] (FWD: L_kj, W_k, M_k) or
-// tile[i*TLD + t] (BWD: L_jk^T, W_k^T, N_k^T); Y(t, n) = ys[t*YLD + n],
-// n = 16 cb + ..
+// i = 32 w + 16 rb + .. and columns n = 16 cb + ..; A(i, t) = tile[i*TLD + t],
+// Y(t, n) = ys[n*YLD + t].  MFMA j of step s contracts t = 16 s + 4 g + j
+// over the lane groups g (any order of the sum over t is the same product).
 template <bool FWD, int NCB>
 __device__ __forceinline__ void tile_product(f4s_t (&acc)[2][NCB], const float *tile, const float *ys)
 {
     typedef SolveCfg<FWD, NCB> C;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll 4
-    for (int kk = 0; kk < kNB; kk += 4) {
-        const int t = kk + (lane >> 4);
-        float b[NCB];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g4 = 4 * (lane >> 4);
+    const float *ap0 = tile + ((w * C::RB + 0) * 16 + r) * C::TLD + g4;
+    const float *ap1 = tile + ((w * C::RB + 1) * 16 + r) * C::TLD + g4;
+    const float *bp = ys + r * C::YLD + g4;
+#pragma unroll 2
+    for (int k16 = 0; k16 < kNB; k16 += 16) {
+        const f4s_t a0 = *reinterpret_cast<const f4s_t *>(ap0 + k16);
+        const f4s_t a1 = *reinterpret_cast<const f4s_t *>(ap1 + k16);
+        f4s_t b[NCB];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) b[cb] = ys[t * C::YLD + cb * 16 + (lane & 15)];
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const f4s_t *>(bp + cb * 16 * C::YLD + k16);
 #pragma unroll
-        for (int rb = 0; rb < C::RB; ++rb) {
-            const int i = (w * C::RB + rb) * 16 + (lane & 15);
-            const float a = FWD ? tile[t * C::TLD + i] : tile[i * C::TLD + t];
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[cb], acc[rb][cb], 0, 0, 0);
-        }
+            for (int cb = 0; cb < NCB; ++cb) {
+                acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[j], b[cb][j], acc[0][cb], 0, 0, 0);
+                acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[j], b[cb][j], acc[1][cb], 0, 0, 0);
+            }
     }
 }
 
@@ -339,7 +366,31 @@ __device__ __forceinline__ bool pub_complete(uint64_t (&wd)[NW], const uint64_t 
     if (!good) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return !__syncthreads_or(!good);
 }
-// words -> ys[row * YLD + col] (FP32): word t + 256 u is (R, cb) = (u / NCB,
+// The same for the blocks a workgroup's last two products wait on (the
+// solve's critical path): every thread re-loads its own stale words until
+// they carry `tag`, which takes one memory round trip after publication
+// instead of two.  Two workgroups wait on a block this way, so the extra
+// polling traffic is two blocks per round trip.
+template <int NW>
+__device__ __forceinline__ bool pub_complete_direct(uint64_t (&wd)[NW], const uint64_t *blk, uint32_t tag,
+                                                    int32_t *err, int limit)
+{
+    const uint64_t *p = blk + threadIdx.x;
+    bool good = true;
+    for (int n = 0;; ++n) {
+        good = true;
+#pragma unroll
+        for (int u = 0; u < NW; ++u) good = good && (uint32_t)(wd[u] >> 32) == tag;
+        if (good || n >= limit) break;
+#pragma unroll
+        for (int u = 0; u < NW; ++u)
+            if ((uint32_t)(wd[u] >> 32) != tag)
+                wd[u] = __hip_atomic_load(p + 256 * u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!good) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return !__syncthreads_or(!good);
+}
+// words -> ys[col * YLD + row] (FP32): word t + 256 u is (R, cb) = (u / NCB,
 // u % NCB), q = wave, l = lane
 template <bool FWD, int NCB>
 __device__ __forceinline__ void pub_to_lds(float *ys, const uint64_t (&wd)[SolveCfg<FWD, NCB>::NW])
@@ -349,7 +400,7 @@ __device__ __forceinline__ void pub_to_lds(float *ys, const uint64_t (&wd)[Solve
 #pragma unroll
     for (int u = 0; u < C::NW; ++u) {
         const int R = u / NCB, cb = u % NCB;
-        ys[(R * 16 + 4 * (lane >> 4) + q) * C::YLD + cb * 16 + (lane & 15)] = __uint_as_float((uint32_t)wd[u]);
+        ys[(cb * 16 + (lane & 15)) * C::YLD + R * 16 + 4 * (lane >> 4) + q] = __uint_as_float((uint32_t)wd[u]);
     }
 }
 
@@ -358,7 +409,8 @@ __device__ __forceinline__ void pub_to_lds(float *ys, const uint64_t (&wd)[Solve
 template <bool FWD, int NCB>
 __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__ L, int64_t lda,
                                                        const float *__restrict__ W, const float *__restrict__ S,
-                                                       double *B, int64_t ldb, uint64_t *Y, int m, int nb,
+                                                       const float *__restrict__ S2, double *B, int64_t ldb,
+                                                       uint64_t *Y, int m, int nb,
                                                        int32_t *__restrict__ counter, uint32_t base, uint32_t tag,
                                                        int32_t *err, int limit)
 {
@@ -376,7 +428,7 @@ __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__
     // solve order: FWD blocks 0, 1, ..; BWD blocks nb-1, nb-2, ..
     const int k = FWD ? tk : nb - 1 - tk, k0 = k * kNB;
     const int cnt = tk;                      // blocks this one depends on
-    const int nn = cnt > 0 ? cnt - 1 : 0;    // all but the last of them
+    const int nn = cnt > 1 ? cnt - 2 : 0;    // all but the last two of them
     constexpr int BW = kNB * C::MC;          // words per published block
     auto jof = [&](int idx) { return FWD ? idx : nb - 1 - idx; };
     auto pblk = [&](int idx) { return Y + (int64_t)jof(idx) * BW; };
@@ -412,7 +464,7 @@ __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__
         pub_issue<C::NW>(wd, pblk(0));
         if (!pub_complete<C::NW>(wd, pblk(0), tag, err, limit)) return;
         pub_to_lds<FWD, NCB>(ys0, wd);
-        tile_store<C::TLD>(tile, tr);
+        tile_store<FWD, C::TLD>(tile, tr);
         if (nn > 1) tile_load(tr, lsrc(1), lda);
         __syncthreads();
         for (int idx = 0; idx < nn; ++idx) {
@@ -422,13 +474,16 @@ __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__
             if (!more) break;
             if (!pub_complete<C::NW>(wd, pblk(idx + 1), tag, err, limit)) return;
             __syncthreads();
-            tile_store<C::TLD>(tile, tr);
+            tile_store<FWD, C::TLD>(tile, tr);
             pub_to_lds<FWD, NCB>(((idx + 1) & 1) ? ys1 : ys0, wd);
             if (idx + 2 < nn) tile_load(tr, lsrc(idx + 2), lda);
             __syncthreads();
         }
     }
     __syncthreads();   // the last product is done with tile, ys0 and ys1
+    // M2_k / N2_k into the registers the L tiles used; waited for after the
+    // W_k product
+    if (cnt > 1) tile_load(tr, S2 + (int64_t)k * kNB * kNB, kNB);
     // Z = W_k (B_k - acc): the difference goes through LDS as the right operand
 #pragma unroll
     for (int rb = 0; rb < C::RB; ++rb)
@@ -436,18 +491,38 @@ __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__
         for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                ys0[erow(rb, q) * C::YLD + cb * 16 + col] = (float)(bk[rb][cb][q] - (double)acc[rb][cb][q]);
+                ys0[(cb * 16 + col) * C::YLD + erow(rb, q)] = (float)(bk[rb][cb][q] - (double)acc[rb][cb][q]);
             acc[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
         }
-    tile_store<C::TLD>(tile, wr);
-    if (cnt > 0) pub_issue<C::NW>(wd, pblk(cnt - 1));   // the last dependency, completed after the product
+    tile_store<FWD, C::TLD>(tile, wr);
+    // the next dependency to arrive (the second-to-last, else the last), completed after the product
+    if (cnt > 0) pub_issue<C::NW>(wd, pblk(cnt > 1 ? cnt - 2 : cnt - 1));
     __syncthreads();
     tile_product<FWD, NCB>(acc, tile, ys0);
+    if (cnt > 1) {
+        // Z -= M2_k Y_{k-2} (FWD) or N2_k^T X_{k+2} (BWD), while Y_{k-1} / X_{k+1} is computed
+        __syncthreads();   // every wave is done with W_k in the tile
+        tile_store<FWD, C::TLD>(tile, tr);
+        if (!pub_complete_direct<C::NW>(wd, pblk(cnt - 2), tag, err, limit)) return;
+        pub_to_lds<FWD, NCB>(ys1, wd);
+        pub_issue<C::NW>(wd, pblk(cnt - 1));   // the last dependency, completed after this product
+        __syncthreads();
+        f4s_t acc2[2][NCB];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc2[rb][cb] = f4s_t{0.f, 0.f, 0.f, 0.f};
+        tile_product<FWD, NCB>(acc2, tile, ys1);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] -= acc2[rb][cb];
+    }
     if (cnt > 0) {
         // Y_k = Z - M_k Y_{k-1} (FWD) or X_k = Z - N_k^T X_{k+1} (BWD)
-        __syncthreads();   // every wave is done with W_k in the tile
-        tile_store<C::TLD>(tile, sr);
-        if (!pub_complete<C::NW>(wd, pblk(cnt - 1), tag, err, limit)) return;
+        __syncthreads();   // every wave is done with the tile (W_k or M2_k) and with ys1
+        tile_store<FWD, C::TLD>(tile, sr);
+        if (!pub_complete_direct<C::NW>(wd, pblk(cnt - 1), tag, err, limit)) return;
         pub_to_lds<FWD, NCB>(ys1, wd);
         __syncthreads();
         f4s_t acc2[2][NCB];
@@ -481,9 +556,13 @@ __global__ __launch_bounds__(256) void tsolve32_kernel(const float *__restrict__
                 if (cb * 16 + col < m) B[(k0 + erow(rb, q)) + (int64_t)(cb * 16 + col) * ldb] = (double)acc[rb][cb][q];
 }
 
-// M_k = W_k L_{k,k-1} (k = 1 .. nb-1, slot k of S) and N_k = L_{k+1,k} W_k
-// (k = 0 .. nb-2, slot k of S + npad * 128).  One workgroup per product,
-// both operands in LDS, 8 x 8 outputs per thread on FP32 FMAs.
+// Products with the diagonal-block inverses for the FP32 solves, in four
+// npad x 128 slots of S: M_k = W_k L_{k,k-1} (slot 0, k = 1 .. nb-1),
+// N_k = L_{k+1,k} W_k (slot 1, k = 0 .. nb-2), M2_k = W_k L_{k,k-2}
+// (slot 2, k = 2 .. nb-1), N2_k = L_{k+2,k} W_k (slot 3, k = 0 .. nb-3);
+// block k of a slot at offset 128 k * 128.  One workgroup per product
+// (blockIdx.y = slot), both operands in LDS, 8 x 8 outputs per thread on
+// FP32 FMAs.
 constexpr int kPLd = kNB + 4;
 __global__ __launch_bounds__(256) void solve_prep_kernel(const float *__restrict__ L, int64_t lda,
                                                          const float *__restrict__ W, float *__restrict__ S,
@@ -492,15 +571,17 @@ __global__ __launch_bounds__(256) void solve_prep_kernel(const float *__restrict
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     float *As = reinterpret_cast<float *>(smem_raw);   // As[t * kPLd + i] = A(i, t)
     float *Bs = As + kNB * kPLd;                       // Bs[t * kPLd + c] = B(t, c)
-    const bool second = blockIdx.y == 1;
-    const int k = second ? blockIdx.x : blockIdx.x + 1;
+    const int slot = blockIdx.y, d = 1 + (slot >> 1);   // d: block distance of the L factor
+    const bool second = slot & 1;                        // L block on the left (N_k, N2_k)
+    if ((int64_t)(blockIdx.x + d) * kNB >= npad) return; // slots 2, 3 hold one product fewer
+    const int k = second ? blockIdx.x : blockIdx.x + d;
     const int64_t k0 = (int64_t)k * kNB;
     const float *Wk = W + k0 * kNB;
-    const float *A = second ? L + (k0 + kNB) + k0 * lda : Wk;
+    const float *A = second ? L + (k0 + d * kNB) + k0 * lda : Wk;
     const int64_t ldA = second ? lda : kNB;
-    const float *Bm = second ? Wk : L + k0 + (k0 - kNB) * lda;
+    const float *Bm = second ? Wk : L + k0 + (k0 - d * kNB) * lda;
     const int64_t ldB = second ? kNB : lda;
-    float *out = S + (second ? npad * kNB : 0) + k0 * kNB;
+    float *out = S + slot * npad * kNB + k0 * kNB;
     const int tid = threadIdx.x;
     {
         const int c = tid >> 1, h = tid & 1;
@@ -562,17 +643,18 @@ static hipError_t solve32_n(int64_t npad, const float *L, int64_t lda, const flo
     uint64_t *Yf = sync.pub, *Yb = sync.pub + (size_t)npad * kMaxPub;
     const unsigned grid = (unsigned)nb;
     const int tok = prof ? prof->start(s, GBEM_K_SOLVE) : -1;
+    const float *sub = sync.sub;   // M, N, M2, N2: npad x 128 floats each
     hipLaunchKernelGGL((tsolve32_kernel<true, NCB>), dim3(grid), dim3(256), (SolveCfg<true, NCB>::kSmem), s, L, lda, W,
-                       (const float *)sync.sub, B, ldb, Yf, m, nb, sync.err + 1, sync.base_f, tag, sync.err, limit);
+                       sub, sub + 2 * npad * kNB, B, ldb, Yf, m, nb, sync.err + 1, sync.base_f, tag, sync.err, limit);
     hipLaunchKernelGGL((tsolve32_kernel<false, NCB>), dim3(grid), dim3(256), (SolveCfg<false, NCB>::kSmem), s, L, lda,
-                       W, (const float *)sync.sub + npad * kNB, B, ldb, Yb, m, nb, sync.err + 2, sync.base_b, tag,
+                       W, sub + npad * kNB, sub + 3 * npad * kNB, B, ldb, Yb, m, nb, sync.err + 2, sync.base_b, tag,
                        sync.err, limit);
     if (prof) {
-        // L once per direction, W and M/N per block, B read/written, published blocks read by every later block
+        // L once per direction, W, M/N and M2/N2 per block, B read/written, published blocks read by every later block
         const double lbytes = (double)npad * (npad + kNB) / 2.0 * 4.0;
         const double pub = (double)nb * (nb - 1) / 2.0 * kNB * 16 * NCB * 8.0;
         prof->stop(tok, GBEM_K_SOLVE, 2.0 * 2.0 * (double)npad * npad / 2.0 * m,
-                   2.0 * lbytes + 4.0 * npad * kNB * 4.0 + 4.0 * npad * m * 8.0 + 2.0 * pub, s, 2);
+                   2.0 * lbytes + 6.0 * npad * kNB * 4.0 + 4.0 * npad * m * 8.0 + 2.0 * pub, s, 2);
     }
     e = hipGetLastError();
     if (e == hipSuccess) {   // each launch consumes exactly grid tickets
@@ -657,7 +739,7 @@ hipError_t chol_solve_prep(int dtype, int64_t npad, const void *L, int64_t lda, 
         hipError_t e = hipFuncSetAttribute((const void *)solve_prep_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(solve_prep_kernel, dim3(nb - 1, 2), dim3(256), smem, s, (const float *)L, lda,
+        hipLaunchKernelGGL(solve_prep_kernel, dim3(nb - 1, 4), dim3(256), smem, s, (const float *)L, lda,
                            (const float *)Winv, sync.sub, npad);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
