@@ -18,6 +18,8 @@
 // Residual: R = B - A X with the FP64 matrix (row i of the symmetric A is read
 // as column i).  The j range is split over several workgroups per row block;
 // partial sums are added in a fixed order by a second kernel.
+#include <type_traits>
+
 #include "gbem_internal.h"
 
 namespace gbem {
@@ -751,79 +753,106 @@ hipError_t chol_solve_prep(int dtype, int64_t npad, const void *L, int64_t lda, 
 // ------------------------------------------------------------------------
 // Residual R = B - A X, split over j.  Row i of the symmetric A is read as
 // column i (contiguous in j).  A workgroup takes 128 values of i (32 per
-// wave) and a range of j; each wave multiplies on v_mfma_f64_16x16x4f64
-// without LDS or barriers: the summation index is permuted so that lane l
-// (k-slot q = l / 16) reads the 8 consecutive j = j0 + 8q .. j0 + 8q + 7 of
-// a 32-long chunk as four 16-byte loads, from A (column i0 + l % 16) and from
-// X (column c0 + l % 16) alike; the next chunk is loaded while the current
-// one is multiplied.  With X as the first operand the outputs of lane l lie
-// in row i0 + l % 16, so partial sums are stored 16 rows at a time.
+// wave) and a range of j in chunks of 32; each wave multiplies on
+// v_mfma_f64_16x16x4f64.  The summation index is permuted so that lane l
+// (k-slot q = l / 16) takes the 8 consecutive j = j0 + 8q .. j0 + 8q + 7 of
+// a chunk: four 16-byte loads of A (column i0 + l % 16) straight into
+// registers, one chunk ahead of their use, and four 16-byte LDS reads of X
+// (column c0 + l % 16).  The workgroup stages each X chunk in LDS once for
+// its four waves (double-buffered, loaded one chunk ahead) instead of every
+// wave holding it in registers, so two waves fit on each SIMD (three-layer
+// bus, 48 columns: 8.1 against 9.2 ms per residual with X in registers at
+// one wave per SIMD; A two chunks ahead at one wave per SIMD: 9.6 ms).
+// With X as the first operand the outputs of lane l lie in row
+// i0 + l % 16, so partial sums are stored 16 rows at a time.
 // ------------------------------------------------------------------------
-constexpr int kRRows = 128, kRChunk = 32;
+constexpr int kRRows = 128, kRChunk = 32, kRXld = kRChunk + 2;   // X chunk row stride in LDS (doubles)
 typedef double d4r_t __attribute__((ext_vector_type(4)));
 typedef double d2r_t __attribute__((ext_vector_type(2)));
 
 template <int MC>
-__global__ __launch_bounds__(256) void residual_partial_kernel(const double *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256, 2) void residual_partial_kernel(const double *__restrict__ A, int64_t lda,
                                                                int npad, const double *__restrict__ X,
                                                                int64_t ldx, int m, int jspan,
                                                                double *__restrict__ P)
 {
     constexpr int CB = MC / 16;
+    constexpr int NXP = MC / 16;   // 16-byte pieces of an X chunk per thread (MC columns x 16 pieces / 256)
+    extern __shared__ __attribute__((aligned(16))) double xs_raw[];   // [2][MC][kRXld]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int q = lane >> 4, li = lane & 15;
     const int i0 = blockIdx.x * kRRows + w * 32, s = blockIdx.y;
     const int jb = s * jspan, je = min(npad, jb + jspan);
+    const int nch = je > jb ? (je - jb) / kRChunk : 0;   // npad, jb and jspan are multiples of 32
     d4r_t acc[2][CB];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = d4r_t{0, 0, 0, 0};
-    if (jb >= je) {
-        // empty range: zero partials keep the fixed-order sum exact
-    } else {
-        d2r_t ra[2][2][4], rx[2][CB][4];   // [buffer][block][16-byte piece]
-        auto load = [&](int buf, int j0) __attribute__((always_inline)) {
-            const int j = j0 + 8 * q;
+    if (nch > 0) {   // uniform over the workgroup; an empty range leaves zero partials
+        d2r_t ra[2][2][4];   // [buffer][row block][16-byte piece]
+        d2r_t xg[NXP];       // the next X chunk on its way to LDS
+        auto loadA = [&](d2r_t (&r)[2][4], int c) __attribute__((always_inline)) {
+            const int j = jb + c * kRChunk + 8 * q;
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb) {
                 const d2r_t *pa = reinterpret_cast<const d2r_t *>(A + j + (int64_t)(i0 + rb * 16 + li) * lda);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) ra[buf][rb][e] = pa[e];
-            }
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const int c = cb * 16 + li;
-                if (c < m) {
-                    const d2r_t *px = reinterpret_cast<const d2r_t *>(X + j + (int64_t)c * ldx);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) rx[buf][cb][e] = px[e];
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) rx[buf][cb][e] = d2r_t{0, 0};
-                }
+                for (int e = 0; e < 4; ++e) r[rb][e] = pa[e];
             }
         };
-        auto mult = [&](int buf) __attribute__((always_inline)) {
+        auto loadX = [&](int c) __attribute__((always_inline)) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int u = 0; u < NXP; ++u) {
+                const int p = threadIdx.x + 256 * u, col = p >> 4, jj = (p & 15) * 2;
+                xg[u] = col < m ? *reinterpret_cast<const d2r_t *>(X + jb + c * kRChunk + jj + (int64_t)col * ldx)
+                                : d2r_t{0, 0};
+            }
+        };
+        auto storeX = [&](int buf) __attribute__((always_inline)) {
+            double *xs = xs_raw + buf * MC * kRXld;
+#pragma unroll
+            for (int u = 0; u < NXP; ++u) {
+                const int p = threadIdx.x + 256 * u;
+                *reinterpret_cast<d2r_t *>(xs + (p >> 4) * kRXld + (p & 15) * 2) = xg[u];
+            }
+        };
+        auto mult = [&](const d2r_t (&r)[2][4], int buf) __attribute__((always_inline)) {
+            const double *xs = xs_raw + buf * MC * kRXld + li * kRXld + 8 * q;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                d2r_t xf[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) xf[cb] = *reinterpret_cast<const d2r_t *>(xs + cb * 16 * kRXld + 2 * e);
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb)
-                            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(rx[buf][cb][e][h], ra[buf][rb][e][h],
-                                                                               acc[rb][cb], 0, 0, 0);
+                            acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xf[cb][h], r[rb][e][h], acc[rb][cb], 0, 0, 0);
+            }
         };
-        load(0, jb);
-        // two chunks per trip: the register buffers are indexed by constants
-        for (int j0 = jb; j0 < je; j0 += 2 * kRChunk) {
-            if (j0 + kRChunk < je) load(1, j0 + kRChunk);
-            mult(0);
-            if (j0 + kRChunk >= je) break;
-            if (j0 + 2 * kRChunk < je) load(0, j0 + 2 * kRChunk);
-            mult(1);
+        // chunk c: A in ra[c % 2] (loaded one chunk ahead), X in LDS buffer c & 1
+        auto step = [&](auto cur, int c) __attribute__((always_inline)) {
+            constexpr int B = decltype(cur)::value;
+            if (c + 1 < nch) loadA(ra[B ^ 1], c + 1);
+            mult(ra[B], c & 1);
+            if (c + 1 < nch) {
+                storeX((c + 1) & 1);   // its last readers finished before the previous barrier
+                if (c + 2 < nch) loadX(c + 2);
+            }
+            __syncthreads();
+        };
+        loadA(ra[0], 0);
+        loadX(0);
+        storeX(0);
+        if (nch > 1) loadX(1);
+        __syncthreads();
+        for (int c = 0; c < nch; c += 2) {
+            step(std::integral_constant<int, 0>{}, c);
+            if (c + 1 >= nch) break;
+            step(std::integral_constant<int, 1>{}, c + 1);
         }
     }
     // lane l, register r: row i0 + rb*16 + l%16, column cb*16 + l/16 + 4r
@@ -858,14 +887,16 @@ hipError_t launch_residual(const double *A, int64_t lda, int npad, const double 
     const int ns = residual_splits(npad);
     const int jspan = (int)round_up((npad + ns - 1) / ns, kRChunk);
     const dim3 grid(npad / kRRows, ns);
+    const int mc = m <= 16 ? 16 : m <= 32 ? 32 : m <= 48 ? 48 : 64;   // the instance launched below
+    const size_t smem = (size_t)2 * mc * kRXld * 8;
     if (m <= 16)
-        hipLaunchKernelGGL(residual_partial_kernel<16>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
+        hipLaunchKernelGGL(residual_partial_kernel<16>, grid, dim3(256), smem, st, A, lda, npad, X, ldx, m, jspan, partial);
     else if (m <= 32)
-        hipLaunchKernelGGL(residual_partial_kernel<32>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
+        hipLaunchKernelGGL(residual_partial_kernel<32>, grid, dim3(256), smem, st, A, lda, npad, X, ldx, m, jspan, partial);
     else if (m <= 48)   // FP64 MFMA work grows with the padded width: 48 saves a quarter against 64
-        hipLaunchKernelGGL(residual_partial_kernel<48>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
+        hipLaunchKernelGGL(residual_partial_kernel<48>, grid, dim3(256), smem, st, A, lda, npad, X, ldx, m, jspan, partial);
     else
-        hipLaunchKernelGGL(residual_partial_kernel<64>, grid, dim3(256), 0, st, A, lda, npad, X, ldx, m, jspan, partial);
+        hipLaunchKernelGGL(residual_partial_kernel<64>, grid, dim3(256), smem, st, A, lda, npad, X, ldx, m, jspan, partial);
     hipLaunchKernelGGL(residual_finish_kernel, dim3((npad + 255) / 256, m), dim3(256), 0, st, partial, ns, npad, m, B,
                        ldb, R, ldr);
     return hipGetLastError();
