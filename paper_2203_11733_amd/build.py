@@ -42,7 +42,7 @@ def _compile(src: str, extra: list[str]) -> str:
     obj = os.path.join(BUILD, src + ".o")
     cmd = [hipcc(), "-c", "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function",
+           "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function", "-Werror=return-type",
            *extra, "-o", obj, os.path.join(CSRC, src)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
