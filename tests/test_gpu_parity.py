@@ -347,6 +347,43 @@ def test_capacitance_mixed_vs_oracle(ctx, factor):
     assert rep["residual"] <= 1e-8
 
 
+def test_tile_shapes_same_capacitance(ctx):
+    """The Cholesky tile shapes (outer panel width 256 / 512, outer panels per
+    16-bit trailing update 1 / 2 / 4, forced as the autotuner forces them) are
+    schedule parameters only: every shape gives the oracle's capacitances of
+    the same mesh (a random layout of about 6,000 panels, padded order 6,144:
+    24 or 12 outer panels, super-panels with a ragged last one) within the
+    path's bar."""
+    rng = np.random.default_rng(12)
+    lay = None
+    for _ in range(100):
+        lay = gi.random_manhattan(rng, n_target=6000)
+        if 5000 <= mesh(lay)[0].shape[0] <= 6100:
+            break
+    lo, hi, cond = mesh(lay)
+    m = lay.n_conductors
+    say(f"tile shapes: N={lo.shape[0]} M={m}")
+    ref = oracle.extract_panels(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, 3, 2.0)
+    try:
+        for ow in (256, 512):
+            binding.set_tuning_override(ow, 0)
+            C, rep = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m, binding.make_opts())
+            err = rel_err(C, ref)
+            say(f"  f64 outer_width {ow}: {err:.2e} (report {rep['outer_width']})")
+            assert rep["outer_width"] == ow
+            assert err <= 1e-10
+            for sp in (1, 2, 4):
+                binding.set_tuning_override(ow, sp)
+                C, rep = ctx.extract(lo, hi, cond, m, lay.eps_r, lay.length_unit_m,
+                                     binding.make_opts(3, 2.0, "f32", "f16", 1e-8, 40))
+                err = rel_err(C, ref)
+                say(f"  mixed {ow} x {sp}: {err:.2e}, {rep['refine_iters']} sweeps")
+                assert (rep["outer_width"], rep["super_panels"]) == (ow, sp)
+                assert err <= 1e-6
+    finally:
+        binding.set_tuning_override(0, 0)
+
+
 @pytest.mark.parametrize("layout,factor", [
     (gi.crossing_bars_in_box(), "bf16"),
     (gi.three_layer_bus(n_per_layer=8, h=0.25), "f16"),
