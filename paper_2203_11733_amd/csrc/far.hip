@@ -29,16 +29,16 @@ template <> __device__ __forceinline__ float rsqrt_t<float>(float x)
     return __builtin_amdgcn_rsqf(x);
 }
 
-// Hardware reciprocal square root refined by two Newton steps
-// y <- y + y/2 (1 - x y^2), each squaring the relative error.
+// Hardware reciprocal square root refined by one Newton step
+// y <- y (3 - x y^2) / 2, which squares its relative error: the hardware
+// value is within 2^-24.2 of 1/sqrt(x) on gfx950 and the refined one within
+// 4.2e-15 (measured over 4e7 arguments spanning 40 binades), far below what
+// the far rule's quadrature error or the entries' 5e-12 parity bar resolve.
+// (Two steps cost four more instructions per evaluation: 12.5 against 8.5.)
 template <> __device__ __forceinline__ double rsqrt_t<double>(double x)
 {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = __builtin_fma(-x * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    e = __builtin_fma(-x * y, y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    return (0.5 * y) * __builtin_fma(-x * y, y, 3.0);
 }
 
 // fused multiply-add in the arithmetic type itself (the plain builtin is the
