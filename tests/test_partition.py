@@ -264,3 +264,29 @@ def test_gpu_partitioned_extraction_three_nets(ctx):
     say(f"  random4 panels {panels.tolist()} rel {_rel(C, Co):.2e}")
     assert panels.tolist() == po
     assert _rel(C, Co) < 1e-10
+
+
+@pytest.mark.gpu
+def test_gpu_table2_size_594(ctx):
+    """Section 5, Table 2, 594-panel row on the GPU: the rule (1.5, 4, 0.5, 4)
+    meshes each main net with about 594 pieces; the library's partitioned
+    extraction equals the oracle's (FP64, 1e-10) and lands within 2 % of the
+    paper's capacitances in both modes."""
+    with open(os.path.join(GOLDEN, "table2_crossing_bars.json")) as f:
+        g = json.load(f)
+    row = [r for r in g["gbem"] if r["panels"] == 594][0]
+    blo, bhi, bc = BARS.arrays()
+    prm = (1.5, 4.0, 0.5, 4.0)
+    C, panels, rep = ctx.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, *prm)
+    Co, po = op.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, *prm)
+    o = binding.make_opts(3, 2.0, "f32", "f16", 1e-8, 40)
+    Cm, _, _ = ctx.extract_partitioned(blo, bhi, bc, 2, BARS.eps_r, BARS.length_unit_m, *prm, opts=o)
+    say(f"  594-size GPU C (aF) {np.round(C * 1e18, 2).tolist()} panels {panels.tolist()} vs oracle {_rel(C, Co):.2e}")
+    assert panels.tolist() == po
+    assert all(abs(n - 594) <= 0.02 * 594 for n in po)
+    assert _rel(C, Co) < 1e-10
+    assert _rel(Cm, Co) < 1e-6
+    for M in (C, Cm):
+        M = M * 1e18
+        for key, val in (("C11", M[0, 0]), ("C12", M[0, 1]), ("C21", M[1, 0]), ("C22", M[1, 1])):
+            assert abs(val - row[key]) <= 0.02 * abs(row[key]), (key, val)
