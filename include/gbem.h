@@ -273,10 +273,18 @@ typedef struct {
     double p3;   /* > 0: factor of the far bound */
     double p5;   /* > 0: distance (length unit) where the far bound starts */
 } gbem_partition;
-/* Mesh for main net main_net (a conductor id of box_cond); arrays as for
- * gbem_mesh_boxes (library-allocated, free with gbem_mesh_buf_free).
- * GBEM_EINVAL: invalid rule, no box on main_net, intersecting boxes, or a
- * rule that asks for more than 2^29 panels or pieces below 1e-12 of a face. */
+/* main_net value for one mesh refined around every conductor: the union of
+ * all boxes with a conductor id >= 0 acts as the main net (distance to the
+ * nearest of them, faces of any conductor facing), so one mesh and one
+ * system serve every column of C and C is symmetric by construction.  This
+ * is the reading under which the paper's Table 2 (section 5) prints
+ * C12 = C21 at every mesh size. */
+#define GBEM_ALL_NETS (-2)
+/* Mesh for main net main_net (a conductor id of box_cond, or GBEM_ALL_NETS);
+ * arrays as for gbem_mesh_boxes (library-allocated, free with
+ * gbem_mesh_buf_free).  GBEM_EINVAL: invalid rule, no box on main_net,
+ * intersecting boxes, or a rule that asks for more than 2^29 panels or
+ * pieces below 1e-12 of a face. */
 gbem_status gbem_mesh_partition(const double *box_lo, const double *box_hi, const int32_t *box_cond,
                                 int32_t n_boxes, int32_t main_net, const gbem_partition *rule,
                                 gbem_mesh_buf *out);

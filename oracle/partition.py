@@ -29,6 +29,12 @@ by the tests as the definition):
     area = (hi1 - lo1) * (hi2 - lo2).
 Output order: boxes as given; faces -x, +x, -y, +y, -z, +z.
 
+Section 5's Table 2 prints C12 = C21 at every mesh size, which per-main-net
+meshes do not give at 74 or 183 panels (the other net is meshed coarsely in
+each).  Its reading here: one mesh refined around every conductor at once
+(main_net = ALL_NETS: the union of all conductor boxes is the main net), so
+one symmetric system yields every column and C is symmetric.
+
 Pure Python (no shared code with the GPU library); meant for meshes of up to
 a few thousand panels.
 """
@@ -86,12 +92,21 @@ def faces_main_net(box_lo, box_hi, on_net: bool, net, nrm: int, upper: bool) -> 
     return any(b[0][nrm] < plane for b in net)
 
 
+ALL_NETS = -2   # main_net value: every conductor together is the main net
+
+
+def _on_main(c: int, main_net: int) -> bool:
+    return c >= 0 if main_net == ALL_NETS else c == main_net
+
+
 def mesh_partition(blo, bhi, bcond, main_net: int, p1: float, p2: float, p3: float, p5: float):
-    """Boxes -> panels (lo, hi, cond) for one main net."""
+    """Boxes -> panels (lo, hi, cond) for one main net, or for all conductors
+    together (main_net = ALL_NETS: distance to the nearest conductor box, every
+    conductor face facing), one mesh for every column of C."""
     blo = [tuple(float(v) for v in row) for row in np.asarray(blo, dtype=np.float64).reshape(-1, 3)]
     bhi = [tuple(float(v) for v in row) for row in np.asarray(bhi, dtype=np.float64).reshape(-1, 3)]
     bcond = [int(c) for c in np.asarray(bcond).reshape(-1)]
-    net = [(blo[b], bhi[b]) for b in range(len(blo)) if bcond[b] == main_net]
+    net = [(blo[b], bhi[b]) for b in range(len(blo)) if _on_main(bcond[b], main_net)]
     if not net:
         raise ValueError("no box on the main net")
     out_lo, out_hi, out_c = [], [], []
@@ -121,7 +136,7 @@ def mesh_partition(blo, bhi, bcond, main_net: int, p1: float, p2: float, p3: flo
         for f in range(6):
             nrm, upper = f // 2, bool(f & 1)
             plane = bhi[b][nrm] if upper else blo[b][nrm]
-            facing = faces_main_net(blo[b], bhi[b], bcond[b] == main_net, net, nrm, upper)
+            facing = faces_main_net(blo[b], bhi[b], _on_main(bcond[b], main_net), net, nrm, upper)
             p4 = p1 if facing else p1 * p2
             t1, t2 = _in_plane(nrm)
             refine(nrm, plane, blo[b][t1], bhi[b][t1], blo[b][t2], bhi[b][t2], p4, bcond[b])
@@ -143,4 +158,13 @@ def extract_partitioned(blo, bhi, bcond, n_conductors: int, eps_r: float, length
     return C, panels
 
 
-__all__ = ["area_bound", "faces_main_net", "mesh_partition", "extract_partitioned"]
+def extract_shared(blo, bhi, bcond, n_conductors: int, eps_r: float, length_unit_m: float,
+                   p1: float, p2: float, p3: float, p5: float, p: int = 3, eta: float = 2.0):
+    """All of C from one mesh refined around every conductor (the reading of
+    section 5's Table 2, whose coupling columns agree at every size).
+    Returns (C, panel count)."""
+    lo, hi, cond = mesh_partition(blo, bhi, bcond, ALL_NETS, p1, p2, p3, p5)
+    return _o.extract_panels(lo, hi, cond, n_conductors, eps_r, length_unit_m, p, eta), lo.shape[0]
+
+
+__all__ = ["ALL_NETS", "area_bound", "faces_main_net", "mesh_partition", "extract_partitioned", "extract_shared"]

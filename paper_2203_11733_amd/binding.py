@@ -240,8 +240,12 @@ def _take_buf(lib, buf):
     return lo, hi, cond
 
 
+ALL_NETS = -2   # gbem.h GBEM_ALL_NETS: one mesh refined around every conductor
+
+
 def mesh_partition(box_lo, box_hi, box_cond, main_net, p1, p2, p3, p5):
-    """Library mesher, partition rule of section 3.3 for one main net: (lo, hi, cond)."""
+    """Library mesher, partition rule of section 3.3 for one main net (or
+    ALL_NETS): (lo, hi, cond)."""
     lib = load()
     blo = np.ascontiguousarray(box_lo, dtype=np.float64).reshape(-1, 3)
     bhi = np.ascontiguousarray(box_hi, dtype=np.float64).reshape(-1, 3)

@@ -283,10 +283,12 @@ extern "C" gbem_status gbem_mesh_partition(const double *box_lo, const double *b
         set_error("gbem_mesh_partition: " + why);
         return GBEM_EINVAL;
     }
+    // boxes of the main net: one conductor, or every conductor (GBEM_ALL_NETS)
+    auto on_main = [&](int b) { return main_net == GBEM_ALL_NETS ? box_cond[b] >= 0 : box_cond[b] == main_net; };
     NetBoxes net;
     double nlo[3] = {INFINITY, INFINITY, INFINITY}, nhi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int b = 0; b < n_boxes; ++b)
-        if (box_cond[b] == main_net)
+        if (on_main(b))
             for (int k = 0; k < 3; ++k) {
                 net.lo.push_back(box_lo[3 * b + k]);
                 net.hi.push_back(box_hi[3 * b + k]);
@@ -309,7 +311,7 @@ extern "C" gbem_status gbem_mesh_partition(const double *box_lo, const double *b
             const int nrm = f / 2;
             const bool upper = f & 1;
             const double plane = upper ? bh[nrm] : bl[nrm];
-            bool facing = box_cond[b] == main_net || contains;
+            bool facing = on_main(b) || contains;
             if (!facing) {
                 for (size_t q = 0; q < net.lo.size() / 3 && !facing; ++q)
                     facing = upper ? net.hi[3 * q + nrm] > plane : net.lo[3 * q + nrm] < plane;
