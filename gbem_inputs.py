@@ -198,3 +198,142 @@ def random_small_layout(seed: int, n_boxes: int = 3, h: float = 0.25) -> Layout:
         if ok:
             boxes.append((tuple(float(x) for x in lo), tuple(float(x) for x in hi), len(boxes)))
     return Layout(f"random{seed}", boxes, len(boxes), ("uniform", h), 1.0)
+
+
+# ---------------------------------------------------------------- several dielectrics
+# Panel kinds of a multi-dielectric mesh (the numbering of gbem_panel_kind).
+CONDUCTOR, DIRICHLET, NEUMANN, INTERFACE = 0, 1, 2, 3
+
+
+@dataclass
+class DielectricMesh:
+    """Panels with their kind, net and the dielectric region on each side.
+
+    lo, hi: (n, 3) corners (exactly one zero extent, the normal axis);
+    region_plus / region_minus: region on the + / - side along that axis, -1
+    where there is none (inside a conductor, outside the domain)."""
+    name: str
+    lo: np.ndarray
+    hi: np.ndarray
+    kind: np.ndarray
+    conductor: np.ndarray
+    region_plus: np.ndarray
+    region_minus: np.ndarray
+    eps_r: list
+    n_conductors: int
+    length_unit_m: float = MICRON
+
+    @property
+    def n_panels(self) -> int:
+        return int(self.lo.shape[0])
+
+    def args(self):
+        """Positional arguments of the extractors: lo, hi, kind, conductor,
+        region_plus, region_minus, eps_r, n_conductors, length_unit_m."""
+        return (self.lo, self.hi, self.kind, self.conductor, self.region_plus, self.region_minus, self.eps_r,
+                self.n_conductors, self.length_unit_m)
+
+
+def _face_grid(nrm, plane, r1, r2, n1, n2):
+    """n1 x n2 equal rectangles of the face {x_nrm = plane} spanning r1 along
+    the first in-plane axis and r2 along the second (axes in increasing order)."""
+    t1, t2 = [k for k in range(3) if k != nrm]
+    out = []
+    for i in range(n1):
+        for j in range(n2):
+            lo = [0.0] * 3
+            hi = [0.0] * 3
+            lo[nrm] = hi[nrm] = plane
+            lo[t1] = r1[0] + (r1[1] - r1[0]) * i / n1
+            hi[t1] = r1[0] + (r1[1] - r1[0]) * (i + 1) / n1
+            lo[t2] = r2[0] + (r2[1] - r2[0]) * j / n2
+            hi[t2] = r2[0] + (r2[1] - r2[0]) * (j + 1) / n2
+            out.append((lo, hi))
+    return out
+
+
+def _cells(length, h):
+    return max(1, int(math.ceil(length / h - 1e-9)))
+
+
+class _PanelList:
+    def __init__(self):
+        self.rows = []
+
+    def face(self, nrm, plane, r1, r2, h, kind, cond, rp, rm):
+        for lo, hi in _face_grid(nrm, plane, r1, r2, _cells(r1[1] - r1[0], h), _cells(r2[1] - r2[0], h)):
+            self.rows.append((lo, hi, kind, cond, rp, rm))
+
+    def box_surface(self, lo, hi, h, kind, cond, region, outside):
+        """The six faces of a box; `region` lies outside it when `outside`
+        (a conductor in a dielectric) and inside it otherwise (the domain)."""
+        for nrm in range(3):
+            t1, t2 = [k for k in range(3) if k != nrm]
+            r1, r2 = (lo[t1], hi[t1]), (lo[t2], hi[t2])
+            # the face at lo[nrm] has the box interior on its + side
+            inner_plus = (-1, region) if outside else (region, -1)
+            self.face(nrm, lo[nrm], r1, r2, h, kind, cond, *inner_plus)
+            self.face(nrm, hi[nrm], r1, r2, h, kind, cond, *inner_plus[::-1])
+
+    def mesh(self, name, eps_r, n_conductors, length_unit_m=MICRON):
+        cols = list(zip(*self.rows))
+        return DielectricMesh(name, np.array(cols[0], float), np.array(cols[1], float),
+                              np.array(cols[2], np.int32), np.array(cols[3], np.int32),
+                              np.array(cols[4], np.int32), np.array(cols[5], np.int32), list(eps_r), n_conductors,
+                              length_unit_m)
+
+
+def two_slab_capacitor(L=1.0, d1=0.3, d2=0.7, n_xy=4, n_z=2, eps_r=(4.0, 1.0)) -> DielectricMesh:
+    """Plates z = 0 (net 1) and z = d1 + d2 (net 0) of side L, region 0 in
+    0 < z < d1, region 1 above, the interface at z = d1, Neumann side walls
+    (no fringing field: the exact capacitance per unit permittivity is
+    L^2 / (d1 / eps_0 + d2 / eps_1))."""
+    H = d1 + d2
+    pl = _PanelList()
+    for lo, hi in _face_grid(2, 0.0, (0, L), (0, L), n_xy, n_xy):
+        pl.rows.append((lo, hi, CONDUCTOR, 1, 0, -1))
+    for lo, hi in _face_grid(2, H, (0, L), (0, L), n_xy, n_xy):
+        pl.rows.append((lo, hi, CONDUCTOR, 0, -1, 1))
+    for lo, hi in _face_grid(2, d1, (0, L), (0, L), n_xy, n_xy):
+        pl.rows.append((lo, hi, INTERFACE, -1, 1, 0))
+    for z0, z1, reg in ((0.0, d1, 0), (d1, H, 1)):
+        for nrm in (0, 1):
+            for plane, plus in ((0.0, True), (L, False)):
+                for lo, hi in _face_grid(nrm, plane, (0, L), (z0, z1), n_xy, n_z):
+                    pl.rows.append((lo, hi, NEUMANN, -1, reg if plus else -1, -1 if plus else reg))
+    return pl.mesh(f"two_slab_{n_xy}x{n_z}", eps_r, 2)
+
+
+def layered_stack(n_wires: int = 3, h: float = 0.25, h_out: float | None = None,
+                  eps_r=(3.9, 2.7, 4.2)) -> DielectricMesh:
+    """Synthetic interconnect stack with several dielectrics: three layers in
+    a W x W x H domain (grounded top and bottom, Neumann side walls, two
+    interfaces), n_wires parallel wires along x in layer 1 and n_wires along
+    y in layer 2 (2 n_wires nets, each wire inside one layer).  Conductor
+    faces are split into cells of at most h, the interfaces and the domain
+    boundary into cells of at most h_out (default 2 h).  Micrometres."""
+    h_out = 2.0 * h if h_out is None else h_out
+    W = 2.0 + 1.0 * n_wires
+    z = (0.0, 1.0, 2.2, 3.6)                       # layer boundaries
+    pl = _PanelList()
+    wires = []
+    for k in range(n_wires):                       # layer 1: along x, 0.4 wide, 0.5 thick
+        y0 = 1.3 + 1.0 * k
+        wires.append(((0.6, y0, 1.35), (W - 0.6, y0 + 0.4, 1.85), 1))
+    for k in range(n_wires):                       # layer 2: along y
+        x0 = 1.3 + 1.0 * k
+        wires.append(((x0, 0.6, 2.6), (x0 + 0.4, W - 0.6, 3.1), 2))
+    for c, (lo, hi, layer) in enumerate(wires):
+        assert z[layer] < lo[2] and hi[2] < z[layer + 1]
+        pl.box_surface(lo, hi, h, CONDUCTOR, c, layer, outside=True)
+    # grounded bottom and top, interfaces between the layers
+    pl.face(2, z[0], (0, W), (0, W), h_out, DIRICHLET, -1, 0, -1)
+    pl.face(2, z[3], (0, W), (0, W), h_out, DIRICHLET, -1, -1, 2)
+    for a in (1, 2):
+        pl.face(2, z[a], (0, W), (0, W), h_out, INTERFACE, -1, a, a - 1)
+    # Neumann side walls, split at the layer boundaries
+    for a in range(3):
+        for nrm in (0, 1):
+            pl.face(nrm, 0.0, (0, W), (z[a], z[a + 1]), h_out, NEUMANN, -1, a, -1)
+            pl.face(nrm, W, (0, W), (z[a], z[a + 1]), h_out, NEUMANN, -1, -1, a)
+    return pl.mesh(f"layered_stack_{2 * n_wires}nets_h{h:g}", eps_r, 2 * n_wires)

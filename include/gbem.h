@@ -307,6 +307,59 @@ gbem_status gbem_extract_partitioned(gbem_ctx *ctx, const double *box_lo, const 
                                      const gbem_opts *opts, double *C_out, int32_t *panels_out,
                                      gbem_report *rep);
 
+/* ---- several dielectrics (section 4) ---------------------------------------
+ * In each dielectric region the potential solves Laplace's equation; on the
+ * boundary of a region, Green's identity ties the potential u and its normal
+ * derivative q (along the region's outward normal) through the single-layer
+ * integrals G and the double-layer integrals Q of section 4.2.  With u and q
+ * constant per panel the Galerkin form has one equation per (region, panel
+ * on its boundary) (section 4.1):
+ *     1/2 |I_i| u_i + sum_k Q_ik u_k = sum_j G_ij q_j.
+ * Unknowns: q on conductor and Dirichlet panels, u on Neumann panels, u and
+ * q on interface panels (the neighbour region's q follows from
+ * eps_a q_a = -eps_b q_b, section 2.1); u = 1 on the main net, 0 on the other
+ * nets and on Dirichlet panels. */
+typedef enum {
+    GBEM_PANEL_CONDUCTOR = 0,   /* on net `conductor` (u known), one region side */
+    GBEM_PANEL_DIRICHLET = 1,   /* grounded outer boundary (u = 0), one region side */
+    GBEM_PANEL_NEUMANN = 2,     /* outer boundary with du/dn = 0, one region side */
+    GBEM_PANEL_INTERFACE = 3    /* between two different regions */
+} gbem_panel_kind;
+
+/* A multi-dielectric mesh.  Panels are axis-aligned rectangles as in
+ * gbem_mesh (lo, hi: [3 * n_panels]); region_plus[i] / region_minus[i] name
+ * the region on the + / - side of panel i along its normal axis, in
+ * [0, n_regions), or -1 where there is none (inside a conductor, outside the
+ * domain); eps_r[n_regions] > 0.  conductor[i] is read for conductor panels
+ * only (in [0, n_conductors), every net with at least one panel). */
+typedef struct {
+    int32_t n_panels;
+    int32_t n_conductors;       /* 1..64 */
+    int32_t n_regions;
+    const double *lo;
+    const double *hi;
+    const int32_t *kind;        /* gbem_panel_kind per panel */
+    const int32_t *conductor;
+    const int32_t *region_plus;
+    const int32_t *region_minus;
+    const double *eps_r;
+    double length_unit_m;       /* metres per coordinate unit, > 0 */
+} gbem_dmesh;
+
+/* Maxwell capacitance matrix of a multi-dielectric mesh (host arrays in and
+ * out): C_out[n * n_conductors + k] = charge on net n (eps0 * sum over its
+ * panels of eps_r q |I|) per volt on net k.  The single-layer entries use
+ * opts->far_order and opts->near_eta in FP64 (far_dtype and factor_dtype are
+ * not read); the system is not symmetric, so it is solved through its normal
+ * equations M^T M x = M^T b by the FP64 Cholesky factorisation and refined
+ * against the residual of M itself until max_k |b_k - M x_k| / |b_k| <=
+ * 1e-13 (at most six sweeps; rep->residual reports it).  GBEM_EINVAL on an
+ * inconsistent mesh (a panel kind with the wrong number of regions, a
+ * conductor id out of range, a net without panels), GBEM_ENOTPD when the
+ * normal equations are singular. */
+gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *mesh, const gbem_opts *opts, double *C_out,
+                                    gbem_report *rep);
+
 /* ---- stage entry points (same kernels as gbem_extract; for parity tests) ---- */
 
 /* Near-pair list of the mesh (host arrays in/out): row_ptr[n+1], col[nnz] with
@@ -328,6 +381,14 @@ gbem_status gbem_assemble_sample(gbem_ctx *ctx, const gbem_mesh *mesh, const gbe
  * is GBEM_F64 (no scaled copy is made) or an index is out of range. */
 gbem_status gbem_assemble_scaled_sample(gbem_ctx *ctx, const gbem_mesh *mesh, const gbem_opts *opts,
                                         int64_t m, const int32_t *ii, const int32_t *jj, float *out);
+/* Double-layer integrals of section 4.2 (host arrays): Q_out[i * n + k] =
+ * Int_{I_i} Int_{I_k} <x - y, n_k> / (4 pi |x - y|^3) with n_k the unit
+ * vector along + the normal axis of panel k; 0 for coplanar pairs.  Pairs of
+ * the near list of near_eta (as in gbem_opts) are integrated in closed form
+ * over both panels; the others take the closed-form integral over I_k (its
+ * solid angle at x over 4 pi) under 6 x 6 Gauss points on I_i. */
+gbem_status gbem_assemble_double_layer(gbem_ctx *ctx, int32_t n_panels, const double *lo, const double *hi,
+                                       double near_eta, double *Q_out);
 /* In-place Cholesky A = L L^T of a device matrix (column-major, lower
  * triangle referenced, leading dimension lda >= n).  dtype GBEM_F64 takes
  * double*, GBEM_F32/F16/BF16 take float* (F16/BF16 = FP32 storage with 16-bit

@@ -92,8 +92,9 @@ def _gl(n):
     return _GL[n]
 
 
-def _rect_gauss(f, lo, hi, t1, t2, n):
-    """Tensor Gauss-Legendre (n x n) of f over the rectangle's in-plane extent."""
+def _rect_nodes(lo, hi, t1, t2, n):
+    """Nodes (n*n x 3) and weights of the n x n tensor Gauss-Legendre rule on
+    a rectangle's in-plane extent."""
     x, w = _gl(n)
     a1, b1, a2, b2 = lo[t1], hi[t1], lo[t2], hi[t2]
     u = 0.5 * (a1 + b1) + 0.5 * (b1 - a1) * x
@@ -103,7 +104,12 @@ def _rect_gauss(f, lo, hi, t1, t2, n):
     pts[:, :] = lo
     pts[:, t1] = U.ravel()
     pts[:, t2] = V.ravel()
-    W = np.outer(w, w).ravel() * 0.25 * (b1 - a1) * (b2 - a2)
+    return pts, np.outer(w, w).ravel() * 0.25 * (b1 - a1) * (b2 - a2)
+
+
+def _rect_gauss(f, lo, hi, t1, t2, n):
+    """Tensor Gauss-Legendre (n x n) of f over the rectangle's in-plane extent."""
+    pts, W = _rect_nodes(lo, hi, t1, t2, n)
     return float(np.dot(W, f(pts)))
 
 
@@ -112,7 +118,8 @@ def double_layer_pair(lo_i, hi_i, lo_k, hi_k, tol=1e-12, n=8, depth=14):
     + its normal axis.  The outer integral: Gauss on I_i against the sum over
     its four quarters, recursing where they differ by more than tol |I_i|
     (the inner integral is bounded, so the recursion ends at the edges where
-    I_i meets the plane of I_k)."""
+    I_i meets the plane of I_k).  The four quarters' rules are evaluated in
+    one call of the inner integral."""
     lo_i = np.asarray(lo_i, float)
     hi_i = np.asarray(hi_i, float)
     lo_k = np.asarray(lo_k, float)
@@ -133,7 +140,9 @@ def double_layer_pair(lo_i, hi_i, lo_k, hi_k, tol=1e-12, n=8, depth=14):
                 ql, qh = lo.copy(), hi.copy()
                 ql[t1], qh[t1], ql[t2], qh[t2] = a1, b1, a2, b2
                 quarters.append((ql, qh))
-        parts = [_rect_gauss(f, ql, qh, t1, t2, n) for ql, qh in quarters]
+        nodes = [_rect_nodes(ql, qh, t1, t2, n) for ql, qh in quarters]
+        vals = f(np.concatenate([p for p, _ in nodes])).reshape(4, n * n)
+        parts = [float(np.dot(w, v)) for (_, w), v in zip(nodes, vals)]
         s = sum(parts)
         sub = (hi[t1] - lo[t1]) * (hi[t2] - lo[t2])
         if abs(s - whole) <= tol * area * max(sub / area, 1e-3) or d >= depth:
@@ -181,12 +190,16 @@ def single_layer_matrix(lo, hi):
     return G
 
 
-def extract(lo, hi, kind, cond, reg_plus, reg_minus, eps_r, n_conductors: int, length_unit_m: float):
+def extract(lo, hi, kind, cond, reg_plus, reg_minus, eps_r, n_conductors: int, length_unit_m: float,
+            single_layer=None):
     """Maxwell capacitance matrix (n_conductors x n_conductors, F) of a
     multi-dielectric mesh.  kind: CONDUCTOR (cond = net id), DIRICHLET
     (grounded outer boundary), NEUMANN (du/dn = 0), INTERFACE; reg_plus /
     reg_minus: region on the + / - side of the panel's normal axis (-1 none);
-    eps_r: relative permittivity per region.  Column k: main net k at 1."""
+    eps_r: relative permittivity per region.  Column k: main net k at 1.
+    single_layer: None for the exact G_ij, or (p, eta) for G_ij as section 3.4
+    computes it (exact near pairs, p x p Gauss far pairs: the oracle's
+    assemble, times the two panel areas)."""
     lo = np.asarray(lo, float).reshape(-1, 3)
     hi = np.asarray(hi, float).reshape(-1, 3)
     kind = np.asarray(kind, int)
@@ -195,7 +208,10 @@ def extract(lo, hi, kind, cond, reg_plus, reg_minus, eps_r, n_conductors: int, l
     rm = np.asarray(reg_minus, int)
     n = lo.shape[0]
     area = np.array([float(np.prod([hi[i][t] - lo[i][t] for t in _axes(lo[i], hi[i])[1:]])) for i in range(n)])
-    G = single_layer_matrix(lo, hi)
+    if single_layer is None:
+        G = single_layer_matrix(lo, hi)
+    else:
+        G = _o.assemble(lo, hi, *single_layer) * np.outer(area, area)
     Q = double_layer_matrix(lo, hi)
     n_reg = int(max(rp.max(), rm.max())) + 1
     # unknown slots: q of conductor / Dirichlet / interface panels (interface:

@@ -28,7 +28,10 @@ EXPORTS = [
     "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
     "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
     "gbem_extract_device_noalloc", "gbem_load_tuning", "gbem_set_tuning_override", "gbem_tuning_source",
+    "gbem_extract_dielectric", "gbem_assemble_double_layer",
 ]
+# gbem_panel_kind
+CONDUCTOR, DIRICHLET, NEUMANN, INTERFACE = range(4)
 
 
 class GbemError(RuntimeError):
@@ -41,6 +44,13 @@ class Mesh(ctypes.Structure):
     _fields_ = [("n_panels", ctypes.c_int32), ("n_conductors", ctypes.c_int32),
                 ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("conductor", ctypes.c_void_p),
                 ("eps_r", ctypes.c_double), ("length_unit_m", ctypes.c_double), ("basis", ctypes.c_int32)]
+
+
+class DMesh(ctypes.Structure):
+    _fields_ = [("n_panels", ctypes.c_int32), ("n_conductors", ctypes.c_int32), ("n_regions", ctypes.c_int32),
+                ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("kind", ctypes.c_void_p),
+                ("conductor", ctypes.c_void_p), ("region_plus", ctypes.c_void_p),
+                ("region_minus", ctypes.c_void_p), ("eps_r", ctypes.c_void_p), ("length_unit_m", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -165,11 +175,15 @@ def load():
                                          ctypes.POINTER(ctypes.c_int32), _vp]
     lib.gbem_cholesky_solve_device.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
                                                ctypes.c_int32, _vp, ctypes.c_int64, _vp]
+    lib.gbem_extract_dielectric.argtypes = [_vp, ctypes.POINTER(DMesh), ctypes.POINTER(Opts), _vp,
+                                            ctypes.POINTER(Report)]
+    lib.gbem_assemble_double_layer.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_double, _vp]
     for name in ("gbem_create", "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit",
                  "gbem_poll", "gbem_wait", "gbem_server_stats", "gbem_mesh_boxes", "gbem_near_list",
                  "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
                  "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
-                 "gbem_extract_device_noalloc", "gbem_load_tuning", "gbem_set_tuning_override"):
+                 "gbem_extract_device_noalloc", "gbem_load_tuning", "gbem_set_tuning_override",
+                 "gbem_extract_dielectric", "gbem_assemble_double_layer"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -346,6 +360,32 @@ class Context:
                                                     ctypes.c_void_p(d_C.data_ptr()), ctypes.c_void_p(st),
                                                     ctypes.byref(rep)))
         return rep.as_dict()
+
+    def extract_dielectric(self, lo, hi, kind, conductor, region_plus, region_minus, eps_r, n_conductors,
+                           length_unit_m, opts: Opts | None = None):
+        """Capacitance matrix of a multi-dielectric mesh (gbem_extract_dielectric).
+        Returns (C, report)."""
+        lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(-1, 3)
+        hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(-1, 3)
+        ints = [np.ascontiguousarray(a, dtype=np.int32).reshape(-1) for a in (kind, conductor, region_plus,
+                                                                               region_minus)]
+        eps = np.ascontiguousarray(eps_r, dtype=np.float64).reshape(-1)
+        m = DMesh(lo.shape[0], n_conductors, eps.shape[0], lo.ctypes.data, hi.ctypes.data, ints[0].ctypes.data,
+                  ints[1].ctypes.data, ints[2].ctypes.data, ints[3].ctypes.data, eps.ctypes.data, length_unit_m)
+        C = np.zeros((n_conductors, n_conductors))
+        rep = Report()
+        o = opts or make_opts()
+        _check(self.lib.gbem_extract_dielectric(self.h, ctypes.byref(m), ctypes.byref(o), _ptr(C), ctypes.byref(rep)))
+        return C, rep.as_dict()
+
+    def assemble_double_layer(self, lo, hi, near_eta=2.0):
+        """Q (n x n) of section 4.2 (gbem_assemble_double_layer)."""
+        lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(-1, 3)
+        hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(-1, 3)
+        n = lo.shape[0]
+        Q = np.zeros((n, n))
+        _check(self.lib.gbem_assemble_double_layer(self.h, n, _ptr(lo), _ptr(hi), near_eta, _ptr(Q)))
+        return Q
 
     def near_list(self, lo, hi, near_eta=2.0):
         n = np.asarray(lo).shape[0]

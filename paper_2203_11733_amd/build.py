@@ -27,6 +27,7 @@ SOURCES = {
     "chol.hip": [],
     "refine.hip": [],
     "solve.hip": [],
+    "dielectric.hip": [],
     "tune.cpp": [],
 }
 

@@ -122,6 +122,8 @@ struct DevBuf {
 // Small results the host reads during an extraction, in pinned memory so a
 // read is one DMA (no staging copy), gathered so that each host wait covers
 // all of them.
+constexpr double kEps0 = 8.8541878128e-12;   // vacuum permittivity, F/m
+
 struct Readback {
     int64_t nnz;
     int32_t bad, info, perr, serr;   // info, perr: flags[1], flags[2] (pivot status, panel wait error)
@@ -589,8 +591,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     const int nchunks = (int)chunks_of(n);
     HIPCHK(ws.partial.ensure((size_t)nchunks * m * m * 8), "alloc partials");
     HIPCHK(launch_charge_partials(X, npad, dcond, n, m, ws.partial.as<double>(), nchunks, st), "charges");
-    const double eps0 = 8.8541878128e-12;
-    HIPCHK(launch_charge_finish(ws.partial.as<double>(), nchunks, m, eps_r * eps0 * lu, dC, st), "charges");
+    HIPCHK(launch_charge_finish(ws.partial.as<double>(), nchunks, m, eps_r * kEps0 * lu, dC, st), "charges");
     HIPCHK(hipEventRecord(ws.ev[3], st), "hipEventRecord");
     HIPCHK(hipMemcpyAsync(&rbk->serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
     if (hC) HIPCHK(hipMemcpyAsync(rbk->C, dC, sizeof(double) * m * m, hipMemcpyDeviceToHost, st), "D2H C");
@@ -1564,5 +1565,305 @@ extern "C" gbem_status gbem_extract_partitioned(gbem_ctx *ctx, const double *box
     memcpy(C_out, C.data(), sizeof(double) * m * m);
     tot.asym = asym_of(C.data(), m);
     if (rep) *rep = tot;
+    return GBEM_OK;
+}
+
+// ------------------------------------------------------------------------
+// Multi-dielectric case (section 4)
+// ------------------------------------------------------------------------
+namespace {
+struct LocalBuf : DevBuf {
+    ~LocalBuf() { release(); }
+};
+}  // namespace
+
+// Panel table, near list (near_eta) and the double-layer matrix Q (n x n,
+// column-major, ldq = n) of the mesh in ws.lo / ws.hi with conductor ids in
+// ws.cond; optionally the single-layer matrix A (FP64 far rule of order p)
+// in ws.A (npad x npad).  Returns the near-pair count in *nnz.
+static gbem_status dl_assemble(gbem_ctx *ctx, int n, int n_cond, double near_eta, int p, bool with_A, DevBuf &Q,
+                               int64_t *nnz, hipStream_t st)
+{
+    Workspace &ws = ctx->ws;
+    const int64_t npad = round_up(n, kPad);
+    HIPCHK(ws.pan.ensure(sizeof(Panel) * n), "alloc panels");
+    HIPCHK(ws.flags.ensure(64), "alloc flags");
+    HIPCHK(ws.cnt.ensure(sizeof(int64_t) * n), "alloc");
+    HIPCHK(ws.rowptr.ensure(sizeof(int64_t) * (n + 1)), "alloc");
+    HIPCHK(ws.nmask.ensure(sizeof(uint64_t) * (size_t)n * near_mask_words(n)), "alloc");
+    HIPCHK(hipMemsetAsync(ws.flags.p, 0, 64, st), "memset");
+    HIPCHK(launch_build_panels(ws.lo.as<double>(), ws.hi.as<double>(), ws.cond.as<int32_t>(), n, n_cond,
+                               ws.pan.as<Panel>(), ws.flags.as<int32_t>(), st), "build_panels");
+    HIPCHK(launch_near_count(ws.lo.as<double>(), ws.hi.as<double>(), n, near_eta * near_eta, ws.cnt.as<int64_t>(),
+                             ws.nmask.as<uint64_t>(), st), "near_count");
+    HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), st), "scan");
+    int64_t cnt = 0;
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, ws.rowptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st), "D2H");
+    HIPCHK(hipMemcpyAsync(&bad, ws.flags.p, 4, hipMemcpyDeviceToHost, st), "D2H");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    if (bad) {
+        set_error("panel " + std::to_string(bad - 1) + " is not an axis-aligned rectangle with exactly one zero extent");
+        return GBEM_EINVAL;
+    }
+    *nnz = cnt;
+    HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(cnt, 1)), "alloc");
+    HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(cnt, 1)), "alloc");
+    HIPCHK(launch_near_fill(ws.nmask.as<uint64_t>(), n, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
+                            ws.ncol.as<int32_t>(), st), "near_fill");
+    HIPCHK(Q.ensure((size_t)n * n * 8), "alloc Q");
+    HIPCHK(launch_double_layer(ws.pan.as<Panel>(), n, ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), cnt,
+                               Q.as<double>(), n, st), "double layer");
+    if (with_A) {
+        HIPCHK(ws.A.ensure((size_t)npad * npad * 8), "alloc A");
+        HIPCHK(ws.semi.ensure(near_semi_bytes(cnt)), "alloc near queue");
+        GaussRule rule;
+        gauss_legendre_rule(p, &rule);
+        HIPCHK(launch_far(ws.pan.as<Panel>(), n, (int)npad, p, rule, GBEM_F64, ws.A.as<double>(), npad, st), "far");
+        HIPCHK(launch_near_eval(ws.lo.as<double>(), ws.hi.as<double>(), ws.pan.as<Panel>(), ws.nrow.as<int32_t>(),
+                                ws.ncol.as<int32_t>(), cnt, ws.A.as<double>(), npad, ws.semi.as<int32_t>(), st),
+               "near_eval");
+    }
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_assemble_double_layer(gbem_ctx *ctx, int32_t n_panels, const double *lo,
+                                                  const double *hi, double near_eta, double *Q_out)
+{
+    if (!ctx || n_panels <= 0 || !lo || !hi || !Q_out || !(near_eta >= kMinNearEta) || !isfinite(near_eta)) {
+        set_error("gbem_assemble_double_layer: null argument, no panels or near_eta < 1e-6");
+        return GBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    Workspace &ws = ctx->ws;
+    const int n = n_panels;
+    hipStream_t st = ctx->stream;
+    HIPCHK(ws.lo.ensure(sizeof(double) * 3 * n), "alloc mesh");
+    HIPCHK(ws.hi.ensure(sizeof(double) * 3 * n), "alloc mesh");
+    HIPCHK(ws.cond.ensure(sizeof(int32_t) * n), "alloc mesh");
+    HIPCHK(hipMemcpyAsync(ws.lo.p, lo, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
+    HIPCHK(hipMemcpyAsync(ws.hi.p, hi, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
+    HIPCHK(hipMemsetAsync(ws.cond.p, 0xff, sizeof(int32_t) * n, st), "memset");   // -1: no conductor
+    LocalBuf Q;
+    int64_t nnz = 0;
+    gbem_status s = dl_assemble(ctx, n, 0, near_eta, 3, false, Q, &nnz, st);
+    if (s != GBEM_OK) return s;
+    std::vector<double> tmp((size_t)n * n);
+    HIPCHK(hipMemcpyAsync(tmp.data(), Q.p, sizeof(double) * n * n, hipMemcpyDeviceToHost, st), "D2H");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) Q_out[(size_t)i * n + k] = tmp[i + (size_t)k * n];
+    return GBEM_OK;
+}
+
+extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *mesh, const gbem_opts *opts,
+                                               double *C_out, gbem_report *rep)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!mesh || !C_out || !mesh->lo || !mesh->hi || !mesh->kind || !mesh->conductor || !mesh->region_plus ||
+        !mesh->region_minus || !mesh->eps_r || mesh->n_panels <= 0 || mesh->n_conductors <= 0 ||
+        mesh->n_conductors > kMaxRhs || mesh->n_regions <= 0 || !(mesh->length_unit_m > 0.0)) {
+        set_error("gbem_extract_dielectric: null argument, no panels, or n_conductors outside 1..64, or no region");
+        return GBEM_EINVAL;
+    }
+    gbem_opts o;
+    if (opts) o = *opts; else gbem_default_opts(&o);
+    std::string why;
+    if (!opts_ok(o, why)) {
+        set_error("gbem_extract_dielectric: " + why);
+        return GBEM_EINVAL;
+    }
+    const int n = mesh->n_panels, M = mesh->n_conductors, R = mesh->n_regions;
+    for (int a = 0; a < R; ++a)
+        if (!(mesh->eps_r[a] > 0.0) || !isfinite(mesh->eps_r[a])) {
+            set_error("gbem_extract_dielectric: eps_r of region " + std::to_string(a) + " must be > 0");
+            return GBEM_EINVAL;
+        }
+    // unknown slots and equations (region-major, panels in order), as in the
+    // section 4.1 system: q on conductor, Dirichlet and interface panels, u on
+    // Neumann and interface panels
+    std::vector<int32_t> u_slot(n, -1), q_slot(n, -1), cond(n, -1), eq_reg, eq_pan;
+    int nu = 0;
+    for (int i = 0; i < n; ++i) {
+        const int k = mesh->kind[i], rp = mesh->region_plus[i], rm = mesh->region_minus[i];
+        const bool rp_ok = rp >= -1 && rp < R, rm_ok = rm >= -1 && rm < R;
+        const int sides = (rp >= 0) + (rm >= 0);
+        bool ok = rp_ok && rm_ok && k >= GBEM_PANEL_CONDUCTOR && k <= GBEM_PANEL_INTERFACE;
+        if (ok && k == GBEM_PANEL_INTERFACE) ok = sides == 2 && rp != rm;
+        else if (ok) ok = sides == 1;
+        if (ok && k == GBEM_PANEL_CONDUCTOR) ok = mesh->conductor[i] >= 0 && mesh->conductor[i] < M;
+        if (!ok) {
+            set_error("gbem_extract_dielectric: panel " + std::to_string(i) +
+                      ": kind, regions or conductor id inconsistent (conductor, Dirichlet and Neumann panels bound "
+                      "one region, interface panels two different ones)");
+            return GBEM_EINVAL;
+        }
+        if (k == GBEM_PANEL_CONDUCTOR) cond[i] = mesh->conductor[i];
+        if (k != GBEM_PANEL_NEUMANN) q_slot[i] = nu++;
+        if (k == GBEM_PANEL_NEUMANN || k == GBEM_PANEL_INTERFACE) u_slot[i] = nu++;
+    }
+    for (int a = 0; a < R; ++a)
+        for (int i = 0; i < n; ++i)
+            if (mesh->region_plus[i] == a || mesh->region_minus[i] == a) {
+                eq_reg.push_back(a);
+                eq_pan.push_back(i);
+            }
+    if ((int)eq_reg.size() != nu) {
+        set_error("gbem_extract_dielectric: equations and unknowns do not match");
+        return GBEM_EINVAL;
+    }
+    for (int k = 0; k < M; ++k) {
+        bool any = false;
+        for (int i = 0; i < n && !any; ++i) any = cond[i] == k;
+        if (!any) {
+            set_error("gbem_extract_dielectric: conductor " + std::to_string(k) + " has no panels");
+            return GBEM_EINVAL;
+        }
+    }
+    if (!ctx) {
+        set_error("gbem_extract_dielectric: no context");
+        return GBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    Workspace &ws = ctx->ws;
+    hipStream_t st = ctx->stream;
+    HIPCHK(ws.lo.ensure(sizeof(double) * 3 * n), "alloc mesh");
+    HIPCHK(ws.hi.ensure(sizeof(double) * 3 * n), "alloc mesh");
+    HIPCHK(ws.cond.ensure(sizeof(int32_t) * n), "alloc mesh");
+    HIPCHK(hipMemcpyAsync(ws.lo.p, mesh->lo, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
+    HIPCHK(hipMemcpyAsync(ws.hi.p, mesh->hi, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
+    HIPCHK(hipMemcpyAsync(ws.cond.p, cond.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st), "H2D");
+    // per-panel and per-equation tables in one device block of int32
+    LocalBuf tab, epsb, Q, Mb, Bb, N, X, Rr, D, Cd, nrm;
+    const size_t ntab = (size_t)6 * n + 2 * (size_t)nu;
+    HIPCHK(tab.ensure(sizeof(int32_t) * ntab), "alloc");
+    std::vector<int32_t> htab(ntab);
+    for (int i = 0; i < n; ++i) {
+        htab[i] = mesh->kind[i];
+        htab[n + i] = cond[i];
+        htab[2 * n + i] = mesh->region_plus[i];
+        htab[3 * n + i] = mesh->region_minus[i];
+        htab[4 * n + i] = u_slot[i];
+        htab[5 * n + i] = q_slot[i];
+    }
+    for (int r = 0; r < nu; ++r) {
+        htab[6 * (size_t)n + r] = eq_reg[r];
+        htab[6 * (size_t)n + nu + r] = eq_pan[r];
+    }
+    HIPCHK(hipMemcpyAsync(tab.p, htab.data(), sizeof(int32_t) * ntab, hipMemcpyHostToDevice, st), "H2D");
+    HIPCHK(epsb.ensure(sizeof(double) * R), "alloc");
+    HIPCHK(hipMemcpyAsync(epsb.p, mesh->eps_r, sizeof(double) * R, hipMemcpyHostToDevice, st), "H2D");
+    const int32_t *d_kind = tab.as<int32_t>(), *d_cond = d_kind + n, *d_rp = d_kind + 2 * n, *d_rm = d_kind + 3 * n,
+                  *d_us = d_kind + 4 * n, *d_qs = d_kind + 5 * n, *d_er = d_kind + 6 * (size_t)n,
+                  *d_ep = d_er + nu;
+    int64_t nnz = 0;
+    gbem_status s = dl_assemble(ctx, n, M, o.near_eta, o.far_order, true, Q, &nnz, st);
+    if (s != GBEM_OK) return s;
+    const int64_t npadA = round_up(n, kPad), npad = round_up(nu, kPad);
+    const auto t_asm = std::chrono::steady_clock::now();
+    // the section 4.1 system M X = B (one column per main net)
+    HIPCHK(Mb.ensure((size_t)nu * nu * 8), "alloc M");
+    HIPCHK(Bb.ensure((size_t)nu * M * 8), "alloc B");
+    HIPCHK(hipMemsetAsync(Mb.p, 0, (size_t)nu * nu * 8, st), "memset");
+    HIPCHK(launch_dl_system(ws.pan.as<Panel>(), n, ws.A.as<double>(), npadA, Q.as<double>(), n, d_kind, d_cond, d_rp,
+                            d_rm, epsb.as<double>(), d_er, d_ep, d_us, d_qs, nu, M, Mb.as<double>(), nu,
+                            Bb.as<double>(), nu, st), "system");
+    // normal equations M^T M X = M^T B on the FP64 Cholesky (the system is not
+    // symmetric), then FP64 refinement with the residual of M itself
+    HIPCHK(N.ensure((size_t)npad * npad * 8), "alloc N");
+    HIPCHK(X.ensure((size_t)npad * M * 8), "alloc X");
+    HIPCHK(D.ensure((size_t)npad * M * 8), "alloc D");
+    HIPCHK(Rr.ensure((size_t)nu * M * 8), "alloc R");
+    HIPCHK(nrm.ensure(sizeof(double) * 2 * kMaxRhs), "alloc");
+    HIPCHK(hipMemsetAsync(N.p, 0, (size_t)npad * npad * 8, st), "memset");
+    HIPCHK(launch_dgemm(true, nu, nu, nu, 1.0, Mb.as<double>(), nu, Mb.as<double>(), nu, 0.0, N.as<double>(), npad, st),
+           "M^T M");
+    HIPCHK(launch_identity_pad(N.p, npad, nu, (int)npad, true, st), "pad");
+    HIPCHK(hipMemsetAsync(X.p, 0, (size_t)npad * M * 8, st), "memset");
+    HIPCHK(hipMemsetAsync(D.p, 0, (size_t)npad * M * 8, st), "memset");
+    HIPCHK(launch_dgemm(true, nu, M, nu, 1.0, Mb.as<double>(), nu, Bb.as<double>(), nu, 0.0, X.as<double>(), npad, st),
+           "M^T B");
+    HIPCHK(ws.Winv.ensure(chol_winv_bytes(GBEM_F64, npad)), "alloc W");
+    HIPCHK(ws.Pw.ensure(chol_panel_bytes(GBEM_F64, npad)), "alloc panel");
+    HIPCHK(ws.P16.ensure(std::max<size_t>(chol_panel16_bytes(GBEM_F64, npad), 64)), "alloc panel16");
+    HIPCHK(hipMemsetAsync(ws.flags.p, 0, 64, st), "memset");
+    HIPCHK(ws.ensure_side(), "side stream");
+    HIPCHK(chol_factor(GBEM_F64, npad, N.p, npad, ws.Winv.p, ws.Pw.p, ws.P16.p, ws.flags.as<int32_t>() + 1, st, ws.side,
+                       ws.fev), "cholesky");
+    int32_t ie[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(ie, ws.flags.as<int32_t>() + 1, 8, hipMemcpyDeviceToHost, st), "D2H");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    if (ie[1]) {
+        set_error("Cholesky: a panel wait exceeded its poll limit");
+        return GBEM_EDEVICE;
+    }
+    if (ie[0] != 0 && ie[0] <= nu) {
+        set_error("gbem_extract_dielectric: the normal equations of the system are singular (check the mesh)");
+        return GBEM_ENOTPD;
+    }
+    const auto t_fac = std::chrono::steady_clock::now();
+    HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
+    HIPCHK(chol_solve_prep(GBEM_F64, npad, N.p, npad, ws.Winv.p, ws.sync, st), "solve prep");
+    auto solve = [&](DevBuf &rhs) -> gbem_status {
+        HIPCHK(hipMemsetAsync(ws.sync.err, 0, 4, st), "memset");
+        HIPCHK(chol_solve(GBEM_F64, npad, N.p, npad, ws.Winv.p, M, rhs.as<double>(), npad, ws.sync, st), "solve");
+        int32_t serr = 0;
+        HIPCHK(hipMemcpyAsync(&serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H");
+        HIPCHK(hipStreamSynchronize(st), "sync");
+        if (serr) {
+            set_error("triangular solve: a block wait exceeded its poll limit");
+            return GBEM_EDEVICE;
+        }
+        return GBEM_OK;
+    };
+    if ((s = solve(X)) != GBEM_OK) return s;
+    double bn[kMaxRhs], rn[kMaxRhs];
+    HIPCHK(launch_col_norms(Bb.as<double>(), nu, nu, M, nrm.as<double>(), st), "norms");
+    HIPCHK(hipMemcpyAsync(bn, nrm.p, sizeof(double) * M, hipMemcpyDeviceToHost, st), "D2H");
+    int iters = 0;
+    double resid = 0.0;
+    for (;; ++iters) {
+        HIPCHK(hipMemcpyAsync(Rr.p, Bb.p, (size_t)nu * M * 8, hipMemcpyDeviceToDevice, st), "copy B");
+        HIPCHK(launch_dgemm(false, nu, M, nu, -1.0, Mb.as<double>(), nu, X.as<double>(), npad, 1.0, Rr.as<double>(), nu,
+                            st), "residual");
+        HIPCHK(launch_col_norms(Rr.as<double>(), nu, nu, M, nrm.as<double>(), st), "norms");
+        HIPCHK(hipMemcpyAsync(rn, nrm.p, sizeof(double) * M, hipMemcpyDeviceToHost, st), "D2H");
+        HIPCHK(hipStreamSynchronize(st), "sync");
+        double worst = 0.0;
+        for (int k = 0; k < M; ++k) worst = std::max(worst, bn[k] > 0.0 ? sqrt(rn[k] / bn[k]) : sqrt(rn[k]));
+        if (!(worst < INFINITY)) {
+            set_error("gbem_extract_dielectric: the solution is not finite");
+            return GBEM_ENOCONV;
+        }
+        resid = worst;
+        if (worst <= 1e-13 || iters >= 6) break;
+        HIPCHK(launch_dgemm(true, nu, M, nu, 1.0, Mb.as<double>(), nu, Rr.as<double>(), nu, 0.0, D.as<double>(), npad,
+                            st), "M^T R");
+        if ((s = solve(D)) != GBEM_OK) return s;
+        HIPCHK(launch_axpy_cols(X.as<double>(), npad, D.as<double>(), npad, nu, M, st), "update");
+    }
+    HIPCHK(Cd.ensure(sizeof(double) * M * M), "alloc C");
+    HIPCHK(launch_dl_charges(ws.pan.as<Panel>(), n, d_kind, d_cond, d_rp, d_rm, epsb.as<double>(), d_qs, X.as<double>(),
+                             npad, M, kEps0 * mesh->length_unit_m, Cd.as<double>(), st), "charges");
+    HIPCHK(hipMemcpyAsync(C_out, Cd.p, sizeof(double) * M * M, hipMemcpyDeviceToHost, st), "D2H");
+    HIPCHK(hipStreamSynchronize(st), "sync");
+    const auto t_end = std::chrono::steady_clock::now();
+    if (rep) {
+        gbem_report r{};
+        auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+        r.t_assemble_ms = ms(t_start, t_asm);
+        r.t_factor_ms = ms(t_asm, t_fac);
+        r.t_solve_ms = ms(t_fac, t_end);
+        r.t_total_ms = ms(t_start, t_end);
+        r.residual = resid;
+        r.refine_iters = iters;
+        r.factor_used = GBEM_F64;
+        r.n_near = nnz;
+        r.n_panels = n;
+        r.asym = asym_of(C_out, M);
+        *rep = r;
+    }
     return GBEM_OK;
 }

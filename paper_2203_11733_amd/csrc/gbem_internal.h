@@ -234,4 +234,26 @@ hipError_t launch_scale_rows(double *X, int64_t ldx, const double *s, int npad, 
 hipError_t launch_axpy_cols(double *X, int64_t ldx, const double *D, int64_t ldd, int npad, int m,
                             hipStream_t st);
 
+// dielectric.hip: multi-dielectric case
+// Q[i + k ldq] = double-layer integral of target panel i and source panel k
+// (normal of k along + its axis), every pair: far rule, then the near pairs
+// (row, col: the near list, col <= row) in both orders
+hipError_t launch_double_layer(const Panel *pan, int n, const int32_t *row, const int32_t *col, int64_t nnz,
+                               double *Q, int64_t ldq, hipStream_t s);
+// system matrix M (nu x nu, zeroed by the caller) and right-hand sides B (nu
+// x m_main) of the region-by-region equations; A: single-layer entries
+// (normalised by the two areas), Q: double-layer integrals
+hipError_t launch_dl_system(const Panel *pan, int n, const double *A, int64_t lda, const double *Q, int64_t ldq,
+                            const int32_t *kind, const int32_t *cond, const int32_t *rp, const int32_t *rm,
+                            const double *eps, const int32_t *eq_reg, const int32_t *eq_pan, const int32_t *u_slot,
+                            const int32_t *q_slot, int nu, int m_main, double *M, int64_t ldm, double *B, int64_t ldb,
+                            hipStream_t s);
+// C[k m_main + m] = scale * sum over the panels of conductor k of eps q |I|
+hipError_t launch_dl_charges(const Panel *pan, int n, const int32_t *kind, const int32_t *cond, const int32_t *rp,
+                             const int32_t *rm, const double *eps, const int32_t *q_slot, const double *X,
+                             int64_t ldx, int m_main, double scale, double *C, hipStream_t s);
+// C (m x nc) = alpha op(A) B + beta C in FP64, op(A) = A^T when ta
+hipError_t launch_dgemm(bool ta, int m, int nc, int kk, double alpha, const double *A, int64_t lda, const double *B,
+                        int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t s);
+
 }  // namespace gbem

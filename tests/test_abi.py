@@ -177,3 +177,36 @@ def test_committed_tuning_cache_parses():
     binding.load_tuning(path)
     assert binding.tuning_source() == path
     binding.load_tuning(None)
+
+
+def test_dielectric_mesh_checks_before_context():
+    """gbem_extract_dielectric refuses inconsistent meshes before touching the
+    device: a conductor panel with regions on both sides, a net without
+    panels; a consistent mesh reaches the context check."""
+    lib = binding.load()
+    m = gi.two_slab_capacitor(n_xy=2, n_z=1)
+
+    def call(kind=None, cond=None, rp=None, rm=None, n_cond=2):
+        arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in
+                (m.kind if kind is None else kind, m.conductor if cond is None else cond,
+                 m.region_plus if rp is None else rp, m.region_minus if rm is None else rm)]
+        lo, hi = np.ascontiguousarray(m.lo), np.ascontiguousarray(m.hi)
+        eps = np.ascontiguousarray(m.eps_r, dtype=np.float64)
+        d = binding.DMesh(m.n_panels, n_cond, len(m.eps_r), lo.ctypes.data, hi.ctypes.data, arrs[0].ctypes.data,
+                          arrs[1].ctypes.data, arrs[2].ctypes.data, arrs[3].ctypes.data, eps.ctypes.data, 1e-6)
+        C = np.zeros((n_cond, n_cond))
+        st = lib.gbem_extract_dielectric(None, ctypes.byref(d), None, C.ctypes.data, None)
+        return st, lib.gbem_last_error()
+
+    rm = m.region_minus.copy()
+    rm[0] = 1 - m.region_plus[0] if m.region_plus[0] >= 0 else 0
+    st, msg = call(rm=rm)
+    assert st == binding.EINVAL and b"panel 0" in msg
+    st, msg = call(n_cond=3)
+    assert st == binding.EINVAL and b"conductor 2 has no panels" in msg
+    kind = m.kind.copy()
+    kind[0] = 7
+    st, msg = call(kind=kind)
+    assert st == binding.EINVAL and b"panel 0" in msg
+    st, msg = call()
+    assert st == binding.EINVAL and b"context" in msg

@@ -16,6 +16,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
+import gbem_inputs as gi  # noqa: E402
 from oracle import dielectric as od  # noqa: E402
 from oracle import oracle as oo  # noqa: E402
 
@@ -124,45 +125,6 @@ def test_coplanar_pairs_vanish():
     assert od.double_layer_pair([0, 0, 0], [1, 1, 0], [3, 4, 0], [5, 5, 0]) == 0.0
 
 
-def _face_grid(nrm, plane, r1, r2, n1, n2):
-    t1, t2 = [k for k in range(3) if k != nrm]
-    out = []
-    for i in range(n1):
-        for j in range(n2):
-            lo = [0.0] * 3
-            hi = [0.0] * 3
-            lo[nrm] = hi[nrm] = plane
-            lo[t1] = r1[0] + (r1[1] - r1[0]) * i / n1
-            hi[t1] = r1[0] + (r1[1] - r1[0]) * (i + 1) / n1
-            lo[t2] = r2[0] + (r2[1] - r2[0]) * j / n2
-            hi[t2] = r2[0] + (r2[1] - r2[0]) * (j + 1) / n2
-            out.append((lo, hi))
-    return out
-
-
-def two_slab_capacitor(L, d1, d2, n_xy, n_z):
-    """Plates z = 0 (net 1) and z = d1 + d2 (net 0) of side L, dielectric 0 in
-    0 < z < d1 and 1 above, an interface at z = d1, Neumann side walls (no
-    fringing field: the exact capacitance is eps0 L^2 / (d1/eps_0 + d2/eps_1))."""
-    H = d1 + d2
-    P = []
-    for lo, hi in _face_grid(2, 0.0, (0, L), (0, L), n_xy, n_xy):
-        P.append((lo, hi, od.CONDUCTOR, 1, 0, -1))
-    for lo, hi in _face_grid(2, H, (0, L), (0, L), n_xy, n_xy):
-        P.append((lo, hi, od.CONDUCTOR, 0, -1, 1))
-    for lo, hi in _face_grid(2, d1, (0, L), (0, L), n_xy, n_xy):
-        P.append((lo, hi, od.INTERFACE, -1, 1, 0))
-    for z0, z1, reg in ((0.0, d1, 0), (d1, H, 1)):
-        for nrm in (0, 1):
-            # in-plane axes of a wall of normal nrm: the other horizontal axis, then z
-            for plane, plus in ((0.0, True), (L, False)):
-                for lo, hi in _face_grid(nrm, plane, (0, L), (z0, z1), n_xy, n_z):
-                    P.append((lo, hi, od.NEUMANN, -1, reg if plus else -1, -1 if plus else reg))
-    cols = list(zip(*P))
-    return np.array(cols[0], float), np.array(cols[1], float), list(cols[2]), list(cols[3]), list(cols[4]), \
-        list(cols[5])
-
-
 def test_two_slab_capacitor_converges_to_series_formula():
     """Two dielectric slabs between plates with Neumann side walls: the field
     is one-dimensional, C = eps0 L^2 / (d1/eps1 + d2/eps2).  The piecewise
@@ -173,7 +135,7 @@ def test_two_slab_capacitor_converges_to_series_formula():
     exact = oo.EPS0 * 1e-6 * L * L / (d1 / e[0] + d2 / e[1])
     errs = []
     for nxy, nz in ((2, 1), (4, 2), (6, 3)):
-        C = od.extract(*two_slab_capacitor(L, d1, d2, nxy, nz), e, 2, 1e-6)
+        C = od.extract(*gi.two_slab_capacitor(L, d1, d2, nxy, nz, e).args())
         errs.append(C[0, 0] / exact - 1.0)
         say(f"  {nxy} x {nz}: C00 / exact - 1 = {errs[-1]:.4f}, C01 / C10 = {C[0, 1] / C[1, 0]:.6f}")
         assert C[0, 0] > 0 and C[1, 0] < 0
@@ -187,13 +149,11 @@ def test_two_slab_mirror_and_scaling():
     """The mirrored capacitor (slabs swapped, plates swapped) gives the same C
     with the nets exchanged, and scaling every permittivity scales C."""
     L, d1, d2 = 1.0, 0.3, 0.7
-    m = two_slab_capacitor(L, d1, d2, 3, 2)
-    C = od.extract(*m, [4.0, 1.0], 2, 1e-6)
-    mm = two_slab_capacitor(L, d2, d1, 3, 2)
+    C = od.extract(*gi.two_slab_capacitor(L, d1, d2, 3, 2, [4.0, 1.0]).args())
     # mirror z -> H - z: swap the roles (net 0 <-> net 1, region 0 <-> region 1)
-    Cm = od.extract(*mm, [1.0, 4.0], 2, 1e-6)
+    Cm = od.extract(*gi.two_slab_capacitor(L, d2, d1, 3, 2, [1.0, 4.0]).args())
     assert Cm[1, 1] == pytest.approx(C[0, 0], rel=1e-10)
     assert Cm[0, 0] == pytest.approx(C[1, 1], rel=1e-10)
     assert Cm[0, 1] == pytest.approx(C[1, 0], rel=1e-10)
-    C2 = od.extract(*m, [8.0, 2.0], 2, 1e-6)
+    C2 = od.extract(*gi.two_slab_capacitor(L, d1, d2, 3, 2, [8.0, 2.0]).args())
     assert np.allclose(C2, 2.0 * C, rtol=1e-12, atol=0)
