@@ -1735,9 +1735,20 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     HIPCHK(hipMemcpyAsync(ws.lo.p, mesh->lo, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
     HIPCHK(hipMemcpyAsync(ws.hi.p, mesh->hi, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
     HIPCHK(hipMemcpyAsync(ws.cond.p, cond.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st), "H2D");
-    // per-panel and per-equation tables in one device block of int32
-    LocalBuf tab, epsb, Q, Mb, Bb, N, X, Rr, D, Cd, nrm;
-    const size_t ntab = (size_t)6 * n + 2 * (size_t)nu;
+    // per-panel and per-equation tables and the conductor panels of each net
+    // (CSR over nets) in one device block of int32
+    LocalBuf tab, epsb, Q, Mb, Mt, Bb, Bn, Z, N, X, Rr, D, Cd, nrm, part;
+    std::vector<int32_t> cp_ptr(M + 1, 0), cp_idx;
+    for (int i = 0; i < n; ++i)
+        if (cond[i] >= 0) ++cp_ptr[cond[i] + 1];
+    for (int k = 0; k < M; ++k) cp_ptr[k + 1] += cp_ptr[k];
+    cp_idx.resize(cp_ptr[M]);
+    {
+        std::vector<int32_t> fill(cp_ptr.begin(), cp_ptr.end() - 1);
+        for (int i = 0; i < n; ++i)
+            if (cond[i] >= 0) cp_idx[fill[cond[i]]++] = i;
+    }
+    const size_t ntab = (size_t)6 * n + 2 * (size_t)nu + (M + 1) + cp_idx.size();
     HIPCHK(tab.ensure(sizeof(int32_t) * ntab), "alloc");
     std::vector<int32_t> htab(ntab);
     for (int i = 0; i < n; ++i) {
@@ -1752,39 +1763,44 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
         htab[6 * (size_t)n + r] = eq_reg[r];
         htab[6 * (size_t)n + nu + r] = eq_pan[r];
     }
+    std::copy(cp_ptr.begin(), cp_ptr.end(), htab.begin() + 6 * (size_t)n + 2 * nu);
+    std::copy(cp_idx.begin(), cp_idx.end(), htab.begin() + 6 * (size_t)n + 2 * nu + M + 1);
     HIPCHK(hipMemcpyAsync(tab.p, htab.data(), sizeof(int32_t) * ntab, hipMemcpyHostToDevice, st), "H2D");
     HIPCHK(epsb.ensure(sizeof(double) * R), "alloc");
     HIPCHK(hipMemcpyAsync(epsb.p, mesh->eps_r, sizeof(double) * R, hipMemcpyHostToDevice, st), "H2D");
-    const int32_t *d_kind = tab.as<int32_t>(), *d_cond = d_kind + n, *d_rp = d_kind + 2 * n, *d_rm = d_kind + 3 * n,
+    const int32_t *d_kind = tab.as<int32_t>(), *d_rp = d_kind + 2 * n, *d_rm = d_kind + 3 * n,
                   *d_us = d_kind + 4 * n, *d_qs = d_kind + 5 * n, *d_er = d_kind + 6 * (size_t)n,
-                  *d_ep = d_er + nu;
+                  *d_ep = d_er + nu, *d_cpp = d_ep + nu, *d_cpi = d_cpp + M + 1;
     int64_t nnz = 0;
     gbem_status s = dl_assemble(ctx, n, M, o.near_eta, o.far_order, true, Q, &nnz, st);
     if (s != GBEM_OK) return s;
     const int64_t npadA = round_up(n, kPad), npad = round_up(nu, kPad);
     const auto t_asm = std::chrono::steady_clock::now();
-    // the section 4.1 system M X = B (one column per main net)
-    HIPCHK(Mb.ensure((size_t)nu * nu * 8), "alloc M");
-    HIPCHK(Bb.ensure((size_t)nu * M * 8), "alloc B");
-    HIPCHK(hipMemsetAsync(Mb.p, 0, (size_t)nu * nu * 8, st), "memset");
-    HIPCHK(launch_dl_system(ws.pan.as<Panel>(), n, ws.A.as<double>(), npadA, Q.as<double>(), n, d_kind, d_cond, d_rp,
-                            d_rm, epsb.as<double>(), d_er, d_ep, d_us, d_qs, nu, M, Mb.as<double>(), nu,
-                            Bb.as<double>(), nu, st), "system");
-    // normal equations M^T M X = M^T B on the FP64 Cholesky (the system is not
-    // symmetric), then FP64 refinement with the residual of M itself
-    HIPCHK(N.ensure((size_t)npad * npad * 8), "alloc N");
-    HIPCHK(X.ensure((size_t)npad * M * 8), "alloc X");
-    HIPCHK(D.ensure((size_t)npad * M * 8), "alloc D");
-    HIPCHK(Rr.ensure((size_t)nu * M * 8), "alloc R");
+    // the section 4.1 system M X = B (one column per main net), M and its
+    // transpose zero-padded to order npad, B and -B to npad rows
+    const size_t mat = (size_t)npad * npad * 8, vec = (size_t)npad * M * 8;
+    HIPCHK(Mb.ensure(mat), "alloc M");
+    HIPCHK(Mt.ensure(mat), "alloc M^T");
+    HIPCHK(N.ensure(mat), "alloc N");
+    for (DevBuf *v : {&Bb, &Bn, &Z, &X, &Rr, &D}) HIPCHK(v->ensure(vec), "alloc");
     HIPCHK(nrm.ensure(sizeof(double) * 2 * kMaxRhs), "alloc");
-    HIPCHK(hipMemsetAsync(N.p, 0, (size_t)npad * npad * 8, st), "memset");
-    HIPCHK(launch_dgemm(true, nu, nu, nu, 1.0, Mb.as<double>(), nu, Mb.as<double>(), nu, 0.0, N.as<double>(), npad, st),
-           "M^T M");
+    HIPCHK(part.ensure((size_t)residual_splits((int)npad) * M * npad * 8), "alloc residual partials");
+    for (DevBuf *v : {&Mb, &Mt, &N}) HIPCHK(hipMemsetAsync(v->p, 0, mat, st), "memset");
+    for (DevBuf *v : {&Bb, &Bn, &Z, &X, &Rr, &D}) HIPCHK(hipMemsetAsync(v->p, 0, vec, st), "memset");
+    HIPCHK(launch_dl_system(ws.pan.as<Panel>(), n, ws.A.as<double>(), npadA, Q.as<double>(), n, d_kind, d_rp, d_rm,
+                            epsb.as<double>(), d_er, d_ep, d_us, d_qs, d_cpp, d_cpi, nu, M, Mb.as<double>(),
+                            Mt.as<double>(), npad, Bb.as<double>(), Bn.as<double>(), npad, st), "system");
+    // normal equations (M^T M) X = M^T B on the FP64 Cholesky (the system is
+    // not symmetric): M^T M on the factorisation's MFMA tiles (M^T is the
+    // tile operand, rows = unknowns); the tall-skinny products through the
+    // residual kernel, which forms B - A^T X:
+    //   M^T B   = 0 - M^T (-B)      (A = M)
+    //   B - M X                     (A = M^T)
+    //   -M^T R  = 0 - M^T R         (A = M), subtracted from X
+    HIPCHK(launch_gram_f64(npad, npad, Mt.as<double>(), npad, N.as<double>(), npad, st), "M^T M");
     HIPCHK(launch_identity_pad(N.p, npad, nu, (int)npad, true, st), "pad");
-    HIPCHK(hipMemsetAsync(X.p, 0, (size_t)npad * M * 8, st), "memset");
-    HIPCHK(hipMemsetAsync(D.p, 0, (size_t)npad * M * 8, st), "memset");
-    HIPCHK(launch_dgemm(true, nu, M, nu, 1.0, Mb.as<double>(), nu, Bb.as<double>(), nu, 0.0, X.as<double>(), npad, st),
-           "M^T B");
+    HIPCHK(launch_residual(Mb.as<double>(), npad, (int)npad, Bn.as<double>(), npad, Z.as<double>(), npad, M,
+                           X.as<double>(), npad, part.as<double>(), st), "M^T B");
     HIPCHK(ws.Winv.ensure(chol_winv_bytes(GBEM_F64, npad)), "alloc W");
     HIPCHK(ws.Pw.ensure(chol_panel_bytes(GBEM_F64, npad)), "alloc panel");
     HIPCHK(ws.P16.ensure(std::max<size_t>(chol_panel16_bytes(GBEM_F64, npad), 64)), "alloc panel16");
@@ -1820,15 +1836,14 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     };
     if ((s = solve(X)) != GBEM_OK) return s;
     double bn[kMaxRhs], rn[kMaxRhs];
-    HIPCHK(launch_col_norms(Bb.as<double>(), nu, nu, M, nrm.as<double>(), st), "norms");
+    HIPCHK(launch_col_norms(Bb.as<double>(), npad, (int)npad, M, nrm.as<double>(), st), "norms");
     HIPCHK(hipMemcpyAsync(bn, nrm.p, sizeof(double) * M, hipMemcpyDeviceToHost, st), "D2H");
     int iters = 0;
     double resid = 0.0;
     for (;; ++iters) {
-        HIPCHK(hipMemcpyAsync(Rr.p, Bb.p, (size_t)nu * M * 8, hipMemcpyDeviceToDevice, st), "copy B");
-        HIPCHK(launch_dgemm(false, nu, M, nu, -1.0, Mb.as<double>(), nu, X.as<double>(), npad, 1.0, Rr.as<double>(), nu,
-                            st), "residual");
-        HIPCHK(launch_col_norms(Rr.as<double>(), nu, nu, M, nrm.as<double>(), st), "norms");
+        HIPCHK(launch_residual(Mt.as<double>(), npad, (int)npad, X.as<double>(), npad, Bb.as<double>(), npad, M,
+                               Rr.as<double>(), npad, part.as<double>(), st), "residual");
+        HIPCHK(launch_col_norms(Rr.as<double>(), npad, (int)npad, M, nrm.as<double>(), st), "norms");
         HIPCHK(hipMemcpyAsync(rn, nrm.p, sizeof(double) * M, hipMemcpyDeviceToHost, st), "D2H");
         HIPCHK(hipStreamSynchronize(st), "sync");
         double worst = 0.0;
@@ -1839,13 +1854,13 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
         }
         resid = worst;
         if (worst <= 1e-13 || iters >= 6) break;
-        HIPCHK(launch_dgemm(true, nu, M, nu, 1.0, Mb.as<double>(), nu, Rr.as<double>(), nu, 0.0, D.as<double>(), npad,
-                            st), "M^T R");
+        HIPCHK(launch_residual(Mb.as<double>(), npad, (int)npad, Rr.as<double>(), npad, Z.as<double>(), npad, M,
+                               D.as<double>(), npad, part.as<double>(), st), "M^T R");
         if ((s = solve(D)) != GBEM_OK) return s;
-        HIPCHK(launch_axpy_cols(X.as<double>(), npad, D.as<double>(), npad, nu, M, st), "update");
+        HIPCHK(launch_dl_sub(X.as<double>(), npad, D.as<double>(), npad, (int)npad, M, st), "update");
     }
     HIPCHK(Cd.ensure(sizeof(double) * M * M), "alloc C");
-    HIPCHK(launch_dl_charges(ws.pan.as<Panel>(), n, d_kind, d_cond, d_rp, d_rm, epsb.as<double>(), d_qs, X.as<double>(),
+    HIPCHK(launch_dl_charges(ws.pan.as<Panel>(), d_rp, d_rm, epsb.as<double>(), d_qs, d_cpp, d_cpi, X.as<double>(),
                              npad, M, kEps0 * mesh->length_unit_m, Cd.as<double>(), st), "charges");
     HIPCHK(hipMemcpyAsync(C_out, Cd.p, sizeof(double) * M * M, hipMemcpyDeviceToHost, st), "D2H");
     HIPCHK(hipStreamSynchronize(st), "sync");

@@ -1290,4 +1290,12 @@ hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t ld
     return diag_inverses_t<float>(npad, (const float *)L, lda, (float *)Winv, s);
 }
 
+hipError_t launch_gram_f64(int64_t nrows, int64_t K, const double *P, int64_t ldp, double *C, int64_t ldc,
+                           hipStream_t s)
+{
+    if (nrows % kBM || K % kBK || nrows <= 0 || K <= 0) return hipErrorInvalidValue;
+    const int tm = (int)(nrows / kBM);
+    return launch_gemm<double, kTri, true, false>(tm, tm * (tm + 1) / 2, (int)K, P, ldp, P, ldp, C, ldc, s);
+}
+
 }  // namespace gbem

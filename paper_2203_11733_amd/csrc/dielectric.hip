@@ -7,7 +7,9 @@
 //   far pairs (the near list's complement): the inner integral over the flat
 //   rectangle I_k in closed form (its solid angle at x over 4 pi: sum over the
 //   corners of s_x s_y atan(u v / (h r)), h the height of x over the plane of
-//   I_k), the outer one 6 x 6 Gauss-Legendre over I_i; one thread per pair.
+//   I_k, evaluated as one atan2), the outer one n x n Gauss-Legendre over
+//   I_i with n = 6 at the near threshold down to 2 at 40 diameters (within
+//   about 1e-13 |I_i| of the exact value); one thread per pair.
 //   near pairs: all four integrations in closed form, one thread per ordered
 //   pair.  Section 4.2 integrates the kernel analytically along all but one
 //   coordinate (corner differences D of antiderivatives) and leaves a single
@@ -81,19 +83,27 @@ __device__ __forceinline__ Source source_of(const Panel &p)
     return s;
 }
 
-// Int over I_k of q*(x, y) dG(y) at x (normal of I_k along +): solid angle / 4 pi
-__device__ __forceinline__ double dl_potential(const Source &s, const P3 &x)
+// Int over I_k of q*(x, y) dG(y) at x (normal of I_k along +): the solid angle
+// Omega over 4 pi, Omega = sum over the corners of s_x s_y atan(u v / (h r)),
+// for points x from which the rectangle subtends |Omega| < pi (every far pair:
+// the solid angle there is below 1/8).  The four atan terms are the arguments
+// of (h r_ab +- i u_a v_b), whose real parts carry the common sign of h, so
+// their sum is the argument of the product of the four factors (the positive
+// scale h^4 r_11 r_12 r_21 r_22 drops out): one atan2 and no division.
+__device__ __forceinline__ double dl_potential_far(const Source &s, const P3 &x)
 {
     const double h = comp(x, s.nrm) - s.z;
     if (h == 0.0) return 0.0;
     const double px = comp(x, s.t1), py = comp(x, s.t2);
     const double u2 = s.x2 - px, u1 = s.x1 - px, v2 = s.y2 - py, v1 = s.y1 - py;
     const double h2 = h * h;
-    double a = atan(u2 * v2 / (h * sqrt(u2 * u2 + v2 * v2 + h2)));
-    a += atan(u1 * v1 / (h * sqrt(u1 * u1 + v1 * v1 + h2)));
-    a -= atan(u2 * v1 / (h * sqrt(u2 * u2 + v1 * v1 + h2)));
-    a -= atan(u1 * v2 / (h * sqrt(u1 * u1 + v2 * v2 + h2)));
-    return a * kInv4Pi;
+    const double a = h * sqrt(u2 * u2 + v2 * v2 + h2), b = u2 * v2;    // + atan(u2 v2 / (h r))
+    const double c = h * sqrt(u1 * u1 + v1 * v1 + h2), d = u1 * v1;    // + atan(u1 v1 / (h r))
+    const double e = h * sqrt(u2 * u2 + v1 * v1 + h2), f = -u2 * v1;   // - atan(u2 v1 / (h r))
+    const double g = h * sqrt(u1 * u1 + v2 * v2 + h2), k = -u1 * v2;   // - atan(u1 v2 / (h r))
+    const double re1 = a * c - b * d, im1 = a * d + b * c;
+    const double re2 = e * g - f * k, im2 = e * k + f * g;
+    return atan2(re1 * im2 + im1 * re2, re1 * re2 - im1 * im2) * kInv4Pi;
 }
 
 __device__ __forceinline__ bool coplanar(const Panel &a, const Panel &b)
@@ -102,10 +112,39 @@ __device__ __forceinline__ bool coplanar(const Panel &a, const Panel &b)
 }
 }  // namespace
 
-// Q[i + k ldq] for every pair with the 6 x 6 rule (near pairs are overwritten
-// by dl_near_kernel).  Block: 256 targets i for one source k.
-__global__ __launch_bounds__(256) void dl_far_kernel(const Panel *__restrict__ pan, int n, GaussRule g,
-                                                     double *__restrict__ Q, int64_t ldq)
+// Gauss-Legendre rules of 2..6 points per direction for the far pairs (nodes
+// on [-1, 1] and halved weights, rule n at offset (n - 2)(n + 1) / 2), written
+// by launch_double_layer from the library's own rule generator.
+__constant__ double kFarX[20], kFarW[20];
+
+__device__ __forceinline__ double half_extent(const Panel &p, int k)
+{
+    int t1, t2;
+    inplane(p.nrm, t1, t2);
+    return k == t1 ? p.h1 : (k == t2 ? p.h2 : 0.0);
+}
+
+// Points per direction of the far rule on the target, from the gap between
+// the two panels' boxes over the larger diameter (rho): the rule's error,
+// measured against the closed form of both integrals at the worst
+// orientations, stays below about 1e-13 |I_i| with 6 points from rho = 2 (the
+// near threshold), 5 from 3, 4 from 5, 3 from 12 and 2 from 40.
+__device__ __forceinline__ int far_points(const Panel &T, const Panel &S)
+{
+    double g2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double g = fmax(0.0, fabs(pc(T, k) - pc(S, k)) - (half_extent(T, k) + half_extent(S, k)));
+        g2 = fma(g, g, g2);
+    }
+    const double d2 = fmax(T.diam2, S.diam2);
+    return g2 >= 1600.0 * d2 ? 2 : g2 >= 144.0 * d2 ? 3 : g2 >= 25.0 * d2 ? 4 : g2 >= 9.0 * d2 ? 5 : 6;
+}
+
+// Q[i + k ldq] for every pair with the far rule (near pairs are overwritten
+// by dl_near_kernel).  Block: 256 targets i for one source k at a time.
+__global__ __launch_bounds__(256) void dl_far_kernel(const Panel *__restrict__ pan, int n, double *__restrict__ Q,
+                                                     int64_t ldq)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -118,11 +157,16 @@ __global__ __launch_bounds__(256) void dl_far_kernel(const Panel *__restrict__ p
         double q = 0.0;
         if (!coplanar(pi, pk)) {
             const Source s = source_of(pk);
-            for (int a = 0; a < 6; ++a)
-                for (int b = 0; b < 6; ++b) {
-                    const P3 x = place(t1, t2, c1 + pi.h1 * g.x[a], c2 + pi.h2 * g.x[b], cn);
-                    q = fma(g.ww[a * 6 + b], dl_potential(s, x), q);
+            const int np = far_points(pi, pk), off = (np - 2) * (np + 1) / 2;
+            for (int a = 0; a < np; ++a) {
+                const double xa = c1 + pi.h1 * kFarX[off + a], wa = kFarW[off + a];
+                double qa = 0.0;
+                for (int b = 0; b < np; ++b) {
+                    const P3 x = place(t1, t2, xa, c2 + pi.h2 * kFarX[off + b], cn);
+                    qa = fma(kFarW[off + b], dl_potential_far(s, x), qa);
                 }
+                q = fma(wa, qa, q);
+            }
             q *= pi.area;
         }
         Q[i + (int64_t)k * ldq] = q;
@@ -216,10 +260,13 @@ hipError_t launch_double_layer(const Panel *pan, int n, const int32_t *row, cons
                                double *Q, int64_t ldq, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    GaussRule g6;
-    gauss_legendre_rule(6, &g6);
-    hipLaunchKernelGGL(dl_far_kernel, dim3((n + 255) / 256, std::min(n, 65535)), dim3(256), 0, s, pan, n, g6, Q, ldq);
-    hipError_t e = hipGetLastError();
+    double x[20], w[20];
+    for (int p = 2, off = 0; p <= 6; off += p, ++p) gauss_legendre(p, x + off, w + off);
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(kFarX), x, sizeof x, 0, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyToSymbolAsync(HIP_SYMBOL(kFarW), w, sizeof w, 0, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dl_far_kernel, dim3((n + 255) / 256, std::min(n, 65535)), dim3(256), 0, s, pan, n, Q, ldq);
+    e = hipGetLastError();
     if (e != hipSuccess || nnz == 0) return e;
     hipLaunchKernelGGL(dl_near_kernel, dim3((unsigned)((2 * nnz + 255) / 256)), dim3(256), 0, s, pan, row, col, nnz,
                        Q, ldq);
@@ -234,8 +281,9 @@ hipError_t launch_double_layer(const Panel *pan, int n, const int32_t *row, cons
 //   q unknown at k (conductor, Dirichlet, interface): M[r, q_slot[k]] = -f G_ik,
 //     f = 1, or for an interface panel seen from its + side region
 //     -eps_minus / eps_plus (the unknown is the - side region's q)
-// Every (row, slot) is written by one thread.  G = A |I_i| |I_k| (A: the
-// single-layer entries with their 1 / (|I_i| |I_k|) normalisation).
+// Every (row, slot) is written by one thread, into M and its transpose Mt.
+// G = A |I_i| |I_k| (A: the single-layer entries with their 1 / (|I_i| |I_k|)
+// normalisation).
 __global__ __launch_bounds__(256) void dl_system_kernel(const Panel *__restrict__ pan, int n,
                                                         const double *__restrict__ A, int64_t lda,
                                                         const double *__restrict__ Q, int64_t ldq,
@@ -245,7 +293,7 @@ __global__ __launch_bounds__(256) void dl_system_kernel(const Panel *__restrict_
                                                         const int32_t *__restrict__ eq_pan,
                                                         const int32_t *__restrict__ u_slot,
                                                         const int32_t *__restrict__ q_slot, int nu,
-                                                        double *__restrict__ M, int64_t ldm)
+                                                        double *__restrict__ M, double *__restrict__ Mt, int64_t ldm)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
@@ -256,136 +304,108 @@ __global__ __launch_bounds__(256) void dl_system_kernel(const Panel *__restrict_
         if (u_slot[k] >= 0) {
             const double coef = (k == i ? 0.5 * pan[i].area : 0.0) + sgn * Q[i + (int64_t)k * ldq];
             M[r + (int64_t)u_slot[k] * ldm] = coef;
+            Mt[u_slot[k] + (int64_t)r * ldm] = coef;
         }
         if (q_slot[k] >= 0) {
             double f = 1.0;
             if (kind[k] == 3 && rp[k] == a) f = -eps[rm[k]] / eps[rp[k]];
-            M[r + (int64_t)q_slot[k] * ldm] = -f * A[i + (int64_t)k * lda] * pan[i].area * pan[k].area;
+            const double g = -f * A[i + (int64_t)k * lda] * pan[i].area * pan[k].area;
+            M[r + (int64_t)q_slot[k] * ldm] = g;
+            Mt[q_slot[k] + (int64_t)r * ldm] = g;
         }
     }
 }
 
-// Right-hand side of main net m (column m of B): the known potential 1 on the
-// panels of conductor m moved to the right, b_r = -sum over those panels k of
-// the region of row r of (1/2 |I_i| [k = i] + s Q_ik); fixed panel order.
-__global__ __launch_bounds__(256) void dl_rhs_kernel(const Panel *__restrict__ pan, int n,
-                                                     const double *__restrict__ Q, int64_t ldq,
-                                                     const int32_t *__restrict__ kind,
-                                                     const int32_t *__restrict__ cond, const int32_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ rm, const int32_t *__restrict__ eq_reg,
-                                                     const int32_t *__restrict__ eq_pan, int nu, int m_main,
-                                                     double *__restrict__ B, int64_t ldb)
+// Right-hand side of main net m (column m of B, and -B beside it): the known
+// potential 1 on the panels of conductor m moved to the right,
+// b_r = -sum over those panels k of the region of row r of
+// (1/2 |I_i| [k = i] + s Q_ik); the net's panels in order.
+__global__ __launch_bounds__(256) void dl_rhs_kernel(const Panel *__restrict__ pan, const double *__restrict__ Q,
+                                                     int64_t ldq, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ rm,
+                                                     const int32_t *__restrict__ eq_reg,
+                                                     const int32_t *__restrict__ eq_pan,
+                                                     const int32_t *__restrict__ cp_ptr,
+                                                     const int32_t *__restrict__ cp_idx, int nu,
+                                                     double *__restrict__ B, double *__restrict__ Bneg, int64_t ldb)
 {
     const int r = blockIdx.x * 256 + threadIdx.x, m = blockIdx.y;
-    if (r >= nu || m >= m_main) return;
+    if (r >= nu) return;
     const int a = eq_reg[r], i = eq_pan[r];
     double b = 0.0;
-    for (int k = 0; k < n; ++k) {
-        if (kind[k] != 0 || cond[k] != m || (rp[k] != a && rm[k] != a)) continue;
+    for (int t = cp_ptr[m]; t < cp_ptr[m + 1]; ++t) {
+        const int k = cp_idx[t];
+        if (rp[k] != a && rm[k] != a) continue;
         const double sgn = rp[k] == a ? -1.0 : 1.0;
         b -= (k == i ? 0.5 * pan[i].area : 0.0) + sgn * Q[i + (int64_t)k * ldq];
     }
     B[r + (int64_t)m * ldb] = b;
+    Bneg[r + (int64_t)m * ldb] = -b;
 }
 
-// C[k * m_main + m] = eps0 l * sum over conductor-k panels of eps q |I|, the
-// region's q (along its outward normal, into the conductor) from column m of
-// X; fixed panel order, FP64.
-__global__ void dl_charge_kernel(const Panel *__restrict__ pan, int n, const int32_t *__restrict__ kind,
-                                 const int32_t *__restrict__ cond, const int32_t *__restrict__ rp,
-                                 const int32_t *__restrict__ rm, const double *__restrict__ eps,
-                                 const int32_t *__restrict__ q_slot, const double *__restrict__ X, int64_t ldx,
-                                 int m_main, double scale, double *__restrict__ C)
+// C[k * m_main + m] = scale * sum over the panels of conductor k of eps q |I|,
+// the region's q (along its outward normal, into the conductor) from column m
+// of X.  One workgroup per (k, m): strided partial sums, then a fixed-order
+// tree, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void dl_charge_kernel(const Panel *__restrict__ pan, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ rm,
+                                                        const double *__restrict__ eps,
+                                                        const int32_t *__restrict__ q_slot,
+                                                        const int32_t *__restrict__ cp_ptr,
+                                                        const int32_t *__restrict__ cp_idx,
+                                                        const double *__restrict__ X, int64_t ldx, int m_main,
+                                                        double scale, double *__restrict__ C)
 {
-    const int k = blockIdx.x, m = threadIdx.x;
-    if (m >= m_main) return;
+    __shared__ double red[4];
+    const int k = blockIdx.x, m = blockIdx.y;
     double s = 0.0;
-    for (int i = 0; i < n; ++i) {
-        if (kind[i] != 0 || cond[i] != k) continue;
+    for (int t = cp_ptr[k] + (int)threadIdx.x; t < cp_ptr[k + 1]; t += 256) {
+        const int i = cp_idx[t];
         const int a = rp[i] >= 0 ? rp[i] : rm[i];
         s += eps[a] * X[q_slot[i] + (int64_t)m * ldx] * pan[i].area;
     }
-    C[k * m_main + m] = scale * s;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) C[k * m_main + m] = scale * ((red[0] + red[1]) + (red[2] + red[3]));
 }
 
-// C (m x nc) = alpha op(A) B + beta C, FP64, op(A) = A (TA false: A is m x k)
-// or A^T (TA true: A is k x m); column-major, any sizes.  64 x 64 output tiles,
-// 256 threads of 4 x 4, K in chunks of 16 through LDS.
-template <bool TA>
-__global__ __launch_bounds__(256) void dgemm_kernel(int m, int nc, int kk, double alpha, const double *__restrict__ A,
-                                                    int64_t lda, const double *__restrict__ B, int64_t ldb,
-                                                    double beta, double *__restrict__ C, int64_t ldc)
+__global__ void dl_sub_kernel(double *__restrict__ X, int64_t ldx, const double *__restrict__ D, int64_t ldd, int rows)
 {
-    __shared__ double As[16][64 + 1], Bs[16][64 + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < kk; k0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int kq = e / 64, ii = e % 64;   // As[kq][ii] = op(A)[i0 + ii, k0 + kq]
-            const int gi = i0 + ii, gk = k0 + kq;
-            double v = 0.0;
-            if (gi < m && gk < kk) v = TA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
-            As[kq][ii] = v;
-            const int gj = j0 + ii;               // Bs[kq][jj] = B[k0 + kq, j0 + jj]
-            Bs[kq][ii] = (gj < nc && gk < kk) ? B[gk + (int64_t)gj * ldb] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kq = 0; kq < 16; ++kq)
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(As[kq][tx + 16 * a], Bs[kq][ty + 16 * b], acc[a][b]);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int gi = i0 + tx + 16 * a, gj = j0 + ty + 16 * b;
-            if (gi < m && gj < nc) {
-                double *c = C + gi + (int64_t)gj * ldc;
-                *c = alpha * acc[a][b] + (beta == 0.0 ? 0.0 : beta * *c);
-            }
-        }
-}
-
-hipError_t launch_dgemm(bool ta, int m, int nc, int kk, double alpha, const double *A, int64_t lda, const double *B,
-                        int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t s)
-{
-    if (m <= 0 || nc <= 0) return hipSuccess;
-    const dim3 grid((m + 63) / 64, (nc + 63) / 64);
-    if (ta)
-        hipLaunchKernelGGL(dgemm_kernel<true>, grid, dim3(256), 0, s, m, nc, kk, alpha, A, lda, B, ldb, beta, C, ldc);
-    else
-        hipLaunchKernelGGL(dgemm_kernel<false>, grid, dim3(256), 0, s, m, nc, kk, alpha, A, lda, B, ldb, beta, C, ldc);
-    return hipGetLastError();
+    const int i = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+    if (i < rows) X[i + (int64_t)c * ldx] -= D[i + (int64_t)c * ldd];
 }
 
 hipError_t launch_dl_system(const Panel *pan, int n, const double *A, int64_t lda, const double *Q, int64_t ldq,
-                            const int32_t *kind, const int32_t *cond, const int32_t *rp, const int32_t *rm,
-                            const double *eps, const int32_t *eq_reg, const int32_t *eq_pan, const int32_t *u_slot,
-                            const int32_t *q_slot, int nu, int m_main, double *M, int64_t ldm, double *B, int64_t ldb,
-                            hipStream_t s)
+                            const int32_t *kind, const int32_t *rp, const int32_t *rm, const double *eps,
+                            const int32_t *eq_reg, const int32_t *eq_pan, const int32_t *u_slot,
+                            const int32_t *q_slot, const int32_t *cp_ptr, const int32_t *cp_idx, int nu, int m_main,
+                            double *M, double *Mt, int64_t ldm, double *B, double *Bneg, int64_t ldb, hipStream_t s)
 {
-    if (n <= 0 || nu <= 0) return hipSuccess;
+    if (n <= 0 || nu <= 0 || m_main <= 0 || m_main > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(dl_system_kernel, dim3((n + 255) / 256, std::min(nu, 65535)), dim3(256), 0, s, pan, n, A, lda,
-                       Q, ldq, kind, rp, rm, eps, eq_reg, eq_pan, u_slot, q_slot, nu, M, ldm);
+                       Q, ldq, kind, rp, rm, eps, eq_reg, eq_pan, u_slot, q_slot, nu, M, Mt, ldm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dl_rhs_kernel, dim3((nu + 255) / 256, m_main), dim3(256), 0, s, pan, n, Q, ldq, kind, cond,
-                       rp, rm, eq_reg, eq_pan, nu, m_main, B, ldb);
+    hipLaunchKernelGGL(dl_rhs_kernel, dim3((nu + 255) / 256, m_main), dim3(256), 0, s, pan, Q, ldq, rp, rm, eq_reg,
+                       eq_pan, cp_ptr, cp_idx, nu, B, Bneg, ldb);
     return hipGetLastError();
 }
 
-hipError_t launch_dl_charges(const Panel *pan, int n, const int32_t *kind, const int32_t *cond, const int32_t *rp,
-                             const int32_t *rm, const double *eps, const int32_t *q_slot, const double *X,
+hipError_t launch_dl_charges(const Panel *pan, const int32_t *rp, const int32_t *rm, const double *eps,
+                             const int32_t *q_slot, const int32_t *cp_ptr, const int32_t *cp_idx, const double *X,
                              int64_t ldx, int m_main, double scale, double *C, hipStream_t s)
 {
-    if (m_main > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(dl_charge_kernel, dim3(m_main), dim3(((m_main + 63) / 64) * 64), 0, s, pan, n, kind, cond, rp,
-                       rm, eps, q_slot, X, ldx, m_main, scale, C);
+    if (m_main <= 0 || m_main > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(dl_charge_kernel, dim3(m_main, m_main), dim3(256), 0, s, pan, rp, rm, eps, q_slot, cp_ptr,
+                       cp_idx, X, ldx, m_main, scale, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_dl_sub(double *X, int64_t ldx, const double *D, int64_t ldd, int rows, int m, hipStream_t s)
+{
+    if (rows <= 0 || m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dl_sub_kernel, dim3((rows + 255) / 256, m), dim3(256), 0, s, X, ldx, D, ldd, rows);
     return hipGetLastError();
 }
 

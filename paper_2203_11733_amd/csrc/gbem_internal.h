@@ -215,6 +215,11 @@ int residual_splits(int npad);
 size_t chol_winv_bytes(int dtype, int64_t npad);
 size_t chol_panel_bytes(int dtype, int64_t npad);
 size_t chol_panel16_bytes(int dtype, int64_t npad);
+// lower triangle of C = P P^T (FP64 MFMA, the factorisation's trailing-update
+// tiles): P is nrows x K column-major (nrows a multiple of 128, K of 16); the
+// upper triangle of C's diagonal tiles keeps its old values
+hipError_t launch_gram_f64(int64_t nrows, int64_t K, const double *P, int64_t ldp, double *C, int64_t ldc,
+                           hipStream_t s);
 // W_k = inverse of the 128 x 128 diagonal blocks of an existing factor L
 hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t lda, void *Winv,
                               hipStream_t s);
@@ -240,20 +245,21 @@ hipError_t launch_axpy_cols(double *X, int64_t ldx, const double *D, int64_t ldd
 // (row, col: the near list, col <= row) in both orders
 hipError_t launch_double_layer(const Panel *pan, int n, const int32_t *row, const int32_t *col, int64_t nnz,
                                double *Q, int64_t ldq, hipStream_t s);
-// system matrix M (nu x nu, zeroed by the caller) and right-hand sides B (nu
-// x m_main) of the region-by-region equations; A: single-layer entries
-// (normalised by the two areas), Q: double-layer integrals
+// system matrix M (nu x nu, zeroed by the caller) and its transpose Mt (both
+// column-major), right-hand sides B and -B (nu x m_main) of the
+// region-by-region equations; A: single-layer entries (normalised by the two
+// areas), Q: double-layer integrals.  cp_ptr / cp_idx: the conductor panels
+// of each net (CSR over nets, panel order)
 hipError_t launch_dl_system(const Panel *pan, int n, const double *A, int64_t lda, const double *Q, int64_t ldq,
-                            const int32_t *kind, const int32_t *cond, const int32_t *rp, const int32_t *rm,
-                            const double *eps, const int32_t *eq_reg, const int32_t *eq_pan, const int32_t *u_slot,
-                            const int32_t *q_slot, int nu, int m_main, double *M, int64_t ldm, double *B, int64_t ldb,
-                            hipStream_t s);
+                            const int32_t *kind, const int32_t *rp, const int32_t *rm, const double *eps,
+                            const int32_t *eq_reg, const int32_t *eq_pan, const int32_t *u_slot,
+                            const int32_t *q_slot, const int32_t *cp_ptr, const int32_t *cp_idx, int nu, int m_main,
+                            double *M, double *Mt, int64_t ldm, double *B, double *Bneg, int64_t ldb, hipStream_t s);
 // C[k m_main + m] = scale * sum over the panels of conductor k of eps q |I|
-hipError_t launch_dl_charges(const Panel *pan, int n, const int32_t *kind, const int32_t *cond, const int32_t *rp,
-                             const int32_t *rm, const double *eps, const int32_t *q_slot, const double *X,
+hipError_t launch_dl_charges(const Panel *pan, const int32_t *rp, const int32_t *rm, const double *eps,
+                             const int32_t *q_slot, const int32_t *cp_ptr, const int32_t *cp_idx, const double *X,
                              int64_t ldx, int m_main, double scale, double *C, hipStream_t s);
-// C (m x nc) = alpha op(A) B + beta C in FP64, op(A) = A^T when ta
-hipError_t launch_dgemm(bool ta, int m, int nc, int kk, double alpha, const double *A, int64_t lda, const double *B,
-                        int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t s);
+// X -= D (rows x m)
+hipError_t launch_dl_sub(double *X, int64_t ldx, const double *D, int64_t ldd, int rows, int m, hipStream_t s);
 
 }  // namespace gbem

@@ -1,10 +1,10 @@
 """GPU tests of the multi-dielectric path (section 4) against the oracle.
 
 The library integrates the double-layer kernel over near pairs in closed form
-and over far pairs with the closed-form inner integral under a 6 x 6 Gauss
-rule on the target (at the near threshold eta = 2 that rule is within 1e-15
-|I_i| of the exact value); the oracle integrates the target adaptively to
-1e-12.  So Q entries agree to 1e-12 |I_i| (Q_ik is at most |I_i| / 2 in
+and over far pairs with the closed-form inner integral under an n x n Gauss
+rule on the target, n from 6 at the near threshold eta = 2 down to 2 at 40
+diameters (each within about 1e-13 |I_i| of the exact value); the oracle
+integrates the target adaptively to 1e-12.  So Q entries agree to 1e-12 |I_i| (Q_ik is at most |I_i| / 2 in
 size), and capacitances with the same single-layer rule on both sides (exact
 near pairs, 3 x 3 Gauss far pairs) to 1e-11 of max |C| (the solves: a direct
 LU in the oracle, the normal equations refined to a residual of 1e-13 on the
