@@ -224,11 +224,11 @@ def serving(args, binding, np):
     import gbem_inputs as gi
     stream = gi.serving_stream(n_jobs=args.jobs)
     meshes = [(t, lay, *binding.mesh_layout(lay)) for t, lay in stream]
-    opts = binding.make_opts(args.p, args.eta, **MODES[args.mode])
+    opts = binding.make_opts(args.p, args.eta, graph=args.graph, **MODES[args.mode])
     n_list = [m[2].shape[0] for m in meshes]
     log(f"serving: {len(meshes)} jobs, N from {min(n_list)} to {max(n_list)}, mode {args.mode}")
     out = {"metric": "served extractions/s + p50/p99 latency", "unit": "extractions/s", "n_gpus": 1,
-           "mode": args.mode, "dtype": DTYPE_LABEL[args.mode], "data": "synthetic",
+           "mode": args.mode, "graph": bool(args.graph), "dtype": DTYPE_LABEL[args.mode], "data": "synthetic",
            "config": {"workload": f"serving stream: {len(meshes)} random Manhattan layouts, "
                                   f"N {min(n_list)}-{max(n_list)}, Poisson 50 jobs/s"}}
     with binding.Context(0) as ctx:
@@ -483,6 +483,9 @@ def main():
                          "crossing_bars_in_box) against the layout's own mesh")
     ap.add_argument("--exact", action="store_true",
                     help="exact reference mode (every pair exact) on --layout vs the far-field settings")
+    ap.add_argument("--graph", action="store_true",
+                    help="opts.graph: replay each job's factor/solve launches as a captured hipGraph "
+                         "(ignored while the library's profiling events are on: use with --no-profile)")
     ap.add_argument("--dielectric", action="store_true",
                     help="multi-dielectric extraction of the six-net three-layer stack instead")
     ap.add_argument("--dl-h", type=float, default=0.1,
@@ -557,7 +560,7 @@ def main():
     # the trailing update (the throughput kernel) is timed too when the
     # panel chain is the largest class
     timed = [dominant] + (["syrk"] if dominant != "syrk" and "syrk" in rep_all["profile"] else [])
-    opts = binding.make_opts(args.p, args.eta, profile=None if args.no_profile else timed,
+    opts = binding.make_opts(args.p, args.eta, profile=None if args.no_profile else timed, graph=args.graph,
                              **MODES[args.mode])
     log(f"bench: warmup done; dominant kernel class {dominant}")
     elapsed, lat_ms, reps = run_steps(opts, args.steps)
@@ -608,7 +611,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "C_rel_err_vs_f64": err,
         "refine_iters": r_last["refine_iters"], "residual": r_last["residual"],
-        "factor_used": r_last["factor_used"],
+        "factor_used": r_last["factor_used"], "graph_used": bool(r_last["graph_used"]),
         "tile_shapes": {"outer_width": r_last["outer_width"], "super_panels": r_last["super_panels"],
                         "source": os.path.relpath(binding.tuning_source(), ROOT)
                         if os.path.isabs(binding.tuning_source()) else binding.tuning_source()},

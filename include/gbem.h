@@ -100,6 +100,14 @@ typedef struct {
     int32_t max_refine;         /* refinement iteration cap (default 30) */
     int32_t profile;            /* bit c set: time the launches of kernel class c (gbem_kernel_class) with
                                    HIP events on their streams (gbem_report.prof_*); 0: no events */
+    int32_t graph;              /* 1: replay the launches between the near-list readback and the first
+                                   refinement readback (FP64: the end of the solve) as one hipGraph,
+                                   captured per job and applied to the worker's cached executable of
+                                   the same launch topology (hipGraphExecUpdate; instantiated when none
+                                   matches); same kernels and results as 0.  Ignored with profile != 0;
+                                   refused by gbem_extract_device_noalloc (instantiation allocates).
+                                   Report times with 1: assemble = panels, near test and far field,
+                                   factor = the graph, solve = the rest. */
 } gbem_opts;
 
 /* Kernel classes of gbem_report.prof_* (see the design notes for their work units). */
@@ -135,6 +143,8 @@ typedef struct {
     double prof_bytes[GBEM_K_COUNT];     /* algorithmic HBM bytes (compulsory reads + writes) */
     int32_t outer_width;        /* tile shapes the factorisation used (see gbem_tuning) */
     int32_t super_panels;
+    int32_t graph_used;         /* opts.graph: 1 when the captured segment ran as a graph */
+    int32_t graph_instantiated; /* 1: no cached executable matched, the graph was instantiated */
 } gbem_report;
 
 /* Tile shapes of the Cholesky factorisation (schedule only: results do not

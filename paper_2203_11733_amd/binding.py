@@ -57,7 +57,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("far_order", ctypes.c_int32), ("near_eta", ctypes.c_double),
                 ("far_dtype", ctypes.c_int32), ("factor_dtype", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("max_refine", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -68,7 +68,8 @@ class Report(ctypes.Structure):
                 ("n_near", ctypes.c_int64), ("n_panels", ctypes.c_int64),
                 ("prof_ms", ctypes.c_double * NCLS), ("prof_launches", ctypes.c_int64 * NCLS),
                 ("prof_flops", ctypes.c_double * NCLS), ("prof_bytes", ctypes.c_double * NCLS),
-                ("outer_width", ctypes.c_int32), ("super_panels", ctypes.c_int32)]
+                ("outer_width", ctypes.c_int32), ("super_panels", ctypes.c_int32),
+                ("graph_used", ctypes.c_int32), ("graph_instantiated", ctypes.c_int32)]
 
     def as_dict(self):
         d = {}
@@ -210,10 +211,10 @@ def profile_mask(profile) -> int:
 
 
 def make_opts(far_order=3, near_eta=2.0, far_dtype="f64", factor_dtype="f64", refine_tol=1e-6,
-              max_refine=30, profile=False) -> Opts:
+              max_refine=30, profile=False, graph=False) -> Opts:
     return Opts(far_order, near_eta, DTYPES[far_dtype] if isinstance(far_dtype, str) else far_dtype,
                 DTYPES[factor_dtype] if isinstance(factor_dtype, str) else factor_dtype, refine_tol, max_refine,
-                profile_mask(profile))
+                profile_mask(profile), int(bool(graph)))
 
 
 def mesh_boxes(box_lo, box_hi, box_cond, rule):

@@ -219,8 +219,55 @@ struct Workspace {
         events_ok = true;
         return hipSuccess;
     }
+    // executables of captured launch sequences (opts.graph), keyed by order,
+    // factor dtype and right-hand sides; a new capture is applied to the
+    // matching one with hipGraphExecUpdate (instantiated when the topology
+    // differs or none matches)
+    struct GraphExec {
+        int64_t npad;
+        int dtype, m;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphExec> gexec;
+    static constexpr size_t kMaxGraphs = 8;
+    hipError_t launch_graph(hipGraph_t g, int64_t npad, int dtype, int m, hipStream_t st, bool &instantiated)
+    {
+        instantiated = false;
+        GraphExec *slot = nullptr;
+        for (auto &x : gexec)
+            if (x.npad == npad && x.dtype == dtype && x.m == m) slot = &x;
+        hipError_t e = hipSuccess;
+        if (slot) {
+            hipGraphNode_t bad_node = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            e = hipGraphExecUpdate(slot->exec, g, &bad_node, &res);
+            if (e != hipSuccess || res != hipGraphExecUpdateSuccess) {
+                (void)hipGetLastError();   // a topology mismatch is not an error here
+                (void)hipGraphExecDestroy(slot->exec);
+                slot->exec = nullptr;
+                if ((e = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+                    gexec.erase(gexec.begin() + (slot - gexec.data()));
+                    return e;
+                }
+                instantiated = true;
+            }
+        } else {
+            if (gexec.size() >= kMaxGraphs) {
+                (void)hipGraphExecDestroy(gexec.front().exec);
+                gexec.erase(gexec.begin());
+            }
+            GraphExec x{npad, dtype, m, nullptr};
+            if ((e = hipGraphInstantiate(&x.exec, g, nullptr, nullptr, 0)) != hipSuccess) return e;
+            gexec.push_back(x);
+            slot = &gexec.back();
+            instantiated = true;
+        }
+        return hipGraphLaunch(slot->exec, st);
+    }
+
     ~Workspace()
     {
+        for (auto &x : gexec) (void)hipGraphExecDestroy(x.exec);
         release_all();
         if (events_ok) {
             for (auto &e : ev) (void)hipEventDestroy(e);
@@ -331,6 +378,10 @@ static bool opts_ok(const gbem_opts &o, std::string &why)
         why = "refinement needs refine_tol > 0 and max_refine >= 0";
         return false;
     }
+    if (o.graph != 0 && o.graph != 1) {
+        why = "graph must be 0 or 1";
+        return false;
+    }
     return true;
 }
 
@@ -395,6 +446,37 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             rep->prof_launches[c] = 0;
         }
     }
+    // opts.graph: the launches from the near-list fill to the first host wait
+    // after it are captured into a graph (no host waits, allocations, memset
+    // nodes or timing events inside; the guard ends a capture left open by an
+    // error return)
+    const bool use_graph = o.graph == 1 && stop == Stop::kFull && !pf.on;
+    struct CaptureGuard {
+        hipStream_t st;
+        bool on = false;
+        ~CaptureGuard()
+        {
+            if (!on) return;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+        }
+    } cap{st};
+    bool graph_used = false, graph_inst = false;
+    const int dtype0 = o.factor_dtype;
+    auto end_segment = [&]() -> hipError_t {
+        if (!cap.on) return hipSuccess;
+        cap.on = false;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (e != hipSuccess) return e;
+        e = ws.launch_graph(g, npad, dtype0, m, st, graph_inst);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return e;
+        graph_used = true;
+        return hipEventRecord(ws.ev[2], st);   // the graph ends the "factor" stage
+    };
     HIPCHK(hipEventRecord(ws.ev[0], st), "hipEventRecord");
     HIPCHK(hipMemsetAsync(flags, 0, 64, st), "hipMemsetAsync");
     int tok = pf.start(st, GBEM_K_OTHER);
@@ -463,15 +545,34 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near rows");
     HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(nnz, 1)), "alloc near cols");
     HIPCHK(ws.semi.ensure(near_semi_bytes(nnz)), "alloc near queue");
+    if (use_graph) {
+        // everything the captured launches use, allocated (and the solve flags
+        // zeroed) before the capture
+        HIPCHK(ws.X.ensure((size_t)npad * m * 8), "alloc X");
+        HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
+        HIPCHK(ws.Winv.ensure(chol_winv_bytes(dtype0, npad)), "alloc W");
+        HIPCHK(ws.Pw.ensure(chol_panel_bytes(dtype0, npad)), "alloc panel");
+        HIPCHK(ws.P16.ensure(std::max<size_t>(chol_panel16_bytes(dtype0, npad), 64)), "alloc panel16");
+        if (dtype0 != GBEM_F64) {
+            HIPCHK(ws.R.ensure((size_t)npad * m * 8), "alloc R");
+            HIPCHK(ws.rpart.ensure((size_t)residual_splits((int)npad) * m * npad * 8), "alloc residual partials");
+        }
+        HIPCHK(ws.partial.ensure((size_t)chunks_of(n) * m * m * 8), "alloc partials");
+        if (!ws.lookahead_on_main) HIPCHK(ws.ensure_side(), "side stream");
+        HIPCHK(near_eval_upload_rule(st), "near rule");
+        HIPCHK(hipEventRecord(ws.ev[1], st), "hipEventRecord");
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+        cap.on = true;
+    }
     tok = pf.start(st, GBEM_K_NEAR_LIST);
     HIPCHK(launch_near_fill(ws.nmask.as<uint64_t>(), n, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
                             ws.ncol.as<int32_t>(), st), "near_fill");
     pf.stop(tok, GBEM_K_NEAR_LIST, 0.0, (double)n * (n + 64) / 16.0 + (double)nnz * 8, st);
     tok = pf.start(st, GBEM_K_NEAR_EVAL);
     HIPCHK(launch_near_eval(dlo, dhi, ws.pan.as<Panel>(), ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), nnz,
-                            A, lda, ws.semi.as<int32_t>(), st, Fasm, npad, sasm), "near_eval");
+                            A, lda, ws.semi.as<int32_t>(), st, Fasm, npad, sasm, !cap.on), "near_eval");
     pf.stop(tok, GBEM_K_NEAR_EVAL, 0.0, (double)nnz * (2 * 8 + 2 * 4 + 2 * 48), st);
-    HIPCHK(hipEventRecord(ws.ev[1], st), "hipEventRecord");
+    if (!cap.on) HIPCHK(hipEventRecord(ws.ev[1], st), "hipEventRecord");
     if (rep) {
         rep->n_near = nnz;
         rep->n_panels = n;
@@ -484,7 +585,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
 
     HIPCHK(ws.X.ensure((size_t)npad * m * 8), "alloc X");
     HIPCHK(ws.ensure_sync(npad, st), "alloc solve flags");
-    HIPCHK(hipMemsetAsync(ws.sync.err, 0, 4, st), "hipMemsetAsync");
+    HIPCHK(launch_fill_i32(ws.sync.err, 1, 0, st), "clear solve flag");
     double *X = ws.X.as<double>();
     int dtype = o.factor_dtype;
     bool f_ready = Fasm != nullptr;   // F = S A S written by the assembly (consumed by the first factor)
@@ -495,7 +596,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         HIPCHK(ws.Winv.ensure(chol_winv_bytes(dtype, npad)), "alloc W");
         HIPCHK(ws.Pw.ensure(chol_panel_bytes(dtype, npad)), "alloc panel");
         HIPCHK(ws.P16.ensure(std::max<size_t>(chol_panel16_bytes(dtype, npad), 64)), "alloc panel16");
-        HIPCHK(hipMemsetAsync(flags + 1, 0, 4, st), "hipMemsetAsync");
+        HIPCHK(launch_fill_i32(flags + 1, 1, 0, st), "clear pivot flag");
         void *Fm = A;
         if (dtype != GBEM_F64) {
             if (!f_ready) {   // a retry: the failed factor overwrote F
@@ -523,7 +624,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         // their termination does not depend on the values).
         HIPCHK(hipMemcpyAsync(&rbk->info, flags + 1, 8, hipMemcpyDeviceToHost, st), "D2H info");
         HIPCHK(chol_solve_prep(dtype, npad, Fm, lda, ws.Winv.p, ws.sync, st), "solve prep");
-        HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
+        if (!cap.on && !graph_used) HIPCHK(hipEventRecord(ws.ev[2], st), "hipEventRecord");
         HIPCHK(hipMemcpyAsync(X, B, (size_t)npad * m * 8, hipMemcpyDeviceToDevice, st), "copy B");
         if (dtype == GBEM_F64) {
             HIPCHK(chol_solve(dtype, npad, A, lda, ws.Winv.p, m, X, npad, ws.sync, st, &pf), "solve");
@@ -551,6 +652,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
             HIPCHK(launch_col_norms(R, npad, (int)npad, m, rnorm, st), "col_norms");
             HIPCHK(hipMemcpyAsync(rbk->rn, rnorm, sizeof(double) * m, hipMemcpyDeviceToHost, st), "D2H norms");
             HIPCHK(hipMemcpyAsync(&rbk->serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
+            HIPCHK(end_segment(), "graph");
             HIPCHK(hipEventRecord(ws.evrb, st), "hipEventRecord");
             HIPCHK(hipEventSynchronize(ws.evrb), "hipEventSynchronize");
             if (rbk->perr) {
@@ -592,6 +694,7 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
     HIPCHK(ws.partial.ensure((size_t)nchunks * m * m * 8), "alloc partials");
     HIPCHK(launch_charge_partials(X, npad, dcond, n, m, ws.partial.as<double>(), nchunks, st), "charges");
     HIPCHK(launch_charge_finish(ws.partial.as<double>(), nchunks, m, eps_r * kEps0 * lu, dC, st), "charges");
+    HIPCHK(end_segment(), "graph");
     HIPCHK(hipEventRecord(ws.ev[3], st), "hipEventRecord");
     HIPCHK(hipMemcpyAsync(&rbk->serr, ws.sync.err, 4, hipMemcpyDeviceToHost, st), "D2H solve flag");
     if (hC) HIPCHK(hipMemcpyAsync(rbk->C, dC, sizeof(double) * m * m, hipMemcpyDeviceToHost, st), "D2H C");
@@ -625,6 +728,8 @@ static gbem_status run_pipeline(Workspace &ws, hipStream_t st, int n, int m, con
         const CholShape sh = chol_shape(dtype, npad);
         rep->outer_width = sh.outer_width;
         rep->super_panels = sh.super_panels;
+        rep->graph_used = graph_used;
+        rep->graph_instantiated = graph_inst;
         pf.collect(rep);
     }
     return GBEM_OK;
@@ -969,6 +1074,7 @@ extern "C" void gbem_default_opts(gbem_opts *o)
     o->refine_tol = 1e-6;
     o->max_refine = 30;
     o->profile = 0;
+    o->graph = 0;
 }
 
 extern "C" gbem_status gbem_create(int device, size_t budget, gbem_ctx **out)
@@ -1132,6 +1238,10 @@ extern "C" gbem_status gbem_extract_device_noalloc(gbem_ctx *ctx, const gbem_mes
     if (o.profile != 0) {
         set_error("gbem_extract_device_noalloc: opts->profile must be 0 (the timing events would be created "
                   "during the call)");
+        return GBEM_EINVAL;
+    }
+    if (o.graph != 0) {
+        set_error("gbem_extract_device_noalloc: opts->graph must be 0 (instantiating a graph allocates)");
         return GBEM_EINVAL;
     }
     const int n = mesh->n_panels, m = mesh->n_conductors;

@@ -154,7 +154,10 @@ hipError_t launch_near_fill(const uint64_t *mask, int n, const int64_t *row_ptr,
 hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
                             const int32_t *row, const int32_t *col, int64_t nnz, double *A,
                             int64_t lda, int32_t *semi_buf, hipStream_t s, float *F = nullptr,
-                            int64_t ldf = 0, const double *sc = nullptr);
+                            int64_t ldf = 0, const double *sc = nullptr, bool upload_rule = true);
+// the reductions' Gauss rules to constant memory (launch_near_eval does it
+// itself unless upload_rule is false: inside a captured region)
+hipError_t near_eval_upload_rule(hipStream_t s);
 // sc[i] = a_ii^(-1/2) from the self integrals of the panels (the values the
 // near pass writes on the diagonal), 1 for the padding rows [n, npad)
 hipError_t launch_self_scale(const double *lo, const double *hi, const Panel *pan, int n, int npad, double *sc,
@@ -224,6 +227,9 @@ hipError_t launch_gram_f64(int64_t nrows, int64_t K, const double *P, int64_t ld
 hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t lda, void *Winv,
                               hipStream_t s);
 
+// refine.hip: mixed-precision helpers; p[0..n) = v as a kernel (no memset
+// node in a captured stream)
+hipError_t launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st);
 // refine.hip: mixed-precision helpers
 hipError_t launch_jacobi_scale(const double *A, int64_t lda, int npad, double *s, hipStream_t st);
 hipError_t launch_scale_convert(const double *A, int64_t lda, const double *s, int npad,

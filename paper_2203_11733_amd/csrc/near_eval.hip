@@ -329,21 +329,28 @@ hipError_t launch_self_scale(const double *lo, const double *hi, const Panel *pa
     return hipGetLastError();
 }
 
-hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
-                            const int32_t *row, const int32_t *col, int64_t nnz, double *A,
-                            int64_t lda, int32_t *semi_buf, hipStream_t s, float *F, int64_t ldf,
-                            const double *sc)
+// Gauss rules of the semi-analytic reductions into constant memory (from a
+// host copy: outside any captured region, since a captured copy would read
+// the host buffer again at every replay)
+hipError_t near_eval_upload_rule(hipStream_t s)
 {
-    if ((F == nullptr) != (sc == nullptr)) return hipErrorInvalidValue;
-    if (nnz <= 0) return hipSuccess;
     NearRule g;
     gauss_legendre(kNearOrder, g.x, g.w);
     gauss_legendre(kNearOrderWide, g.x8, g.w8);
-    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_near), &g, sizeof(g), 0, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_near), &g, sizeof(g), 0, hipMemcpyHostToDevice, s);
+}
+
+hipError_t launch_near_eval(const double *lo, const double *hi, const Panel *pan,
+                            const int32_t *row, const int32_t *col, int64_t nnz, double *A,
+                            int64_t lda, int32_t *semi_buf, hipStream_t s, float *F, int64_t ldf,
+                            const double *sc, bool upload_rule)
+{
+    if ((F == nullptr) != (sc == nullptr)) return hipErrorInvalidValue;
+    if (nnz <= 0) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (upload_rule && (e = near_eval_upload_rule(s)) != hipSuccess) return e;
     int32_t *count = semi_buf, *list = semi_buf + 64;
-    e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
-    if (e != hipSuccess) return e;
+    if ((e = launch_fill_i32(count, 1, 0, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(near_eval_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, lo, hi,
                        pan, row, col, nnz, A, lda, list, count, F, ldf, sc);
     const int64_t waves = std::min<int64_t>(nnz, 4096);

@@ -14,6 +14,21 @@ __global__ void jacobi_scale_kernel(const double *__restrict__ A, int64_t lda, i
     if (i < npad) s[i] = 1.0 / sqrt(A[i + (int64_t)i * lda]);
 }
 
+__global__ void fill_i32_kernel(int32_t *__restrict__ p, int n, int32_t v)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// A kernel in place of hipMemsetAsync for flags and counters: a fill of this
+// kind is a kernel node when the stream is captured into a graph.
+hipError_t launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_jacobi_scale(const double *A, int64_t lda, int npad, double *s, hipStream_t st)
 {
     hipLaunchKernelGGL(jacobi_scale_kernel, dim3((npad + 255) / 256), dim3(256), 0, st, A, lda, npad, s);

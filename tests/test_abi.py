@@ -210,3 +210,20 @@ def test_dielectric_mesh_checks_before_context():
     assert st == binding.EINVAL and b"panel 0" in msg
     st, msg = call()
     assert st == binding.EINVAL and b"context" in msg
+
+
+def test_graph_option_checked_before_context():
+    lib = binding.load()
+    lo, hi, cond = binding.mesh_layout(gi.two_plates(h=0.5))
+    mesh = _host_mesh(lo, hi, cond)
+    C = np.zeros((2, 2))
+    o = binding.make_opts(graph=True)
+    assert o.graph == 1
+    assert lib.gbem_extract(None, ctypes.byref(mesh), ctypes.byref(o), C.ctypes.data, None) == binding.EINVAL
+    assert b"context" in lib.gbem_last_error()
+    o.graph = 2
+    assert lib.gbem_extract(None, ctypes.byref(mesh), ctypes.byref(o), C.ctypes.data, None) == binding.EINVAL
+    assert b"graph must be 0 or 1" in lib.gbem_last_error()
+    d = binding.Opts()
+    lib.gbem_default_opts(ctypes.byref(d))
+    assert d.graph == 0
