@@ -1810,16 +1810,54 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
             return GBEM_EINVAL;
         }
         if (k == GBEM_PANEL_CONDUCTOR) cond[i] = mesh->conductor[i];
+    }
+    // unknowns ordered by the pair (lower, upper region) of their panel, so
+    // that the unknowns of one region's boundary lie in a narrow slot range
+    // (contiguous for layered regions); per panel q first, then u
+    auto lower_region = [&](int i) {
+        const int a = mesh->region_plus[i], b = mesh->region_minus[i];
+        return a < 0 ? b : (b < 0 ? a : std::min(a, b));
+    };
+    auto upper_region = [&](int i) { return std::max(mesh->region_plus[i], mesh->region_minus[i]); };
+    std::vector<int> porder(n);
+    for (int i = 0; i < n; ++i) porder[i] = i;
+    std::stable_sort(porder.begin(), porder.end(), [&](int x, int y) {
+        return std::make_pair(lower_region(x), upper_region(x)) < std::make_pair(lower_region(y), upper_region(y));
+    });
+    for (int i : porder) {
+        const int k = mesh->kind[i];
         if (k != GBEM_PANEL_NEUMANN) q_slot[i] = nu++;
         if (k == GBEM_PANEL_NEUMANN || k == GBEM_PANEL_INTERFACE) u_slot[i] = nu++;
     }
-    for (int a = 0; a < R; ++a)
+    // equations region by region, each region's rows from a multiple of 16
+    // (gap rows: region -1, zero), and the slot range each region touches
+    std::vector<int> row0(R, 0), nrows(R, 0), slo(R, INT32_MAX), shi(R, 0);
+    int neq = 0;
+    for (int a = 0; a < R; ++a) {
+        while (eq_reg.size() % 16) {
+            eq_reg.push_back(-1);
+            eq_pan.push_back(0);
+        }
+        row0[a] = (int)eq_reg.size();
         for (int i = 0; i < n; ++i)
             if (mesh->region_plus[i] == a || mesh->region_minus[i] == a) {
                 eq_reg.push_back(a);
                 eq_pan.push_back(i);
+                ++nrows[a];
+                for (int sl : {q_slot[i], u_slot[i]})
+                    if (sl >= 0) {
+                        slo[a] = std::min(slo[a], sl);
+                        shi[a] = std::max(shi[a], sl + 1);
+                    }
             }
-    if ((int)eq_reg.size() != nu) {
+        neq += nrows[a];
+    }
+    while (eq_reg.size() % 16) {
+        eq_reg.push_back(-1);
+        eq_pan.push_back(0);
+    }
+    const int nrow = (int)eq_reg.size();
+    if (neq != nu) {
         set_error("gbem_extract_dielectric: equations and unknowns do not match");
         return GBEM_EINVAL;
     }
@@ -1858,7 +1896,7 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
         for (int i = 0; i < n; ++i)
             if (cond[i] >= 0) cp_idx[fill[cond[i]]++] = i;
     }
-    const size_t ntab = (size_t)6 * n + 2 * (size_t)nu + (M + 1) + cp_idx.size();
+    const size_t ntab = (size_t)6 * n + 2 * (size_t)nrow + (M + 1) + cp_idx.size();
     HIPCHK(tab.ensure(sizeof(int32_t) * ntab), "alloc");
     std::vector<int32_t> htab(ntab);
     for (int i = 0; i < n; ++i) {
@@ -1869,22 +1907,22 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
         htab[4 * n + i] = u_slot[i];
         htab[5 * n + i] = q_slot[i];
     }
-    for (int r = 0; r < nu; ++r) {
+    for (int r = 0; r < nrow; ++r) {
         htab[6 * (size_t)n + r] = eq_reg[r];
-        htab[6 * (size_t)n + nu + r] = eq_pan[r];
+        htab[6 * (size_t)n + nrow + r] = eq_pan[r];
     }
-    std::copy(cp_ptr.begin(), cp_ptr.end(), htab.begin() + 6 * (size_t)n + 2 * nu);
-    std::copy(cp_idx.begin(), cp_idx.end(), htab.begin() + 6 * (size_t)n + 2 * nu + M + 1);
+    std::copy(cp_ptr.begin(), cp_ptr.end(), htab.begin() + 6 * (size_t)n + 2 * nrow);
+    std::copy(cp_idx.begin(), cp_idx.end(), htab.begin() + 6 * (size_t)n + 2 * nrow + M + 1);
     HIPCHK(hipMemcpyAsync(tab.p, htab.data(), sizeof(int32_t) * ntab, hipMemcpyHostToDevice, st), "H2D");
     HIPCHK(epsb.ensure(sizeof(double) * R), "alloc");
     HIPCHK(hipMemcpyAsync(epsb.p, mesh->eps_r, sizeof(double) * R, hipMemcpyHostToDevice, st), "H2D");
     const int32_t *d_kind = tab.as<int32_t>(), *d_rp = d_kind + 2 * n, *d_rm = d_kind + 3 * n,
                   *d_us = d_kind + 4 * n, *d_qs = d_kind + 5 * n, *d_er = d_kind + 6 * (size_t)n,
-                  *d_ep = d_er + nu, *d_cpp = d_ep + nu, *d_cpi = d_cpp + M + 1;
+                  *d_ep = d_er + nrow, *d_cpp = d_ep + nrow, *d_cpi = d_cpp + M + 1;
     int64_t nnz = 0;
     gbem_status s = dl_assemble(ctx, n, M, o.near_eta, o.far_order, true, Q, &nnz, st);
     if (s != GBEM_OK) return s;
-    const int64_t npadA = round_up(n, kPad), npad = round_up(nu, kPad);
+    const int64_t npadA = round_up(n, kPad), npad = round_up(std::max(nu, nrow), kPad);
     const auto t_asm = std::chrono::steady_clock::now();
     // the section 4.1 system M X = B (one column per main net), M and its
     // transpose zero-padded to order npad, B and -B to npad rows
@@ -1898,7 +1936,7 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     for (DevBuf *v : {&Mb, &Mt, &N}) HIPCHK(hipMemsetAsync(v->p, 0, mat, st), "memset");
     for (DevBuf *v : {&Bb, &Bn, &Z, &X, &Rr, &D}) HIPCHK(hipMemsetAsync(v->p, 0, vec, st), "memset");
     HIPCHK(launch_dl_system(ws.pan.as<Panel>(), n, ws.A.as<double>(), npadA, Q.as<double>(), n, d_kind, d_rp, d_rm,
-                            epsb.as<double>(), d_er, d_ep, d_us, d_qs, d_cpp, d_cpi, nu, M, Mb.as<double>(),
+                            epsb.as<double>(), d_er, d_ep, d_us, d_qs, d_cpp, d_cpi, nrow, M, Mb.as<double>(),
                             Mt.as<double>(), npad, Bb.as<double>(), Bn.as<double>(), npad, st), "system");
     // normal equations (M^T M) X = M^T B on the FP64 Cholesky (the system is
     // not symmetric): M^T M on the factorisation's MFMA tiles (M^T is the
@@ -1907,7 +1945,19 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     //   M^T B   = 0 - M^T (-B)      (A = M)
     //   B - M X                     (A = M^T)
     //   -M^T R  = 0 - M^T R         (A = M), subtracted from X
-    HIPCHK(launch_gram_f64(npad, npad, Mt.as<double>(), npad, N.as<double>(), npad, st), "M^T M");
+    // region by region: N = sum_a M_a^T M_a over region a's rows (K) and the
+    // slot range its boundary touches (the rest of M_a is zero), accumulated
+    // as -N on the subtracting tiles and negated once
+    for (int a = 0; a < R; ++a) {
+        if (nrows[a] == 0) continue;
+        int64_t s0 = slo[a] / 128 * 128;
+        const int64_t len = round_up(shi[a] - s0, 128);
+        if (s0 + len > npad) s0 = npad - len;
+        const int64_t K = round_up(nrows[a], 16);
+        HIPCHK(launch_gram_f64(len, K, Mt.as<double>() + s0 + (int64_t)row0[a] * npad, npad,
+                               N.as<double>() + s0 + s0 * npad, npad, true, st), "M^T M");
+    }
+    HIPCHK(launch_dl_negate(N.as<double>(), npad * npad, st), "M^T M");
     HIPCHK(launch_identity_pad(N.p, npad, nu, (int)npad, true, st), "pad");
     HIPCHK(launch_residual(Mb.as<double>(), npad, (int)npad, Bn.as<double>(), npad, Z.as<double>(), npad, M,
                            X.as<double>(), npad, part.as<double>(), st), "M^T B");

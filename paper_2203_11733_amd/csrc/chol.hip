@@ -1291,10 +1291,12 @@ hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t ld
 }
 
 hipError_t launch_gram_f64(int64_t nrows, int64_t K, const double *P, int64_t ldp, double *C, int64_t ldc,
-                           hipStream_t s)
+                           bool subtract, hipStream_t s)
 {
     if (nrows % kBM || K % kBK || nrows <= 0 || K <= 0) return hipErrorInvalidValue;
     const int tm = (int)(nrows / kBM);
+    if (subtract)
+        return launch_gemm<double, kTri, true, true>(tm, tm * (tm + 1) / 2, (int)K, P, ldp, P, ldp, C, ldc, s);
     return launch_gemm<double, kTri, true, false>(tm, tm * (tm + 1) / 2, (int)K, P, ldp, P, ldp, C, ldc, s);
 }
 

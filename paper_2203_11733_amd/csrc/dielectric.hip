@@ -274,7 +274,8 @@ hipError_t launch_double_layer(const Panel *pan, int n, const int32_t *row, cons
 }
 
 // ---------------------------------------------------------------- system
-// Row r = (region eq_reg[r], panel eq_pan[r]) of the Galerkin system, column k
+// Row r = (region eq_reg[r], panel eq_pan[r]) of the Galerkin system (eq_reg
+// -1: a gap row between two regions' row ranges, left zero), column k
 // a panel of that region's boundary (orientation: the region's outward normal
 // is -e_n when it lies on the + side of panel k, +e_n otherwise):
 //   u unknown at k (Neumann, interface):       M[r, u_slot[k]] = 1/2 |I_i| [k = i] + s Q_ik
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(256) void dl_system_kernel(const Panel *__restrict_
     if (k >= n) return;
     for (int r = blockIdx.y; r < nu; r += gridDim.y) {
         const int a = eq_reg[r], i = eq_pan[r];
-        if (rp[k] != a && rm[k] != a) continue;
+        if (a < 0 || (rp[k] != a && rm[k] != a)) continue;   // a < 0: a gap row (all zero)
         const double sgn = rp[k] == a ? -1.0 : 1.0;
         if (u_slot[k] >= 0) {
             const double coef = (k == i ? 0.5 * pan[i].area : 0.0) + sgn * Q[i + (int64_t)k * ldq];
@@ -332,6 +333,11 @@ __global__ __launch_bounds__(256) void dl_rhs_kernel(const Panel *__restrict__ p
     const int r = blockIdx.x * 256 + threadIdx.x, m = blockIdx.y;
     if (r >= nu) return;
     const int a = eq_reg[r], i = eq_pan[r];
+    if (a < 0) {   // a gap row
+        B[r + (int64_t)m * ldb] = 0.0;
+        Bneg[r + (int64_t)m * ldb] = 0.0;
+        return;
+    }
     double b = 0.0;
     for (int t = cp_ptr[m]; t < cp_ptr[m + 1]; ++t) {
         const int k = cp_idx[t];
@@ -368,6 +374,19 @@ __global__ __launch_bounds__(256) void dl_charge_kernel(const Panel *__restrict_
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) C[k * m_main + m] = scale * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+__global__ void dl_negate_kernel(double *__restrict__ A, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) A[i] = -A[i];
+}
+
+hipError_t launch_dl_negate(double *A, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dl_negate_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1 << 16)), dim3(256), 0, s,
+                       A, n);
+    return hipGetLastError();
 }
 
 __global__ void dl_sub_kernel(double *__restrict__ X, int64_t ldx, const double *__restrict__ D, int64_t ldd, int rows)

@@ -218,11 +218,14 @@ int residual_splits(int npad);
 size_t chol_winv_bytes(int dtype, int64_t npad);
 size_t chol_panel_bytes(int dtype, int64_t npad);
 size_t chol_panel16_bytes(int dtype, int64_t npad);
-// lower triangle of C = P P^T (FP64 MFMA, the factorisation's trailing-update
-// tiles): P is nrows x K column-major (nrows a multiple of 128, K of 16); the
-// upper triangle of C's diagonal tiles keeps its old values
+// lower triangle of C = P P^T, or C -= P P^T with subtract (FP64 MFMA, the
+// factorisation's trailing-update tiles): P is nrows x K column-major (nrows
+// a multiple of 128, K of 16); the upper triangle of C's diagonal tiles keeps
+// its old values
 hipError_t launch_gram_f64(int64_t nrows, int64_t K, const double *P, int64_t ldp, double *C, int64_t ldc,
-                           hipStream_t s);
+                           bool subtract, hipStream_t s);
+// A = -A over n elements
+hipError_t launch_dl_negate(double *A, int64_t n, hipStream_t s);
 // W_k = inverse of the 128 x 128 diagonal blocks of an existing factor L
 hipError_t chol_diag_inverses(int dtype, int64_t npad, const void *L, int64_t lda, void *Winv,
                               hipStream_t s);
