@@ -337,3 +337,38 @@ def layered_stack(n_wires: int = 3, h: float = 0.25, h_out: float | None = None,
             pl.face(nrm, 0.0, (0, W), (z[a], z[a + 1]), h_out, NEUMANN, -1, a, -1)
             pl.face(nrm, W, (0, W), (z[a], z[a + 1]), h_out, NEUMANN, -1, -1, a)
     return pl.mesh(f"layered_stack_{2 * n_wires}nets_h{h:g}", eps_r, 2 * n_wires)
+
+
+def two_slab_with_block(L=1.0, d1=0.3, d2=0.7, n_xy=4, n_z=2, eps_r=(4.0, 1.0, 7.0)) -> DielectricMesh:
+    """The two-slab capacitor with a third dielectric (region 2) embedded in
+    the lower slab: a block over the middle half of the plates (x, y in
+    [L/4, 3L/4]) from z = d1/3 up to the interface z = d1, whose top face is
+    the interface between regions 1 and 2.  Every region borders both others
+    (the region graph is a triangle, not a chain).  n_xy: a multiple of 4."""
+    assert n_xy % 4 == 0
+    H = d1 + d2
+    zb = d1 / 3.0
+    a0, a1 = 0.25 * L, 0.75 * L
+    pl = _PanelList()
+    for lo, hi in _face_grid(2, 0.0, (0, L), (0, L), n_xy, n_xy):
+        pl.rows.append((lo, hi, CONDUCTOR, 1, 0, -1))
+    for lo, hi in _face_grid(2, H, (0, L), (0, L), n_xy, n_xy):
+        pl.rows.append((lo, hi, CONDUCTOR, 0, -1, 1))
+    for lo, hi in _face_grid(2, d1, (0, L), (0, L), n_xy, n_xy):
+        cx, cy = 0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1])
+        below = 2 if (a0 < cx < a1 and a0 < cy < a1) else 0
+        pl.rows.append((lo, hi, INTERFACE, -1, 1, below))
+    nb = n_xy // 2                                   # block cells across
+    nbz = max(1, n_z // 2)
+    for lo, hi in _face_grid(2, zb, (a0, a1), (a0, a1), nb, nb):   # block bottom: region 0 below
+        pl.rows.append((lo, hi, INTERFACE, -1, 2, 0))
+    for nrm in (0, 1):
+        for plane, inside_plus in ((a0, True), (a1, False)):      # block sides
+            for lo, hi in _face_grid(nrm, plane, (a0, a1), (zb, d1), nb, nbz):
+                pl.rows.append((lo, hi, INTERFACE, -1, 2 if inside_plus else 0, 0 if inside_plus else 2))
+    for z0, z1, reg in ((0.0, d1, 0), (d1, H, 1)):
+        for nrm in (0, 1):
+            for plane, plus in ((0.0, True), (L, False)):
+                for lo, hi in _face_grid(nrm, plane, (0, L), (z0, z1), n_xy, n_z):
+                    pl.rows.append((lo, hi, NEUMANN, -1, reg if plus else -1, -1 if plus else reg))
+    return pl.mesh(f"two_slab_block_{n_xy}x{n_z}", eps_r, 2)

@@ -135,6 +135,21 @@ def test_layered_stack_vs_oracle(ctx):
     assert err <= C_TOL
 
 
+def test_three_region_triangle_vs_oracle(ctx):
+    """A third dielectric embedded under the interface of the two-slab
+    capacitor: every region borders both others, so the unknowns of one
+    region do not form one contiguous slot range (the blocked M^T M covers a
+    range with other regions' unknowns inside); 124 panels against the
+    oracle."""
+    m = gi.two_slab_with_block()
+    say(f"three regions: {m.name} n={m.n_panels}")
+    C, rep = ctx.extract_dielectric(*m.args())
+    ref = od.extract(*m.args(), single_layer=(3, 2.0))
+    err = float(np.abs(C - ref).max() / np.abs(ref).max())
+    say(f"  C vs oracle {err:.2e}, residual {rep['residual']:.1e}")
+    assert err <= C_TOL
+
+
 def test_layered_stack_properties_at_size(ctx):
     """Six wires, 4,368 panels: the mirror y -> W - y maps wire 0 to wire 2
     and each upper wire to itself, so C is invariant under that exchange;
