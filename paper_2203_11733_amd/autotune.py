@@ -120,7 +120,7 @@ def main(argv=None):
     props = torch.cuda.get_device_properties(0)
     out = {"device": f"{props.name} ({getattr(props, 'gcnArchName', 'gfx950')})",
            "written_by": "paper_2203_11733_amd/autotune.py",
-           "date": time.strftime("%Y-%m-%d"), "host": platform.node() or "gpu box",
+           "date": time.strftime("%Y-%m-%d"), "host": platform.node() or "unknown host",
            "entries": entries}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
