@@ -8,11 +8,13 @@ far field + FP16 trailing updates + FP64 refinement to 1e-6; the plain FP64
 path is timed over the same number of steps beside it, and both capacitance
 matrices are compared with the oracle's stored result for this layout.
 After the timed steps the seeded 256-job serving stream is replayed in the
-same mode and in FP64 (p50/p99 latency at 50 jobs/s, saturation jobs/s).
+same mode and in FP64 (p50/p99 latency at 50 jobs/s, saturation jobs/s), and
+the six-net multi-dielectric stack is extracted a few times.
 
 Prints one JSON line.  Options: --gpus N (only 1 is supported), --steps K,
 --warmup W, --mode mixed|f64, --layout three_layer_bus|crossing_bus|two_plates|small_job,
---no-f64, --no-cpu-baseline, --no-serving.
+--no-f64, --no-cpu-baseline, --no-serving, --no-dielectric, --graph; other
+workloads alone: --serving, --partition, --exact, --dielectric, --sweep.
 """
 from __future__ import annotations
 
@@ -488,6 +490,8 @@ def main():
                          "(ignored while the library's profiling events are on: use with --no-profile)")
     ap.add_argument("--dielectric", action="store_true",
                     help="multi-dielectric extraction of the six-net three-layer stack instead")
+    ap.add_argument("--no-dielectric", action="store_true",
+                    help="do not time the multi-dielectric stack after the headline steps")
     ap.add_argument("--dl-h", type=float, default=0.1,
                     help="conductor panel size of the --dielectric stack (interfaces and walls 2x)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -652,6 +656,14 @@ def main():
             sv = serving(sargs, binding, np)
             out["serving"].setdefault("workload", sv["config"]["workload"])
             out["serving"][smode] = {"dtype": sv["dtype"], "poisson": sv["poisson"], "saturation": sv["saturation"]}
+    if not args.no_dielectric:
+        # the multi-dielectric extraction (section 4) of the six-net stack,
+        # a few whole extractions in its own context
+        dargs = argparse.Namespace(**vars(args))
+        dargs.steps, dargs.warmup = 5, 1
+        dl = dielectric(dargs, binding, np)
+        out["dielectric"] = {k: dl[k] for k in ("metric", "value", "unit", "ms_per_extraction", "dtype", "stages_ms",
+                                                "residual", "refine_iters", "config")}
     if args.copy_calibration:
         # a plain copy kernel of known size: 256 MiB read + 256 MiB written per launch
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
