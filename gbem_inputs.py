@@ -2,8 +2,10 @@
 
 This module only describes geometry: lists of axis-aligned boxes with a conductor
 id each, plus the meshing rule to apply.  It holds none of the method's
-arithmetic (no meshing, no integrals, no solve); both the library and the oracle
-mesh these boxes with their own code.
+arithmetic (no integrals, no solve); both the library and the oracle mesh these
+boxes with their own code.  The multi-dielectric layouts at the end are given
+panel by panel instead (uniform grids on each face, with the kind and the
+regions on both sides), since that entry point takes panels.
 
 A box is ``(lo, hi, cond)`` with ``lo``/``hi`` 3-tuples in micrometres.
 ``cond`` is the conductor index 0..M-1, or -1 for a grounded boundary that is
@@ -372,3 +374,23 @@ def two_slab_with_block(L=1.0, d1=0.3, d2=0.7, n_xy=4, n_z=2, eps_r=(4.0, 1.0, 7
                 for lo, hi in _face_grid(nrm, plane, (0, L), (z0, z1), n_xy, n_z):
                     pl.rows.append((lo, hi, NEUMANN, -1, reg if plus else -1, -1 if plus else reg))
     return pl.mesh(f"two_slab_block_{n_xy}x{n_z}", eps_r, 2)
+
+
+def bars_in_grounded_box(h_bar=1.0, h_box=2.0, eps_r=1.0) -> DielectricMesh:
+    """One dielectric region: the paper's two crossing bars (section 5,
+    4 x 1 x 1 um at z 1-2 and 3-4) inside a grounded box of 8 x 8 x 5 um (the
+    paper's enclosure is 40 x 40 x 10; smaller here so the oracle stays fast),
+    bar faces split into cells of at most h_bar, box faces h_box."""
+    pl = _PanelList()
+    pl.box_surface((-2.0, -0.5, 1.0), (2.0, 0.5, 2.0), h_bar, CONDUCTOR, 0, 0, outside=True)
+    pl.box_surface((-0.5, -2.0, 3.0), (0.5, 2.0, 4.0), h_bar, CONDUCTOR, 1, 0, outside=True)
+    pl.box_surface((-4.0, -4.0, 0.0), (4.0, 4.0, 5.0), h_box, DIRICHLET, -1, 0, outside=False)
+    return pl.mesh(f"bars_in_grounded_box_{h_bar:g}_{h_box:g}", [eps_r], 2)
+
+
+def bars_in_grounded_box_layout(h: float = 1.0) -> Layout:
+    """The same geometry as boxes for the single-dielectric mesher (the
+    enclosure as a grounded box, conductor id -1)."""
+    boxes = [((-2.0, -0.5, 1.0), (2.0, 0.5, 2.0), 0), ((-0.5, -2.0, 3.0), (0.5, 2.0, 4.0), 1),
+             ((-4.0, -4.0, 0.0), (4.0, 4.0, 5.0), -1)]
+    return Layout("bars_in_grounded_box", boxes, 2, ("uniform", h), 1.0)
