@@ -394,3 +394,42 @@ def bars_in_grounded_box_layout(h: float = 1.0) -> Layout:
     boxes = [((-2.0, -0.5, 1.0), (2.0, 0.5, 2.0), 0), ((-0.5, -2.0, 3.0), (0.5, 2.0, 4.0), 1),
              ((-4.0, -4.0, 0.0), (4.0, 4.0, 5.0), -1)]
     return Layout("bars_in_grounded_box", boxes, 2, ("uniform", h), 1.0)
+
+
+@dataclass
+class DielectricLayout:
+    """A layered dielectric layout: conductor boxes (each inside one layer),
+    a box domain cut along z at z_layer, permittivity per layer, and the kind
+    of the domain's bottom, top and side faces."""
+    name: str
+    box_lo: list
+    box_hi: list
+    box_net: list
+    n_conductors: int
+    domain_lo: tuple
+    domain_hi: tuple
+    z_layer: list
+    eps_r: list
+    bottom_kind: int = DIRICHLET
+    top_kind: int = DIRICHLET
+    side_kind: int = NEUMANN
+    length_unit_m: float = MICRON
+
+
+def layered_stack_layout(n_wires: int = 3, eps_r=(3.9, 2.7, 4.2)) -> DielectricLayout:
+    """The geometry of layered_stack as a layout (for the per-main-net meshes
+    of the partition rules): grounded top and bottom, Neumann side walls."""
+    W = 2.0 + 1.0 * n_wires
+    lo, hi, net = [], [], []
+    for k in range(n_wires):
+        y0 = 1.3 + 1.0 * k
+        lo.append((0.6, y0, 1.35))
+        hi.append((W - 0.6, y0 + 0.4, 1.85))
+        net.append(k)
+    for k in range(n_wires):
+        x0 = 1.3 + 1.0 * k
+        lo.append((x0, 0.6, 2.6))
+        hi.append((x0 + 0.4, W - 0.6, 3.1))
+        net.append(n_wires + k)
+    return DielectricLayout(f"layered_stack_{2 * n_wires}nets", lo, hi, net, 2 * n_wires, (0.0, 0.0, 0.0),
+                            (W, W, 3.6), [0.0, 1.0, 2.2, 3.6], list(eps_r))

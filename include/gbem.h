@@ -370,6 +370,60 @@ typedef struct {
 gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *mesh, const gbem_opts *opts, double *C_out,
                                     gbem_report *rep);
 
+/* A layered dielectric layout: a box domain cut along z into n_layers
+ * dielectric layers (z_layer[0] = domain_lo[2] < ... < z_layer[n_layers] =
+ * domain_hi[2], permittivity eps_r[a] in layer a), conductor boxes each
+ * strictly inside one layer (net box_net[b] in [0, n_conductors)), the
+ * bottom, top and side faces of the domain GBEM_PANEL_DIRICHLET or
+ * GBEM_PANEL_NEUMANN (the paper's experiment with several dielectrics:
+ * grounded top and bottom, Neumann elsewhere). Host arrays. */
+typedef struct {
+    int32_t n_boxes;
+    const double *box_lo;       /* [3 * n_boxes] */
+    const double *box_hi;
+    const int32_t *box_net;     /* [n_boxes] */
+    int32_t n_conductors;
+    double domain_lo[3], domain_hi[3];
+    int32_t n_layers;
+    const double *z_layer;      /* [n_layers + 1] */
+    const double *eps_r;        /* [n_layers] */
+    int32_t bottom_kind, top_kind, side_kind;
+    double length_unit_m;
+} gbem_dlayout;
+
+/* Panels of a multi-dielectric mesh (malloc'ed; free with gbem_dmesh_buf_free). */
+typedef struct {
+    int32_t n_panels;
+    double *lo, *hi;            /* [3 * n_panels] */
+    int32_t *kind, *conductor, *region_plus, *region_minus;
+} gbem_dmesh_buf;
+void gbem_dmesh_buf_free(gbem_dmesh_buf *buf);
+
+/* Mesh of a layered layout for main net main_net by the paper's rules:
+ * conductor faces and the domain boundary by the section 3.3 rule (as
+ * gbem_mesh_partition: |I| <= p4 within p5 of the main net, p4 p3 (d/p5)^3
+ * beyond, p4 = p1 on faces that face the main net and on the domain
+ * boundary, p1 p2 on the others), the interfaces between layers by the
+ * section 4.1 rule, |I| <= p1 within p5 and p1 p3 (d/p5)^2 beyond (the
+ * printed length l read as p5, as in section 3.3). Panel order: conductor
+ * boxes (faces -x, +x, -y, +y, -z, +z), bottom, top, side walls layer by
+ * layer (-x, +x, -y, +y), interfaces bottom to top; each face by bisection
+ * of its longer side, lower half first. */
+gbem_status gbem_mesh_dielectric_partition(const gbem_dlayout *layout, int32_t main_net, const gbem_partition *rule,
+                                           gbem_dmesh_buf *out);
+
+/* Capacitance matrix of a layered layout with one mesh per main net (the
+ * paper's method for several dielectrics, section 4 with section 3.3):
+ * column k of C_out (row-major, C_out[n * n_conductors + k]) from the mesh of
+ * main net k by gbem_mesh_dielectric_partition, extracted by
+ * gbem_extract_dielectric; the n_conductors extractions run one after the
+ * other. panels_out (optional, host, n_conductors): panel count of mesh k.
+ * rep (optional): times and panels summed over the meshes, largest residual,
+ * asym of the assembled C. */
+gbem_status gbem_extract_dielectric_partitioned(gbem_ctx *ctx, const gbem_dlayout *layout, const gbem_partition *rule,
+                                                const gbem_opts *opts, double *C_out, int32_t *panels_out,
+                                                gbem_report *rep);
+
 /* ---- stage entry points (same kernels as gbem_extract; for parity tests) ---- */
 
 /* Near-pair list of the mesh (host arrays in/out): row_ptr[n+1], col[nnz] with

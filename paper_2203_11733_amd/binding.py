@@ -28,7 +28,8 @@ EXPORTS = [
     "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
     "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
     "gbem_extract_device_noalloc", "gbem_load_tuning", "gbem_set_tuning_override", "gbem_tuning_source",
-    "gbem_extract_dielectric", "gbem_assemble_double_layer",
+    "gbem_extract_dielectric", "gbem_assemble_double_layer", "gbem_mesh_dielectric_partition",
+    "gbem_dmesh_buf_free", "gbem_extract_dielectric_partitioned",
 ]
 # gbem_panel_kind
 CONDUCTOR, DIRICHLET, NEUMANN, INTERFACE = range(4)
@@ -51,6 +52,22 @@ class DMesh(ctypes.Structure):
                 ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("kind", ctypes.c_void_p),
                 ("conductor", ctypes.c_void_p), ("region_plus", ctypes.c_void_p),
                 ("region_minus", ctypes.c_void_p), ("eps_r", ctypes.c_void_p), ("length_unit_m", ctypes.c_double)]
+
+
+class DLayout(ctypes.Structure):
+    _fields_ = [("n_boxes", ctypes.c_int32), ("box_lo", ctypes.c_void_p), ("box_hi", ctypes.c_void_p),
+                ("box_net", ctypes.c_void_p), ("n_conductors", ctypes.c_int32),
+                ("domain_lo", ctypes.c_double * 3), ("domain_hi", ctypes.c_double * 3),
+                ("n_layers", ctypes.c_int32), ("z_layer", ctypes.c_void_p), ("eps_r", ctypes.c_void_p),
+                ("bottom_kind", ctypes.c_int32), ("top_kind", ctypes.c_int32), ("side_kind", ctypes.c_int32),
+                ("length_unit_m", ctypes.c_double)]
+
+
+class DMeshBuf(ctypes.Structure):
+    _fields_ = [("n_panels", ctypes.c_int32), ("lo", ctypes.POINTER(ctypes.c_double)),
+                ("hi", ctypes.POINTER(ctypes.c_double)), ("kind", ctypes.POINTER(ctypes.c_int32)),
+                ("conductor", ctypes.POINTER(ctypes.c_int32)), ("region_plus", ctypes.POINTER(ctypes.c_int32)),
+                ("region_minus", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Opts(ctypes.Structure):
@@ -179,12 +196,18 @@ def load():
     lib.gbem_extract_dielectric.argtypes = [_vp, ctypes.POINTER(DMesh), ctypes.POINTER(Opts), _vp,
                                             ctypes.POINTER(Report)]
     lib.gbem_assemble_double_layer.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_double, _vp]
+    lib.gbem_mesh_dielectric_partition.argtypes = [ctypes.POINTER(DLayout), ctypes.c_int32,
+                                                   ctypes.POINTER(Partition), ctypes.POINTER(DMeshBuf)]
+    lib.gbem_dmesh_buf_free.argtypes = [ctypes.POINTER(DMeshBuf)]
+    lib.gbem_extract_dielectric_partitioned.argtypes = [_vp, ctypes.POINTER(DLayout), ctypes.POINTER(Partition),
+                                                        ctypes.POINTER(Opts), _vp, _vp, ctypes.POINTER(Report)]
     for name in ("gbem_create", "gbem_destroy", "gbem_extract", "gbem_extract_device", "gbem_submit",
                  "gbem_poll", "gbem_wait", "gbem_server_stats", "gbem_mesh_boxes", "gbem_near_list",
                  "gbem_assemble", "gbem_assemble_sample", "gbem_assemble_scaled_sample", "gbem_cholesky_device",
                  "gbem_cholesky_solve_device", "gbem_mesh_partition", "gbem_extract_partitioned",
                  "gbem_extract_device_noalloc", "gbem_load_tuning", "gbem_set_tuning_override",
-                 "gbem_extract_dielectric", "gbem_assemble_double_layer"):
+                 "gbem_extract_dielectric", "gbem_assemble_double_layer", "gbem_mesh_dielectric_partition",
+                 "gbem_extract_dielectric_partitioned"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -270,6 +293,39 @@ def mesh_partition(box_lo, box_hi, box_cond, main_net, p1, p2, p3, p5):
     _check(lib.gbem_mesh_partition(_ptr(blo), _ptr(bhi), _ptr(bc), blo.shape[0], main_net, ctypes.byref(r),
                                    ctypes.byref(buf)))
     return _take_buf(lib, buf)
+
+
+def dlayout(layout):
+    """DLayout of a gbem_inputs.DielectricLayout and the arrays it points into."""
+    blo = np.ascontiguousarray(layout.box_lo, dtype=np.float64).reshape(-1, 3)
+    bhi = np.ascontiguousarray(layout.box_hi, dtype=np.float64).reshape(-1, 3)
+    bn = np.ascontiguousarray(layout.box_net, dtype=np.int32).reshape(-1)
+    z = np.ascontiguousarray(layout.z_layer, dtype=np.float64)
+    eps = np.ascontiguousarray(layout.eps_r, dtype=np.float64)
+    d = DLayout(blo.shape[0], blo.ctypes.data, bhi.ctypes.data, bn.ctypes.data, layout.n_conductors,
+                (ctypes.c_double * 3)(*layout.domain_lo), (ctypes.c_double * 3)(*layout.domain_hi),
+                eps.shape[0], z.ctypes.data, eps.ctypes.data, layout.bottom_kind, layout.top_kind,
+                layout.side_kind, layout.length_unit_m)
+    return d, (blo, bhi, bn, z, eps)
+
+
+def mesh_dielectric_partition(layout, main_net, p1, p2, p3, p5):
+    """Library mesher of a layered layout for one main net (sections 3.3 and
+    4.1): (lo, hi, kind, conductor, region_plus, region_minus)."""
+    lib = load()
+    d, keep = dlayout(layout)
+    buf = DMeshBuf()
+    _check(lib.gbem_mesh_dielectric_partition(ctypes.byref(d), main_net, ctypes.byref(Partition(p1, p2, p3, p5)),
+                                              ctypes.byref(buf)))
+    try:
+        n = buf.n_panels
+        lo = np.ctypeslib.as_array(buf.lo, shape=(n * 3,)).reshape(n, 3).copy()
+        hi = np.ctypeslib.as_array(buf.hi, shape=(n * 3,)).reshape(n, 3).copy()
+        ints = [np.ctypeslib.as_array(getattr(buf, f), shape=(n,)).copy()
+                for f in ("kind", "conductor", "region_plus", "region_minus")]
+    finally:
+        lib.gbem_dmesh_buf_free(ctypes.byref(buf))
+    return (lo, hi, *ints)
 
 
 class Context:
@@ -378,6 +434,20 @@ class Context:
         o = opts or make_opts()
         _check(self.lib.gbem_extract_dielectric(self.h, ctypes.byref(m), ctypes.byref(o), _ptr(C), ctypes.byref(rep)))
         return C, rep.as_dict()
+
+    def extract_dielectric_partitioned(self, layout, p1, p2, p3, p5, opts: Opts | None = None):
+        """One mesh per main net of a layered layout (gbem_extract_dielectric_partitioned).
+        Returns (C, panels per mesh, report)."""
+        d, keep = dlayout(layout)
+        m = layout.n_conductors
+        C = np.zeros((m, m))
+        panels = np.zeros(m, dtype=np.int32)
+        rep = Report()
+        o = opts or make_opts()
+        _check(self.lib.gbem_extract_dielectric_partitioned(self.h, ctypes.byref(d),
+                                                            ctypes.byref(Partition(p1, p2, p3, p5)),
+                                                            ctypes.byref(o), _ptr(C), _ptr(panels), ctypes.byref(rep)))
+        return C, panels, rep.as_dict()
 
     def assemble_double_layer(self, lo, hi, near_eta=2.0):
         """Q (n x n) of section 4.2 (gbem_assemble_double_layer)."""

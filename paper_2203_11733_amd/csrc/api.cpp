@@ -2042,3 +2042,54 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     }
     return GBEM_OK;
 }
+
+extern "C" gbem_status gbem_extract_dielectric_partitioned(gbem_ctx *ctx, const gbem_dlayout *L,
+                                                           const gbem_partition *rule, const gbem_opts *opts,
+                                                           double *C_out, int32_t *panels_out, gbem_report *rep)
+{
+    if (!L || !rule || !C_out || L->n_conductors <= 0 || L->n_conductors > kMaxRhs || !L->eps_r) {
+        set_error("gbem_extract_dielectric_partitioned: null argument or n_conductors outside 1..64");
+        return GBEM_EINVAL;
+    }
+    const int M = L->n_conductors;
+    std::vector<double> Ck((size_t)M * M);
+    gbem_report tot{};
+    for (int k = 0; k < M; ++k) {
+        gbem_dmesh_buf mb{};
+        gbem_status s = gbem_mesh_dielectric_partition(L, k, rule, &mb);
+        if (s != GBEM_OK) return s;
+        gbem_dmesh dm{};
+        dm.n_panels = mb.n_panels;
+        dm.n_conductors = M;
+        dm.n_regions = L->n_layers;
+        dm.lo = mb.lo;
+        dm.hi = mb.hi;
+        dm.kind = mb.kind;
+        dm.conductor = mb.conductor;
+        dm.region_plus = mb.region_plus;
+        dm.region_minus = mb.region_minus;
+        dm.eps_r = L->eps_r;
+        dm.length_unit_m = L->length_unit_m;
+        gbem_report r{};
+        s = gbem_extract_dielectric(ctx, &dm, opts, Ck.data(), &r);
+        const int32_t np = mb.n_panels;
+        gbem_dmesh_buf_free(&mb);
+        if (s != GBEM_OK) return s;
+        for (int n = 0; n < M; ++n) C_out[(size_t)n * M + k] = Ck[(size_t)n * M + k];
+        if (panels_out) panels_out[k] = np;
+        tot.t_assemble_ms += r.t_assemble_ms;
+        tot.t_factor_ms += r.t_factor_ms;
+        tot.t_solve_ms += r.t_solve_ms;
+        tot.t_total_ms += r.t_total_ms;
+        tot.residual = std::max(tot.residual, r.residual);
+        tot.refine_iters = std::max(tot.refine_iters, r.refine_iters);
+        tot.n_near += r.n_near;
+        tot.n_panels += r.n_panels;
+        tot.factor_used = r.factor_used;
+    }
+    if (rep) {
+        tot.asym = asym_of(C_out, M);
+        *rep = tot;
+    }
+    return GBEM_OK;
+}

@@ -128,7 +128,7 @@ static double net_dist2(const NetBoxes &net, const double *l, const double *h)
 }
 static bool partition_face(const NetBoxes &net, double p4, const gbem_partition &r, int nrm, double plane,
                            double a0, double a1, double b0, double b1, int32_t c, std::vector<double> &lo,
-                           std::vector<double> &hi, std::vector<int32_t> &cond, size_t max_total)
+                           std::vector<double> &hi, std::vector<int32_t> &cond, size_t max_total, int power = 3)
 {
     const int t1 = nrm == 0 ? 1 : 0, t2 = nrm == 2 ? 1 : 2;
     const double min1 = (a1 - a0) * 1e-12, min2 = (b1 - b0) * 1e-12;
@@ -147,8 +147,10 @@ static bool partition_face(const NetBoxes &net, double p4, const gbem_partition 
         const double d = sqrt(net_dist2(net, l, h));
         double bound = p4;
         if (d > r.p5) {
+            // power 3: conductors and outer boundary (section 3.3); power 2:
+            // dielectric interfaces (section 4.1)
             const double x = d / r.p5;
-            bound = p4 * r.p3 * (x * x * x);
+            bound = p4 * r.p3 * (power == 3 ? x * x * x : x * x);
         }
         const double w1 = q.a1 - q.a0, w2 = q.b1 - q.b0;
         if (w1 * w2 <= bound) {
@@ -343,5 +345,176 @@ extern "C" gbem_status gbem_mesh_partition(const double *box_lo, const double *b
     out->lo = plo;
     out->hi = phi;
     out->conductor = pc;
+    return GBEM_OK;
+}
+
+// ------------------------------------------------------------------------
+// Layered multi-dielectric layouts (section 4): per-main-net meshes
+// ------------------------------------------------------------------------
+extern "C" void gbem_dmesh_buf_free(gbem_dmesh_buf *buf)
+{
+    if (!buf) return;
+    free(buf->lo);
+    free(buf->hi);
+    free(buf->kind);
+    free(buf->conductor);
+    free(buf->region_plus);
+    free(buf->region_minus);
+    memset(buf, 0, sizeof(*buf));
+}
+
+extern "C" gbem_status gbem_mesh_dielectric_partition(const gbem_dlayout *L, int32_t main_net,
+                                                      const gbem_partition *rule, gbem_dmesh_buf *out)
+{
+    if (!L || !rule || !out || !L->box_lo || !L->box_hi || !L->box_net || !L->z_layer || L->n_boxes <= 0 ||
+        L->n_layers <= 0 || L->n_conductors <= 0) {
+        set_error("gbem_mesh_dielectric_partition: null argument, no boxes or no layers");
+        return GBEM_EINVAL;
+    }
+    if (!(rule->p1 > 0.0) || !(rule->p2 >= 1.0) || !(rule->p3 > 0.0) || !(rule->p5 > 0.0) ||
+        !isfinite(rule->p1) || !isfinite(rule->p2) || !isfinite(rule->p3) || !isfinite(rule->p5)) {
+        set_error("gbem_mesh_dielectric_partition: need p1 > 0, p2 >= 1, p3 > 0, p5 > 0 (finite)");
+        return GBEM_EINVAL;
+    }
+    const int nb = L->n_boxes, nl = L->n_layers;
+    const double *dlo = L->domain_lo, *dhi = L->domain_hi, *z = L->z_layer;
+    for (int k = 0; k < 3; ++k)
+        if (!(dlo[k] < dhi[k])) {
+            set_error("gbem_mesh_dielectric_partition: empty domain");
+            return GBEM_EINVAL;
+        }
+    if (z[0] != dlo[2] || z[nl] != dhi[2]) {
+        set_error("gbem_mesh_dielectric_partition: z_layer must run from domain_lo[2] to domain_hi[2]");
+        return GBEM_EINVAL;
+    }
+    for (int a = 0; a < nl; ++a)
+        if (!(z[a] < z[a + 1])) {
+            set_error("gbem_mesh_dielectric_partition: z_layer must increase");
+            return GBEM_EINVAL;
+        }
+    for (int kd : {L->bottom_kind, L->top_kind, L->side_kind})
+        if (kd != GBEM_PANEL_DIRICHLET && kd != GBEM_PANEL_NEUMANN) {
+            set_error("gbem_mesh_dielectric_partition: outer faces must be GBEM_PANEL_DIRICHLET or GBEM_PANEL_NEUMANN");
+            return GBEM_EINVAL;
+        }
+    std::string why;
+    if (!boxes_ok(L->box_lo, L->box_hi, nb, why)) {
+        set_error("gbem_mesh_dielectric_partition: " + why);
+        return GBEM_EINVAL;
+    }
+    // layer of each box: strictly inside one layer and inside the domain
+    std::vector<int> layer(nb, -1);
+    for (int b = 0; b < nb; ++b) {
+        const double *bl = L->box_lo + 3 * b, *bh = L->box_hi + 3 * b;
+        bool inside = L->box_net[b] >= 0 && L->box_net[b] < L->n_conductors;
+        for (int k = 0; k < 3; ++k) inside = inside && dlo[k] < bl[k] && bh[k] < dhi[k];
+        for (int a = 0; a < nl && inside; ++a)
+            if (z[a] < bl[2] && bh[2] < z[a + 1]) layer[b] = a;
+        if (layer[b] < 0) {
+            set_error("gbem_mesh_dielectric_partition: box " + std::to_string(b) +
+                      " is not strictly inside one layer of the domain, or its net is out of range");
+            return GBEM_EINVAL;
+        }
+    }
+    NetBoxes net;
+    for (int b = 0; b < nb; ++b)
+        if (L->box_net[b] == main_net)
+            for (int k = 0; k < 3; ++k) {
+                net.lo.push_back(L->box_lo[3 * b + k]);
+                net.hi.push_back(L->box_hi[3 * b + k]);
+            }
+    if (net.lo.empty()) {
+        set_error("gbem_mesh_dielectric_partition: no box belongs to the main net");
+        return GBEM_EINVAL;
+    }
+    const size_t max_total = (size_t)INT32_MAX / 4;
+    std::vector<double> lo, hi;
+    std::vector<int32_t> cond, kind, rp, rm;
+    // append the panels a face produced since `from`, with their kind and regions
+    auto tag = [&](size_t from, int32_t kd, int32_t plus, int32_t minus) {
+        for (size_t i = from; i < cond.size(); ++i) {
+            kind.push_back(kd);
+            rp.push_back(plus);
+            rm.push_back(minus);
+        }
+    };
+    auto fail = [&]() {
+        set_error("gbem_mesh_dielectric_partition: the rule asks for too many or too small panels");
+        return GBEM_EINVAL;
+    };
+    // conductor faces: the section 3.3 rule, facing / back as for boxes
+    for (int b = 0; b < nb; ++b) {
+        const double *bl = L->box_lo + 3 * b, *bh = L->box_hi + 3 * b;
+        for (int f = 0; f < 6; ++f) {
+            const int nrm = f / 2;
+            const bool upper = f & 1;
+            const double plane = upper ? bh[nrm] : bl[nrm];
+            bool facing = L->box_net[b] == main_net;
+            for (size_t q = 0; q < net.lo.size() / 3 && !facing; ++q)
+                facing = upper ? net.hi[3 * q + nrm] > plane : net.lo[3 * q + nrm] < plane;
+            const double p4 = facing ? rule->p1 : rule->p1 * rule->p2;
+            const int t1 = nrm == 0 ? 1 : 0, t2 = nrm == 2 ? 1 : 2;
+            const size_t from = cond.size();
+            if (!partition_face(net, p4, *rule, nrm, plane, bl[t1], bh[t1], bl[t2], bh[t2], L->box_net[b], lo, hi,
+                                cond, max_total))
+                return fail();
+            // the dielectric lies outside the box: on the - side of a lower face
+            tag(from, GBEM_PANEL_CONDUCTOR, upper ? layer[b] : -1, upper ? -1 : layer[b]);
+        }
+    }
+    // outer boundary (section 3.3 rule; it encloses the main net, so every
+    // face counts as facing): bottom, top, and the side walls per layer
+    {
+        size_t from = cond.size();
+        if (!partition_face(net, rule->p1, *rule, 2, dlo[2], dlo[0], dhi[0], dlo[1], dhi[1], -1, lo, hi, cond,
+                            max_total))
+            return fail();
+        tag(from, L->bottom_kind, 0, -1);
+        from = cond.size();
+        if (!partition_face(net, rule->p1, *rule, 2, dhi[2], dlo[0], dhi[0], dlo[1], dhi[1], -1, lo, hi, cond,
+                            max_total))
+            return fail();
+        tag(from, L->top_kind, -1, nl - 1);
+        for (int a = 0; a < nl; ++a)
+            for (int nrm = 0; nrm < 2; ++nrm)
+                for (int upper = 0; upper < 2; ++upper) {
+                    const int t = 1 - nrm;   // the other horizontal axis (in-plane axes t < 2)
+                    from = cond.size();
+                    const double plane = upper ? dhi[nrm] : dlo[nrm];
+                    if (!partition_face(net, rule->p1, *rule, nrm, plane, dlo[t], dhi[t], z[a], z[a + 1], -1, lo, hi,
+                                        cond, max_total))
+                        return fail();
+                    tag(from, L->side_kind, upper ? -1 : a, upper ? a : -1);
+                }
+    }
+    // interfaces between layers: the section 4.1 rule (growth with d^2)
+    for (int a = 1; a < nl; ++a) {
+        const size_t from = cond.size();
+        if (!partition_face(net, rule->p1, *rule, 2, z[a], dlo[0], dhi[0], dlo[1], dhi[1], -1, lo, hi, cond,
+                            max_total, 2))
+            return fail();
+        tag(from, GBEM_PANEL_INTERFACE, a, a - 1);
+    }
+    const size_t n = cond.size();
+    gbem_dmesh_buf r{};
+    r.lo = (double *)malloc(sizeof(double) * 3 * n);
+    r.hi = (double *)malloc(sizeof(double) * 3 * n);
+    r.kind = (int32_t *)malloc(sizeof(int32_t) * n);
+    r.conductor = (int32_t *)malloc(sizeof(int32_t) * n);
+    r.region_plus = (int32_t *)malloc(sizeof(int32_t) * n);
+    r.region_minus = (int32_t *)malloc(sizeof(int32_t) * n);
+    if (!r.lo || !r.hi || !r.kind || !r.conductor || !r.region_plus || !r.region_minus) {
+        gbem_dmesh_buf_free(&r);
+        set_error("gbem_mesh_dielectric_partition: host allocation failed");
+        return GBEM_ENOMEM;
+    }
+    memcpy(r.lo, lo.data(), sizeof(double) * 3 * n);
+    memcpy(r.hi, hi.data(), sizeof(double) * 3 * n);
+    memcpy(r.kind, kind.data(), sizeof(int32_t) * n);
+    memcpy(r.conductor, cond.data(), sizeof(int32_t) * n);
+    memcpy(r.region_plus, rp.data(), sizeof(int32_t) * n);
+    memcpy(r.region_minus, rm.data(), sizeof(int32_t) * n);
+    r.n_panels = (int32_t)n;
+    *out = r;
     return GBEM_OK;
 }

@@ -1,0 +1,96 @@
+"""Per-main-net meshes of layered multi-dielectric layouts (sections 3.3 and
+4.1): the library's mesher against the oracle's, byte for byte, and
+properties of the meshes that do not re-type the rule: every face of the
+layout is tiled exactly, every region's boundary is closed with consistent
+orientation, pieces near the main net are no larger than p1, and interface
+pieces grow more slowly with distance than conductor and boundary pieces."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import gbem_inputs as gi  # noqa: E402
+from oracle import dielectric_partition as odp  # noqa: E402
+from paper_2203_11733_amd import binding  # noqa: E402
+
+RULES = [(0.04, 4.0, 0.5, 0.5), (0.25, 2.0, 1.0, 0.5), (0.1, 4.0, 0.25, 1.0)]
+
+
+def _areas(lo, hi):
+    e = hi - lo
+    return np.prod(np.where(e == 0, 1.0, e), axis=1)
+
+
+@pytest.mark.parametrize("n_wires", [1, 3])
+@pytest.mark.parametrize("rule", RULES)
+def test_library_mesher_equals_oracle(n_wires, rule):
+    lay = gi.layered_stack_layout(n_wires)
+    for net in range(lay.n_conductors):
+        a = binding.mesh_dielectric_partition(lay, net, *rule)
+        b = odp.mesh(lay, net, *rule)
+        for x, y in zip(a, b):
+            assert x.shape == y.shape and np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_faces_tiled_and_regions_closed(rule):
+    """Per kind, the pieces add up to the layout's surfaces; each region's
+    boundary, with its outward normals, sums to the zero vector (a closed
+    surface), so every piece carries the right regions on the right sides."""
+    lay = gi.layered_stack_layout(3)
+    lo, hi, kind, cond, rp, rm = binding.mesh_dielectric_partition(lay, 2, *rule)
+    area = _areas(lo, hi)
+    W = lay.domain_hi[0] - lay.domain_lo[0]
+    H = lay.domain_hi[2] - lay.domain_lo[2]
+    box_area = sum(2 * ((h[0] - l[0]) * (h[1] - l[1]) + (h[0] - l[0]) * (h[2] - l[2]) + (h[1] - l[1]) * (h[2] - l[2]))
+                   for l, h in zip(np.array(lay.box_lo), np.array(lay.box_hi)))
+    assert math.isclose(area[kind == gi.CONDUCTOR].sum(), box_area, rel_tol=1e-13)
+    assert math.isclose(area[kind == gi.DIRICHLET].sum(), 2 * W * W, rel_tol=1e-13)
+    assert math.isclose(area[kind == gi.NEUMANN].sum(), 4 * W * H, rel_tol=1e-13)
+    assert math.isclose(area[kind == gi.INTERFACE].sum(), (len(lay.z_layer) - 2) * W * W, rel_tol=1e-13)
+    nrm = np.argmax(hi - lo == 0, axis=1)
+    for a in range(len(lay.eps_r)):
+        v = np.zeros(3)
+        for i in np.flatnonzero((rp == a) | (rm == a)):
+            v[nrm[i]] += (-1.0 if rp[i] == a else 1.0) * area[i]   # outward normal of region a
+        assert np.abs(v).max() <= 1e-12 * W * W
+    # conductor pieces carry their box's net
+    for b, (l, h) in enumerate(zip(lay.box_lo, lay.box_hi)):
+        on = np.all((lo >= np.array(l) - 1e-15) & (hi <= np.array(h) + 1e-15), axis=1) & (kind == gi.CONDUCTOR)
+        assert np.all(cond[on] == lay.box_net[b]) and on.any()
+
+
+def test_refinement_near_and_far():
+    """Within p5 of the main net no piece exceeds p1; far from it, interface
+    pieces stay smaller than outer-boundary pieces at the same distance (d^2
+    against d^3 growth), and the main net's own faces are the finest."""
+    p1, p2, p3, p5 = 0.04, 4.0, 0.5, 0.5
+    lay = gi.layered_stack_layout(3)
+    lo, hi, kind, cond, rp, rm = binding.mesh_dielectric_partition(lay, 0, p1, p2, p3, p5)
+    area = _areas(lo, hi)
+    net_lo, net_hi = np.array(lay.box_lo[0]), np.array(lay.box_hi[0])
+    gap = np.maximum(0.0, np.maximum(net_lo - hi, lo - net_hi))
+    d = np.sqrt((gap ** 2).sum(1))
+    assert area[d <= p5].max() <= p1 * (1 + 1e-12)
+    assert area[(kind == gi.CONDUCTOR) & (cond == 0)].max() <= p1 * (1 + 1e-12)
+    far = d > 4 * p5
+    inter = area[far & (kind == gi.INTERFACE)]
+    outer = area[far & (kind == gi.DIRICHLET)]
+    assert inter.size and outer.size and inter.max() < outer.max()
+    assert len(lo) < len(gi.layered_stack(3, math.sqrt(p1)).lo)
+
+
+def test_mesher_refuses_bad_layouts():
+    lay = gi.layered_stack_layout(1)
+    bad = gi.DielectricLayout(**{**lay.__dict__, "box_lo": [(0.6, 1.3, 0.8)] + lay.box_lo[1:]})   # crosses z = 1
+    with pytest.raises(binding.GbemError, match="strictly inside one layer"):
+        binding.mesh_dielectric_partition(bad, 0, 0.1, 2.0, 1.0, 0.5)
+    with pytest.raises(binding.GbemError, match="no box belongs to the main net"):
+        binding.mesh_dielectric_partition(lay, 5, 0.1, 2.0, 1.0, 0.5)
+    with pytest.raises(binding.GbemError, match="p1 > 0"):
+        binding.mesh_dielectric_partition(lay, 0, 0.0, 2.0, 1.0, 0.5)
