@@ -345,6 +345,9 @@ def test_capacitance_mixed_vs_oracle(ctx, factor):
         f"factor_used {rep['factor_used']}")
     assert rel_err(C, Co) < 1e-3
     assert rep["residual"] <= 1e-8
+    # regression guard: the FP32 far field and refinement to a 1e-8 residual
+    # leave about 1e-8 (observed 9e-9); two decades of margin
+    assert rel_err(C, Co) < 1e-6
 
 
 def test_tile_shapes_same_capacitance(ctx):
@@ -476,6 +479,7 @@ def test_padding_edges_vs_oracle(ctx, extra):
     say(f"  f64 {e64:.3e} mixed {em:.3e} (refinement sweeps {rm['refine_iters']})")
     assert e64 < 1e-10
     assert em < 1e-3
+    assert em < 1e-4   # regression guard: 100x the refinement tolerance (observed 3e-8 and below)
 
 
 def test_single_panel_plate(ctx):
@@ -557,6 +561,7 @@ def test_full_size_crossing_bus_capacitance(ctx):
     say(f"  vs oracle: f64 {e64:.3e}, mixed {em:.3e}")
     assert e64 < 1e-10
     assert em < 1e-3
+    assert em < 1e-4   # regression guard: 100x the refinement tolerance (observed 3e-8 and below)
 
 
 def test_full_size_three_layer_bus_capacitance(ctx):
