@@ -265,9 +265,20 @@ struct Workspace {
         return hipGraphLaunch(slot->exec, st);
     }
 
+    // buffers of the multi-dielectric entries (kept between calls like the
+    // rest of the context's workspace)
+    struct DlBufs {
+        DevBuf tab, epsb, Q, M, Mt, B, Bn, Z, N, X, R, D, C, nrm, part;
+        void release()
+        {
+            for (DevBuf *b : {&tab, &epsb, &Q, &M, &Mt, &B, &Bn, &Z, &N, &X, &R, &D, &C, &nrm, &part}) b->release();
+        }
+    } dl;
+
     ~Workspace()
     {
         for (auto &x : gexec) (void)hipGraphExecDestroy(x.exec);
+        dl.release();
         release_all();
         if (events_ok) {
             for (auto &e : ev) (void)hipEventDestroy(e);
@@ -1681,11 +1692,6 @@ extern "C" gbem_status gbem_extract_partitioned(gbem_ctx *ctx, const double *box
 // ------------------------------------------------------------------------
 // Multi-dielectric case (section 4)
 // ------------------------------------------------------------------------
-namespace {
-struct LocalBuf : DevBuf {
-    ~LocalBuf() { release(); }
-};
-}  // namespace
 
 // Panel table, near list (near_eta) and the double-layer matrix Q (n x n,
 // column-major, ldq = n) of the mesh in ws.lo / ws.hi with conductor ids in
@@ -1755,7 +1761,7 @@ extern "C" gbem_status gbem_assemble_double_layer(gbem_ctx *ctx, int32_t n_panel
     HIPCHK(hipMemcpyAsync(ws.lo.p, lo, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
     HIPCHK(hipMemcpyAsync(ws.hi.p, hi, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st), "H2D");
     HIPCHK(hipMemsetAsync(ws.cond.p, 0xff, sizeof(int32_t) * n, st), "memset");   // -1: no conductor
-    LocalBuf Q;
+    DevBuf &Q = ws.dl.Q;
     int64_t nnz = 0;
     gbem_status s = dl_assemble(ctx, n, 0, near_eta, 3, false, Q, &nnz, st);
     if (s != GBEM_OK) return s;
@@ -1885,7 +1891,9 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     HIPCHK(hipMemcpyAsync(ws.cond.p, cond.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st), "H2D");
     // per-panel and per-equation tables and the conductor panels of each net
     // (CSR over nets) in one device block of int32
-    LocalBuf tab, epsb, Q, Mb, Mt, Bb, Bn, Z, N, X, Rr, D, Cd, nrm, part;
+    Workspace::DlBufs &db = ws.dl;
+    DevBuf &tab = db.tab, &epsb = db.epsb, &Q = db.Q, &Mb = db.M, &Mt = db.Mt, &Bb = db.B, &Bn = db.Bn, &Z = db.Z,
+           &N = db.N, &X = db.X, &Rr = db.R, &D = db.D, &Cd = db.C, &nrm = db.nrm, &part = db.part;
     std::vector<int32_t> cp_ptr(M + 1, 0), cp_idx;
     for (int i = 0; i < n; ++i)
         if (cond[i] >= 0) ++cp_ptr[cond[i] + 1];
