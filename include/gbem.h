@@ -416,8 +416,10 @@ gbem_status gbem_mesh_dielectric_partition(const gbem_dlayout *layout, int32_t m
  * paper's method for several dielectrics, section 4 with section 3.3):
  * column k of C_out (row-major, C_out[n * n_conductors + k]) from the mesh of
  * main net k by gbem_mesh_dielectric_partition, extracted by
- * gbem_extract_dielectric; the n_conductors extractions run one after the
- * other. panels_out (optional, host, n_conductors): panel count of mesh k.
+ * gbem_extract_dielectric; the n_conductors extractions run on up to four
+ * lanes at once (a workspace and a stream each, kept by the context), each
+ * column from one lane's kernels, so C equals that of the extractions run one
+ * by one. panels_out (optional, host, n_conductors): panel count of mesh k.
  * rep (optional): times and panels summed over the meshes, largest residual,
  * asym of the assembled C. */
 gbem_status gbem_extract_dielectric_partitioned(gbem_ctx *ctx, const gbem_dlayout *layout, const gbem_partition *rule,

@@ -13,6 +13,7 @@
 #include <deque>
 #include <mutex>
 #include <string>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -871,6 +872,11 @@ struct gbem_ctx {
     size_t reserved = 0, peak = 0;
     size_t peak_held = 0;   // largest sum of the workspaces' real sizes seen at a job's end
     int64_t done = 0;
+
+    // lanes of gbem_extract_dielectric_partitioned: a workspace and a stream
+    // each, created on first use (under call_mu)
+    std::vector<std::unique_ptr<Workspace>> lane_ws;
+    std::vector<hipStream_t> lane_st;
 };
 
 static constexpr int kWorkers = 4;
@@ -1142,6 +1148,11 @@ extern "C" gbem_status gbem_destroy(gbem_ctx *ctx)
             delete w;
         }
     }
+    for (hipStream_t st : ctx->lane_st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    ctx->lane_ws.clear();
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1697,10 +1708,9 @@ extern "C" gbem_status gbem_extract_partitioned(gbem_ctx *ctx, const double *box
 // column-major, ldq = n) of the mesh in ws.lo / ws.hi with conductor ids in
 // ws.cond; optionally the single-layer matrix A (FP64 far rule of order p)
 // in ws.A (npad x npad).  Returns the near-pair count in *nnz.
-static gbem_status dl_assemble(gbem_ctx *ctx, int n, int n_cond, double near_eta, int p, bool with_A, DevBuf &Q,
+static gbem_status dl_assemble(Workspace &ws, int n, int n_cond, double near_eta, int p, bool with_A, DevBuf &Q,
                                int64_t *nnz, hipStream_t st)
 {
-    Workspace &ws = ctx->ws;
     const int64_t npad = round_up(n, kPad);
     HIPCHK(ws.pan.ensure(sizeof(Panel) * n), "alloc panels");
     HIPCHK(ws.flags.ensure(64), "alloc flags");
@@ -1763,7 +1773,7 @@ extern "C" gbem_status gbem_assemble_double_layer(gbem_ctx *ctx, int32_t n_panel
     HIPCHK(hipMemsetAsync(ws.cond.p, 0xff, sizeof(int32_t) * n, st), "memset");   // -1: no conductor
     DevBuf &Q = ws.dl.Q;
     int64_t nnz = 0;
-    gbem_status s = dl_assemble(ctx, n, 0, near_eta, 3, false, Q, &nnz, st);
+    gbem_status s = dl_assemble(ws, n, 0, near_eta, 3, false, Q, &nnz, st);
     if (s != GBEM_OK) return s;
     std::vector<double> tmp((size_t)n * n);
     HIPCHK(hipMemcpyAsync(tmp.data(), Q.p, sizeof(double) * n * n, hipMemcpyDeviceToHost, st), "D2H");
@@ -1773,8 +1783,15 @@ extern "C" gbem_status gbem_assemble_double_layer(gbem_ctx *ctx, int32_t n_panel
     return GBEM_OK;
 }
 
-extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *mesh, const gbem_opts *opts,
-                                               double *C_out, gbem_report *rep)
+// The extraction on the context's workspace and stream (lane == nullptr, the
+// synchronous entry: serialised by call_mu) or on a lane's own workspace and
+// stream (the caller holds call_mu and has made the device current).
+struct Lane {
+    Workspace *ws;
+    hipStream_t st;
+};
+static gbem_status dielectric_run(gbem_ctx *ctx, const Lane *lane, const gbem_dmesh *mesh, const gbem_opts *opts,
+                                  double *C_out, gbem_report *rep)
 {
     const auto t_start = std::chrono::steady_clock::now();
     if (!mesh || !C_out || !mesh->lo || !mesh->hi || !mesh->kind || !mesh->conductor || !mesh->region_plus ||
@@ -1879,10 +1896,13 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
         set_error("gbem_extract_dielectric: no context");
         return GBEM_EINVAL;
     }
-    std::lock_guard<std::mutex> lk(ctx->call_mu);
-    HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
-    Workspace &ws = ctx->ws;
-    hipStream_t st = ctx->stream;
+    std::unique_lock<std::mutex> lk;
+    if (!lane) {
+        lk = std::unique_lock<std::mutex>(ctx->call_mu);
+        HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+    }
+    Workspace &ws = lane ? *lane->ws : ctx->ws;
+    hipStream_t st = lane ? lane->st : ctx->stream;
     HIPCHK(ws.lo.ensure(sizeof(double) * 3 * n), "alloc mesh");
     HIPCHK(ws.hi.ensure(sizeof(double) * 3 * n), "alloc mesh");
     HIPCHK(ws.cond.ensure(sizeof(int32_t) * n), "alloc mesh");
@@ -1928,7 +1948,7 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
                   *d_us = d_kind + 4 * n, *d_qs = d_kind + 5 * n, *d_er = d_kind + 6 * (size_t)n,
                   *d_ep = d_er + nrow, *d_cpp = d_ep + nrow, *d_cpi = d_cpp + M + 1;
     int64_t nnz = 0;
-    gbem_status s = dl_assemble(ctx, n, M, o.near_eta, o.far_order, true, Q, &nnz, st);
+    gbem_status s = dl_assemble(ws, n, M, o.near_eta, o.far_order, true, Q, &nnz, st);
     if (s != GBEM_OK) return s;
     const int64_t npadA = round_up(n, kPad), npad = round_up(std::max(nu, nrow), kPad);
     const auto t_asm = std::chrono::steady_clock::now();
@@ -1973,8 +1993,12 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     HIPCHK(ws.Pw.ensure(chol_panel_bytes(GBEM_F64, npad)), "alloc panel");
     HIPCHK(ws.P16.ensure(std::max<size_t>(chol_panel16_bytes(GBEM_F64, npad), 64)), "alloc panel16");
     HIPCHK(hipMemsetAsync(ws.flags.p, 0, 64, st), "memset");
-    HIPCHK(ws.ensure_side(), "side stream");
-    HIPCHK(chol_factor(GBEM_F64, npad, N.p, npad, ws.Winv.p, ws.Pw.p, ws.P16.p, ws.flags.as<int32_t>() + 1, st, ws.side,
+    hipStream_t la = st;
+    if (!ws.lookahead_on_main) {
+        HIPCHK(ws.ensure_side(), "side stream");
+        la = ws.side;
+    }
+    HIPCHK(chol_factor(GBEM_F64, npad, N.p, npad, ws.Winv.p, ws.Pw.p, ws.P16.p, ws.flags.as<int32_t>() + 1, st, la,
                        ws.fev), "cholesky");
     int32_t ie[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(ie, ws.flags.as<int32_t>() + 1, 8, hipMemcpyDeviceToHost, st), "D2H");
@@ -2051,6 +2075,18 @@ extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *
     return GBEM_OK;
 }
 
+extern "C" gbem_status gbem_extract_dielectric(gbem_ctx *ctx, const gbem_dmesh *mesh, const gbem_opts *opts,
+                                               double *C_out, gbem_report *rep)
+{
+    return dielectric_run(ctx, nullptr, mesh, opts, C_out, rep);
+}
+
+// Column k of C from the mesh of main net k.  The meshes are built on the
+// host first; the extractions then run on up to four lanes (host threads,
+// each with a workspace and a stream of its own and the factorisation's
+// look-ahead on that stream, so the context holds at most four streams
+// besides its own), net k on lane k mod lanes.  Each column comes from one
+// lane's kernels alone, so the result does not depend on the lane count.
 extern "C" gbem_status gbem_extract_dielectric_partitioned(gbem_ctx *ctx, const gbem_dlayout *L,
                                                            const gbem_partition *rule, const gbem_opts *opts,
                                                            double *C_out, int32_t *panels_out, gbem_report *rep)
@@ -2060,31 +2096,88 @@ extern "C" gbem_status gbem_extract_dielectric_partitioned(gbem_ctx *ctx, const 
         return GBEM_EINVAL;
     }
     const int M = L->n_conductors;
-    std::vector<double> Ck((size_t)M * M);
+    std::vector<gbem_dmesh_buf> meshes(M);
+    auto free_meshes = [&]() {
+        for (auto &mb : meshes) gbem_dmesh_buf_free(&mb);
+    };
+    for (int k = 0; k < M; ++k) {
+        const gbem_status s = gbem_mesh_dielectric_partition(L, k, rule, &meshes[k]);
+        if (s != GBEM_OK) {
+            free_meshes();
+            return s;
+        }
+    }
+    if (!ctx) {
+        free_meshes();
+        set_error("gbem_extract_dielectric_partitioned: no context");
+        return GBEM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    const int lanes = std::min(M, 4);
+    {
+        hipError_t e = hipSetDevice(ctx->device);
+        while (e == hipSuccess && (int)ctx->lane_ws.size() < lanes) {
+            hipStream_t st = nullptr;
+            e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e != hipSuccess) break;
+            ctx->lane_st.push_back(st);
+            ctx->lane_ws.emplace_back(new Workspace());
+            ctx->lane_ws.back()->lookahead_on_main = true;
+        }
+        if (e != hipSuccess) {
+            free_meshes();
+            set_error(std::string("gbem_extract_dielectric_partitioned: ") + hipGetErrorString(e));
+            return GBEM_EDEVICE;
+        }
+    }
+    std::vector<std::vector<double>> Ck(M, std::vector<double>((size_t)M * M));
+    std::vector<gbem_report> reps(M);
+    std::vector<gbem_status> stat(M, GBEM_OK);
+    std::vector<std::string> errs(M);
+    auto lane_main = [&](int l) {
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            for (int k = l; k < M; k += lanes) {
+                stat[k] = GBEM_EDEVICE;
+                errs[k] = "hipSetDevice failed on a lane";
+            }
+            return;
+        }
+        const Lane lane{ctx->lane_ws[l].get(), ctx->lane_st[l]};
+        for (int k = l; k < M; k += lanes) {
+            const gbem_dmesh_buf &mb = meshes[k];
+            gbem_dmesh dm{};
+            dm.n_panels = mb.n_panels;
+            dm.n_conductors = M;
+            dm.n_regions = L->n_layers;
+            dm.lo = mb.lo;
+            dm.hi = mb.hi;
+            dm.kind = mb.kind;
+            dm.conductor = mb.conductor;
+            dm.region_plus = mb.region_plus;
+            dm.region_minus = mb.region_minus;
+            dm.eps_r = L->eps_r;
+            dm.length_unit_m = L->length_unit_m;
+            stat[k] = dielectric_run(ctx, &lane, &dm, opts, Ck[k].data(), &reps[k]);
+            if (stat[k] != GBEM_OK) {
+                errs[k] = gbem_last_error();   // the lane thread's message
+                return;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int l = 1; l < lanes; ++l) th.emplace_back(lane_main, l);
+    lane_main(0);
+    for (auto &t : th) t.join();
     gbem_report tot{};
     for (int k = 0; k < M; ++k) {
-        gbem_dmesh_buf mb{};
-        gbem_status s = gbem_mesh_dielectric_partition(L, k, rule, &mb);
-        if (s != GBEM_OK) return s;
-        gbem_dmesh dm{};
-        dm.n_panels = mb.n_panels;
-        dm.n_conductors = M;
-        dm.n_regions = L->n_layers;
-        dm.lo = mb.lo;
-        dm.hi = mb.hi;
-        dm.kind = mb.kind;
-        dm.conductor = mb.conductor;
-        dm.region_plus = mb.region_plus;
-        dm.region_minus = mb.region_minus;
-        dm.eps_r = L->eps_r;
-        dm.length_unit_m = L->length_unit_m;
-        gbem_report r{};
-        s = gbem_extract_dielectric(ctx, &dm, opts, Ck.data(), &r);
-        const int32_t np = mb.n_panels;
-        gbem_dmesh_buf_free(&mb);
-        if (s != GBEM_OK) return s;
-        for (int n = 0; n < M; ++n) C_out[(size_t)n * M + k] = Ck[(size_t)n * M + k];
-        if (panels_out) panels_out[k] = np;
+        if (stat[k] != GBEM_OK) {
+            free_meshes();
+            set_error(errs[k]);
+            return stat[k];
+        }
+        for (int n = 0; n < M; ++n) C_out[(size_t)n * M + k] = Ck[k][(size_t)n * M + k];
+        if (panels_out) panels_out[k] = meshes[k].n_panels;
+        const gbem_report &r = reps[k];
         tot.t_assemble_ms += r.t_assemble_ms;
         tot.t_factor_ms += r.t_factor_ms;
         tot.t_solve_ms += r.t_solve_ms;
@@ -2095,6 +2188,7 @@ extern "C" gbem_status gbem_extract_dielectric_partitioned(gbem_ctx *ctx, const 
         tot.n_panels += r.n_panels;
         tot.factor_used = r.factor_used;
     }
+    free_meshes();
     if (rep) {
         tot.asym = asym_of(C_out, M);
         *rep = tot;

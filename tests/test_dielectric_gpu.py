@@ -190,6 +190,23 @@ def test_partitioned_layout_vs_oracle(ctx):
     assert err <= C_TOL
 
 
+def test_partitioned_lanes_equal_single_extractions(ctx):
+    """The per-main-net extractions run concurrently on up to four lanes
+    (own workspace and stream each); every column equals, bit for bit, the
+    synchronous entry's extraction of that net's mesh."""
+    lay = gi.layered_stack_layout(3)
+    rule = (0.25, 2.0, 1.0, 0.5)
+    C, panels, rep = ctx.extract_dielectric_partitioned(lay, *rule)
+    for k in range(lay.n_conductors):
+        lo, hi, kind, cond, rp, rm = binding.mesh_dielectric_partition(lay, k, *rule)
+        assert lo.shape[0] == panels[k]
+        Ck, _ = ctx.extract_dielectric(lo, hi, kind, cond, rp, rm, lay.eps_r, lay.n_conductors, lay.length_unit_m)
+        assert np.array_equal(C[:, k], Ck[:, k]), k
+    C2, _, _ = ctx.extract_dielectric_partitioned(lay, *rule)
+    assert np.array_equal(C, C2)
+    say(f"partitioned lanes: {lay.n_conductors} columns equal the single extractions")
+
+
 def test_partitioned_layout_accuracy(ctx):
     """The per-main-net meshes of the six-net stack against its uniform
     8,644-panel mesh: the same capacitances to discretisation accuracy with a
