@@ -94,3 +94,23 @@ def test_mesher_refuses_bad_layouts():
         binding.mesh_dielectric_partition(lay, 5, 0.1, 2.0, 1.0, 0.5)
     with pytest.raises(binding.GbemError, match="p1 > 0"):
         binding.mesh_dielectric_partition(lay, 0, 0.0, 2.0, 1.0, 0.5)
+
+
+def test_partitioned_extraction_checks_before_context():
+    """gbem_extract_dielectric_partitioned meshes every main net first: a
+    layout the mesher refuses fails with the mesher's message, a valid one
+    reaches the context check (no device needed for either)."""
+    import ctypes
+    lib = binding.load()
+    lay = gi.layered_stack_layout(1)
+    C = np.zeros((2, 2))
+    rule = binding.Partition(0.25, 2.0, 1.0, 0.5)
+    d, keep = binding.dlayout(lay)
+    st = lib.gbem_extract_dielectric_partitioned(None, ctypes.byref(d), ctypes.byref(rule), None, C.ctypes.data,
+                                                 None, None)
+    assert st == binding.EINVAL and b"no context" in lib.gbem_last_error()
+    bad = gi.DielectricLayout(**{**lay.__dict__, "z_layer": [0.0, 1.0, 0.5, 3.6]})
+    d, keep = binding.dlayout(bad)
+    st = lib.gbem_extract_dielectric_partitioned(None, ctypes.byref(d), ctypes.byref(rule), None, C.ctypes.data,
+                                                 None, None)
+    assert st == binding.EINVAL and b"z_layer must increase" in lib.gbem_last_error()
