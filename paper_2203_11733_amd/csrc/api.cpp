@@ -224,9 +224,15 @@ struct Workspace {
     // factor dtype and right-hand sides; a new capture is applied to the
     // matching one with hipGraphExecUpdate (instantiated when the topology
     // differs or none matches)
+    // The key also holds the addresses of the buffers the captured copies
+    // read or write (flags, B, X, norms, solve flags): an update then only
+    // changes kernel arguments, and a reallocated buffer means a new
+    // executable.
+    static constexpr int kCopyBufs = 5;
     struct GraphExec {
         int64_t npad;
         int dtype, m;
+        const void *bufs[kCopyBufs];
         hipGraphExec_t exec;
     };
     std::vector<GraphExec> gexec;
@@ -234,9 +240,11 @@ struct Workspace {
     hipError_t launch_graph(hipGraph_t g, int64_t npad, int dtype, int m, hipStream_t st, bool &instantiated)
     {
         instantiated = false;
+        const void *bufs[kCopyBufs] = {flags.p, B.p, X.p, norms.p, sflags.p};
         GraphExec *slot = nullptr;
         for (auto &x : gexec)
-            if (x.npad == npad && x.dtype == dtype && x.m == m) slot = &x;
+            if (x.npad == npad && x.dtype == dtype && x.m == m && std::equal(bufs, bufs + kCopyBufs, x.bufs))
+                slot = &x;
         hipError_t e = hipSuccess;
         if (slot) {
             hipGraphNode_t bad_node = nullptr;
@@ -257,7 +265,8 @@ struct Workspace {
                 (void)hipGraphExecDestroy(gexec.front().exec);
                 gexec.erase(gexec.begin());
             }
-            GraphExec x{npad, dtype, m, nullptr};
+            GraphExec x{npad, dtype, m, {}, nullptr};
+            std::copy(bufs, bufs + kCopyBufs, x.bufs);
             if ((e = hipGraphInstantiate(&x.exec, g, nullptr, nullptr, 0)) != hipSuccess) return e;
             gexec.push_back(x);
             slot = &gexec.back();

@@ -90,3 +90,24 @@ def test_served_graph_jobs_equal_direct(meshes, mode):
     assert used == len(results)
     for i, (C, rep) in enumerate(results):
         assert np.array_equal(C, ref[i % len(meshes)])
+
+
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_graph_after_workspace_growth(meshes, mode):
+    """A larger job between two graph runs of the same shape grows the
+    workspace (new buffer addresses): the second run gets a new executable
+    rather than an update of the old one, and the results stay exact."""
+    o_direct = binding.make_opts(3, 2.0, **MODES[mode])
+    o_graph = binding.make_opts(3, 2.0, graph=True, **MODES[mode])
+    small, big = meshes[0], meshes[2]
+    with binding.Context(0) as ctx:
+        ref = ctx.extract(*small[1:], small[0].n_conductors, small[0].eps_r, small[0].length_unit_m, o_direct)[0]
+    with binding.Context(0) as ctx:
+        runs = []
+        for lay, lo, hi, cond in (small, big, small, small):
+            runs.append(ctx.extract(lo, hi, cond, lay.n_conductors, lay.eps_r, lay.length_unit_m, o_graph))
+    say(f"{mode}: instantiated {[r[1]['graph_instantiated'] for r in runs]}")
+    assert all(r[1]["graph_used"] == 1 for r in runs)
+    assert [r[1]["graph_instantiated"] for r in runs] == [1, 1, 1, 0]
+    for k in (0, 2, 3):
+        assert np.array_equal(runs[k][0], ref)
