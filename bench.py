@@ -453,7 +453,8 @@ def dielectric(args, binding, np):
     # size the paper's own experiment with several dielectrics used)
     lay = gi.layered_stack_layout(3)
     partitioned = {}
-    for name, rule in (("fine", (0.04, 4.0, 0.5, 0.5)), ("coarse", (0.25, 2.0, 1.0, 0.5))):
+    for name, rule in (() if args.dl_uniform_only else
+                       (("fine", (0.04, 4.0, 0.5, 0.5)), ("coarse", (0.25, 2.0, 1.0, 0.5)))):
         ctx.extract_dielectric_partitioned(lay, *rule, opts=o)
         pt = []
         for _ in range(args.steps):
@@ -509,6 +510,8 @@ def main():
                     help="multi-dielectric extraction of the six-net three-layer stack instead")
     ap.add_argument("--no-dielectric", action="store_true",
                     help="do not time the multi-dielectric stack after the headline steps")
+    ap.add_argument("--dl-uniform-only", action="store_true",
+                    help="--dielectric: only the uniform mesh (no per-main-net meshes), e.g. for a kernel profile")
     ap.add_argument("--dl-h", type=float, default=0.1,
                     help="conductor panel size of the --dielectric stack (interfaces and walls 2x)")
     ap.add_argument("--copy-calibration", action="store_true",
