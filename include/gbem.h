@@ -360,7 +360,8 @@ typedef struct {
  * out): C_out[n * n_conductors + k] = charge on net n (eps0 * sum over its
  * panels of eps_r q |I|) per volt on net k.  The single-layer entries use
  * opts->far_order and opts->near_eta in FP64 (far_dtype and factor_dtype are
- * not read); the system is not symmetric, so it is solved through its normal
+ * not read); the double-layer entries split near and far at eta = 2 whatever
+ * near_eta is (as gbem_assemble_double_layer with near_eta = 2); the system is not symmetric, so it is solved through its normal
  * equations M^T M x = M^T b by the FP64 Cholesky factorisation and refined
  * against the residual of M itself until max_k |b_k - M x_k| / |b_k| <=
  * 1e-13 (at most six sweeps; rep->residual reports it).  GBEM_EINVAL on an

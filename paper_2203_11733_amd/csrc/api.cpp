@@ -278,10 +278,11 @@ struct Workspace {
     // buffers of the multi-dielectric entries (kept between calls like the
     // rest of the context's workspace)
     struct DlBufs {
-        DevBuf tab, epsb, Q, M, Mt, B, Bn, Z, N, X, R, D, C, nrm, part;
+        DevBuf tab, epsb, Q, M, Mt, B, Bn, Z, N, X, R, D, C, nrm, part, qrow, qcol;
         void release()
         {
-            for (DevBuf *b : {&tab, &epsb, &Q, &M, &Mt, &B, &Bn, &Z, &N, &X, &R, &D, &C, &nrm, &part}) b->release();
+            for (DevBuf *b : {&tab, &epsb, &Q, &M, &Mt, &B, &Bn, &Z, &N, &X, &R, &D, &C, &nrm, &part, &qrow, &qcol})
+                b->release();
         }
     } dl;
 
@@ -1717,8 +1718,19 @@ extern "C" gbem_status gbem_extract_partitioned(gbem_ctx *ctx, const double *box
 // column-major, ldq = n) of the mesh in ws.lo / ws.hi with conductor ids in
 // ws.cond; optionally the single-layer matrix A (FP64 far rule of order p)
 // in ws.A (npad x npad).  Returns the near-pair count in *nnz.
-static gbem_status dl_assemble(Workspace &ws, int n, int n_cond, double near_eta, int p, bool with_A, DevBuf &Q,
-                               int64_t *nnz, hipStream_t st)
+// Near/far split of the double-layer integrals inside gbem_extract_dielectric:
+// fixed, whatever the single layer's near_eta, since both of its rules were
+// verified there (closed form below it; the far rule's error is about 1e-15
+// |I_i| at it, while the closed form loses digits with distance).
+constexpr double kDlNearEta = 2.0;
+
+// Panel table and the double-layer matrix Q (n x n, column-major, ldq = n) of
+// the mesh in ws.lo / ws.hi with conductor ids in ws.cond, near pairs of q_eta
+// in closed form; with_A: also the single-layer matrix A (FP64, far rule of
+// order p, near pairs of near_eta exact) in ws.A (npad x npad).  *nnz: the
+// near pairs of the single layer (with_A) or of Q.
+static gbem_status dl_assemble(Workspace &ws, int n, int n_cond, double near_eta, double q_eta, int p, bool with_A,
+                               DevBuf &Q, int64_t *nnz, hipStream_t st)
 {
     const int64_t npad = round_up(n, kPad);
     HIPCHK(ws.pan.ensure(sizeof(Panel) * n), "alloc panels");
@@ -1729,27 +1741,34 @@ static gbem_status dl_assemble(Workspace &ws, int n, int n_cond, double near_eta
     HIPCHK(hipMemsetAsync(ws.flags.p, 0, 64, st), "memset");
     HIPCHK(launch_build_panels(ws.lo.as<double>(), ws.hi.as<double>(), ws.cond.as<int32_t>(), n, n_cond,
                                ws.pan.as<Panel>(), ws.flags.as<int32_t>(), st), "build_panels");
-    HIPCHK(launch_near_count(ws.lo.as<double>(), ws.hi.as<double>(), n, near_eta * near_eta, ws.cnt.as<int64_t>(),
-                             ws.nmask.as<uint64_t>(), st), "near_count");
-    HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), st), "scan");
-    int64_t cnt = 0;
-    int32_t bad = 0;
-    HIPCHK(hipMemcpyAsync(&cnt, ws.rowptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st), "D2H");
-    HIPCHK(hipMemcpyAsync(&bad, ws.flags.p, 4, hipMemcpyDeviceToHost, st), "D2H");
-    HIPCHK(hipStreamSynchronize(st), "sync");
-    if (bad) {
-        set_error("panel " + std::to_string(bad - 1) + " is not an axis-aligned rectangle with exactly one zero extent");
-        return GBEM_EINVAL;
-    }
-    *nnz = cnt;
-    HIPCHK(ws.nrow.ensure(sizeof(int32_t) * std::max<int64_t>(cnt, 1)), "alloc");
-    HIPCHK(ws.ncol.ensure(sizeof(int32_t) * std::max<int64_t>(cnt, 1)), "alloc");
-    HIPCHK(launch_near_fill(ws.nmask.as<uint64_t>(), n, ws.rowptr.as<int64_t>(), ws.nrow.as<int32_t>(),
-                            ws.ncol.as<int32_t>(), st), "near_fill");
-    HIPCHK(Q.ensure((size_t)n * n * 8), "alloc Q");
-    HIPCHK(launch_double_layer(ws.pan.as<Panel>(), n, ws.nrow.as<int32_t>(), ws.ncol.as<int32_t>(), cnt,
-                               Q.as<double>(), n, st), "double layer");
+    // the near list of eta into (row, col); the panel check with the first one
+    bool checked = false;
+    auto near_list = [&](double eta, DevBuf &row, DevBuf &col, int64_t *count) -> gbem_status {
+        HIPCHK(launch_near_count(ws.lo.as<double>(), ws.hi.as<double>(), n, eta * eta, ws.cnt.as<int64_t>(),
+                                 ws.nmask.as<uint64_t>(), st), "near_count");
+        HIPCHK(launch_exclusive_scan(ws.cnt.as<int64_t>(), n, ws.rowptr.as<int64_t>(), st), "scan");
+        int64_t cnt = 0;
+        int32_t bad = 0;
+        HIPCHK(hipMemcpyAsync(&cnt, ws.rowptr.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st), "D2H");
+        if (!checked) HIPCHK(hipMemcpyAsync(&bad, ws.flags.p, 4, hipMemcpyDeviceToHost, st), "D2H");
+        HIPCHK(hipStreamSynchronize(st), "sync");
+        checked = true;
+        if (bad) {
+            set_error("panel " + std::to_string(bad - 1) +
+                      " is not an axis-aligned rectangle with exactly one zero extent");
+            return GBEM_EINVAL;
+        }
+        HIPCHK(row.ensure(sizeof(int32_t) * std::max<int64_t>(cnt, 1)), "alloc");
+        HIPCHK(col.ensure(sizeof(int32_t) * std::max<int64_t>(cnt, 1)), "alloc");
+        HIPCHK(launch_near_fill(ws.nmask.as<uint64_t>(), n, ws.rowptr.as<int64_t>(), row.as<int32_t>(),
+                                col.as<int32_t>(), st), "near_fill");
+        *count = cnt;
+        return GBEM_OK;
+    };
+    gbem_status s = GBEM_OK;
+    int64_t cnt = 0, qcnt = 0;
     if (with_A) {
+        if ((s = near_list(near_eta, ws.nrow, ws.ncol, &cnt)) != GBEM_OK) return s;
         HIPCHK(ws.A.ensure((size_t)npad * npad * 8), "alloc A");
         HIPCHK(ws.semi.ensure(near_semi_bytes(cnt)), "alloc near queue");
         GaussRule rule;
@@ -1759,6 +1778,14 @@ static gbem_status dl_assemble(Workspace &ws, int n, int n_cond, double near_eta
                                 ws.ncol.as<int32_t>(), cnt, ws.A.as<double>(), npad, ws.semi.as<int32_t>(), st),
                "near_eval");
     }
+    const bool same = with_A && q_eta == near_eta;
+    if (!same && (s = near_list(q_eta, ws.dl.qrow, ws.dl.qcol, &qcnt)) != GBEM_OK) return s;
+    const int32_t *qr = same ? ws.nrow.as<int32_t>() : ws.dl.qrow.as<int32_t>();
+    const int32_t *qc = same ? ws.ncol.as<int32_t>() : ws.dl.qcol.as<int32_t>();
+    HIPCHK(Q.ensure((size_t)n * n * 8), "alloc Q");
+    HIPCHK(launch_double_layer(ws.pan.as<Panel>(), n, qr, qc, same ? cnt : qcnt, Q.as<double>(), n, st),
+           "double layer");
+    *nnz = with_A ? cnt : qcnt;
     return GBEM_OK;
 }
 
@@ -1782,7 +1809,7 @@ extern "C" gbem_status gbem_assemble_double_layer(gbem_ctx *ctx, int32_t n_panel
     HIPCHK(hipMemsetAsync(ws.cond.p, 0xff, sizeof(int32_t) * n, st), "memset");   // -1: no conductor
     DevBuf &Q = ws.dl.Q;
     int64_t nnz = 0;
-    gbem_status s = dl_assemble(ws, n, 0, near_eta, 3, false, Q, &nnz, st);
+    gbem_status s = dl_assemble(ws, n, 0, near_eta, near_eta, 3, false, Q, &nnz, st);
     if (s != GBEM_OK) return s;
     std::vector<double> tmp((size_t)n * n);
     HIPCHK(hipMemcpyAsync(tmp.data(), Q.p, sizeof(double) * n * n, hipMemcpyDeviceToHost, st), "D2H");
@@ -1957,7 +1984,7 @@ static gbem_status dielectric_run(gbem_ctx *ctx, const Lane *lane, const gbem_dm
                   *d_us = d_kind + 4 * n, *d_qs = d_kind + 5 * n, *d_er = d_kind + 6 * (size_t)n,
                   *d_ep = d_er + nrow, *d_cpp = d_ep + nrow, *d_cpi = d_cpp + M + 1;
     int64_t nnz = 0;
-    gbem_status s = dl_assemble(ws, n, M, o.near_eta, o.far_order, true, Q, &nnz, st);
+    gbem_status s = dl_assemble(ws, n, M, o.near_eta, kDlNearEta, o.far_order, true, Q, &nnz, st);
     if (s != GBEM_OK) return s;
     const int64_t npadA = round_up(n, kPad), npad = round_up(std::max(nu, nrow), kPad);
     const auto t_asm = std::chrono::steady_clock::now();

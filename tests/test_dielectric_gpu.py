@@ -224,6 +224,21 @@ def test_partitioned_layout_accuracy(ctx):
     assert dev <= 0.02 and cdev <= 0.02
 
 
+def test_exact_single_layer_mode(ctx):
+    """near_eta = 1e6 puts every single-layer pair on the exact path (the
+    exact reference mode); the double layer keeps its own split at eta = 2
+    (its closed form loses digits with distance).  Against the oracle with
+    the exact G_ij for every pair."""
+    m = gi.layered_stack(1, 0.5)
+    o = binding.make_opts(3, 1e6)
+    C, rep = ctx.extract_dielectric(*m.args(), opts=o)
+    ref = od.extract(*m.args())
+    err = float(np.abs(C - ref).max() / np.abs(ref).max())
+    say(f"exact single layer: near pairs {rep['n_near']} of {m.n_panels * (m.n_panels + 1) // 2}, C vs oracle {err:.2e}")
+    assert rep["n_near"] == m.n_panels * (m.n_panels + 1) // 2
+    assert err <= C_TOL
+
+
 def test_layered_stack_properties_at_size(ctx):
     """Six wires, 4,368 panels: the mirror y -> W - y maps wire 0 to wire 2
     and each upper wire to itself, so C is invariant under that exchange;
