@@ -794,11 +794,11 @@ template <> struct Mfma32<_Float16> {
 };
 
 // LDS rows of a K chunk are 128 bytes (eight 16-byte pieces) without
-// padding; piece p of row r is stored in place p ^ (r & 7).  A 16-byte LDS
-// access is served 16 lanes at a time: the fragment reads (16 consecutive
-// rows, one piece) and the loader's stores (8 rows, two pieces each) then
-// spread over all banks, which a 144-byte padded row stride does not do for
-// the reads on gfx950 (measured 125 against 182 B/clk per CU).
+// padding; piece p of row r is stored in place p ^ (r & 7).  The fragment
+// reads (16 consecutive rows, one piece per lane group) then run without
+// bank conflicts, which a 144-byte padded row stride does not achieve on
+// gfx950 (measured 125 against 182 B/clk per CU); the loader's stores run at
+// the same rate in both layouts.
 constexpr int kBK16 = 64;
 static size_t syrk16_smem_bytes() { return (size_t)2 * 2 * kBM * kBK16 * 2; }
 
