@@ -17,6 +17,7 @@
 #include <thread>
 #include <vector>
 
+#include "admission.h"
 #include "gbem_internal.h"
 
 namespace gbem {
@@ -970,19 +971,76 @@ static void worker_main(gbem_ctx *ctx, Worker *w)
     }
 }
 
-// Admission: the device memory held by all worker workspaces never exceeds
-// the budget (the near list aside, which is estimated before its size is
-// known).  A queued job goes to an idle worker when that worker's workspace,
-// each buffer grown to the job's need, fits beside what the other workers
-// hold (busy ones: their reservation; idle ones: their workspace); idle
-// workspaces are released to make room.  Jobs that fit may pass a larger job
-// at the head of the queue for up to one second.
+// Admission (admission.h): the device memory held by all worker workspaces
+// never exceeds the budget (the near list aside, which is estimated before
+// its size is known).  This adapter gives the policy the live queue and
+// workers; it runs with ctx->mu held, which release_idle gives up while it
+// frees memory (hipFree may wait for the device, and workers finishing a job
+// need the lock); only this thread dispatches, so an idle worker stays idle
+// meanwhile.
+struct LivePool {
+    gbem_ctx *ctx;
+    std::unique_lock<std::mutex> &lk;
+    size_t queue_size() const { return ctx->queue.size(); }
+    int first_idle() const
+    {
+        for (size_t i = 0; i < ctx->workers.size(); ++i)
+            if (!ctx->workers[i]->busy) return (int)i;
+        return -1;
+    }
+    // idle workspaces are only touched by this thread; busy ones are bounded
+    // by what was recorded when they were dispatched
+    size_t others(int w) const
+    {
+        size_t t = 0;
+        for (size_t i = 0; i < ctx->workers.size(); ++i) {
+            const Worker *c = ctx->workers[i];
+            if ((int)i != w) t += c->busy ? std::max(c->held, c->bytes) : c->bytes;
+        }
+        return t;
+    }
+    // each buffer grows to the job's need or keeps its larger capacity
+    size_t grown(int w, size_t qi) const { return grown_bytes(ctx->workers[w]->ws, ctx->queue[qi]->needs); }
+    bool release_idle(size_t qi)
+    {
+        gbem_job *j = ctx->queue[qi];
+        std::vector<Worker *> idle;
+        for (Worker *c : ctx->workers)
+            if (!c->busy && c->bytes > 0) idle.push_back(c);
+        lk.unlock();
+        for (Worker *c : idle) c->ws.release_all();
+        lk.lock();
+        for (Worker *c : idle) c->bytes = 0;
+        // a worker that finished meanwhile is idle now and holds its last
+        // job's workspace: others() counts it on the next call
+        return ctx->queue.size() > qi && ctx->queue[qi] == j;
+    }
+    void dispatch(size_t qi, int wi, size_t mine, size_t total)
+    {
+        gbem_job *j = ctx->queue[qi];
+        Worker *w = ctx->workers[wi];
+        ctx->queue.erase(ctx->queue.begin() + qi);
+        {
+            std::lock_guard<std::mutex> jl(j->mu);
+            j->state = 1;
+        }
+        w->busy = true;
+        w->job = j;
+        w->held = mine;
+        ctx->reserved += j->need;
+        ctx->peak = std::max(ctx->peak, total);
+    }
+};
+
+// A job at the head of the queue that does not fit may be passed by jobs
+// that do for up to one second.
 static void sched_main(gbem_ctx *ctx)
 {
     (void)hipSetDevice(ctx->device);
     auto head_since = std::chrono::steady_clock::now();
     gbem_job *head_seen = nullptr;
     std::unique_lock<std::mutex> lk(ctx->mu);
+    LivePool pool{ctx, lk};
     for (;;) {
         if (ctx->stopping && ctx->queue.empty()) break;
         bool dispatched = false;
@@ -992,61 +1050,7 @@ static void sched_main(gbem_ctx *ctx)
                 head_since = std::chrono::steady_clock::now();
             }
             const bool head_starving = std::chrono::steady_clock::now() - head_since > std::chrono::seconds(1);
-            for (size_t qi = 0; qi < ctx->queue.size() && !dispatched; ++qi) {
-                if (qi > 0 && head_starving) break;
-                gbem_job *j = ctx->queue[qi];
-                Worker *w = nullptr;
-                for (Worker *c : ctx->workers)
-                    if (!c->busy) {
-                        w = c;
-                        break;
-                    }
-                if (!w) break;
-                // idle workspaces are only touched by this thread; busy ones
-                // are bounded by what was recorded when they were dispatched
-                auto held_by_others = [&]() {
-                    size_t t = 0;
-                    for (Worker *c : ctx->workers)
-                        if (c != w) t += c->busy ? std::max(c->held, c->bytes) : c->bytes;
-                    return t;
-                };
-                // what w's workspace will hold after the job: each buffer
-                // grows to the job's need or keeps its larger capacity
-                size_t held_others = held_by_others();
-                size_t mine = grown_bytes(w->ws, j->needs);
-                if (held_others + mine > ctx->budget) {
-                    // free the idle workspaces without holding the lock (hipFree
-                    // may wait for the device, and workers finishing a job need
-                    // the lock); only this thread dispatches, so an idle worker
-                    // stays idle meanwhile
-                    std::vector<Worker *> idle;
-                    for (Worker *c : ctx->workers)
-                        if (!c->busy && c->bytes > 0) idle.push_back(c);
-                    lk.unlock();
-                    for (Worker *c : idle) c->ws.release_all();
-                    lk.lock();
-                    for (Worker *c : idle) c->bytes = 0;
-                    // a worker that finished while the lock was released is
-                    // idle now and holds its last job's workspace: count the
-                    // idle workers again (the ones just released hold nothing)
-                    held_others = held_by_others();
-                    mine = grown_bytes(w->ws, j->needs);
-                    if (ctx->queue.size() <= qi || ctx->queue[qi] != j) break;   // the queue moved: rescan
-                }
-                if (held_others + mine <= ctx->budget) {
-                    ctx->queue.erase(ctx->queue.begin() + qi);
-                    {
-                        std::lock_guard<std::mutex> jl(j->mu);
-                        j->state = 1;
-                    }
-                    w->busy = true;
-                    w->job = j;
-                    w->held = mine;
-                    ctx->reserved += j->need;
-                    ctx->peak = std::max(ctx->peak, held_others + mine);
-                    dispatched = true;
-                }
-            }
+            dispatched = admit_one(pool, ctx->budget, head_starving);
         }
         if (dispatched) {
             ctx->cv_work.notify_all();
